@@ -1,0 +1,258 @@
+/*
+ * cg.h -- C ABI of the MI355X (gfx950) contig-generation library (libcg).
+ *
+ * The library implements the contig-generation step of long-read assembly
+ * described by Guidi et al., "Distributed-Memory Parallel Contig Generation
+ * for De Novo Long-Read Genome Assembly" (ICPP'22), Algorithm 2
+ * (ContigGeneration): BranchRemoval -> ConnectedComponent ->
+ * GreedyPartitioning -> InducedSubgraph -> LocalAssembly.  Each of those five
+ * steps is one call below; every step runs in hand-written HIP kernels on one
+ * GPU.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * * Pointers inside the structs and the array arguments are DEVICE pointers
+ *   unless marked [host].  The caller allocates and owns every buffer; the
+ *   library never frees or resizes caller memory.
+ * * `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on `stream` and returns; outputs are valid once the stream
+ *   has completed.  No call synchronises the host, so the sequence can be
+ *   captured into a HIP graph.
+ * * Return value: CG_OK (0) or a negative error code.  Argument errors are
+ *   detected on the host before anything is enqueued.  Conditions that only
+ *   the device can see (an output capacity too small) are reported through
+ *   device-side counts that the caller reads after the stream completes, and
+ *   through cg_ctx_status().
+ * * Only cg_validate() inspects the graph's contents.  The other calls
+ *   require a graph that passes it: they follow the graph's indices, so on an
+ *   invalid graph both their outputs and their memory accesses are undefined.
+ *   Run cg_validate on any graph that does not come from a trusted producer.
+ * * A cg_ctx owns a device scratch area and must be used by one host thread
+ *   and one stream at a time; independent contexts may share a device.
+ * * No C++ exception crosses this interface.
+ */
+#ifndef CG_H
+#define CG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CG_OK            0
+#define CG_EINVAL       -1  /* bad argument, shape or pointer                    */
+#define CG_ENOMEM       -2  /* context scratch smaller than cg_footprint() asks   */
+#define CG_EHIP         -3  /* HIP runtime error; text in cg_last_error()         */
+#define CG_ECAPACITY    -4  /* a device-side count exceeded a caller capacity     */
+#define CG_EUNSUPPORTED -5  /* valid request outside the library's limits         */
+
+/* ---- component kinds and contig flags ---------------------------------- */
+#define CG_KIND_SINGLE 0    /* one read, no kept edge                              */
+#define CG_KIND_PATH   1    /* q reads, q-1 edges: two roots of degree 1           */
+#define CG_KIND_CYCLE  2    /* q reads, q edges: every read has degree 2           */
+
+#define CG_CONTIG_CIRCULAR      1u  /* cycle cut before its smallest read           */
+#define CG_CONTIG_SAME_END_JOIN 2u  /* a read is entered and left on the same end   */
+#define CG_CONTIG_SINGLE        4u  /* one-read contig (only when min_reads <= 1)   */
+
+/* device status bits reported by cg_ctx_status() */
+#define CG_STATUS_BASES_OVERFLOW 1u /* cg_assemble: contigs need more than cap_words */
+
+/*
+ * The string graph S (Section 2: a bidirected graph, stored as a symmetric
+ * sparse matrix; Section 4.2 calls it the string matrix).
+ *   n, m      vertices (= reads, ids 0..n-1) and directed entries; 0 <= n < 2^30,
+ *             0 <= m < 2^31.
+ *   row_ptr   int32[n+1], col int32[m]: CSR of S, columns strictly increasing
+ *             inside a row, no self loops; entry (u,v) present iff (v,u) is.
+ *   ovl       uint32[m]: overlap length of reads u and v, equal in both
+ *             directions, 1 <= ovl < min(read_len[u], read_len[v]).
+ *   strand    uint8[m]: bit0 s = read u is reverse-complemented when the walk
+ *             leaves u along this entry; bit1 d = read v is reverse-complemented
+ *             when the walk enters v along it.  The twin entry (v,u) carries
+ *             (s', d') = (!d, !s).  Other bits are zero.
+ *   read_len  uint32[n], >= 1.
+ *   read_off  uint64[n]: base offset of read v in seq, a multiple of 16.
+ *   seq       uint32[seq_words]: 2-bit packed bases, 16 per word, base i of the
+ *             store at bits 2*(i%16) of word i/16; A=0 C=1 G=2 T=3, so the
+ *             complement of a base is x^3.
+ */
+typedef struct {
+  int32_t n;
+  int32_t m;
+  const int32_t  *row_ptr;
+  const int32_t  *col;
+  const uint32_t *ovl;
+  const uint8_t  *strand;
+  const uint32_t *read_len;
+  const uint64_t *read_off;
+  const uint32_t *seq;
+  uint64_t seq_words;
+} cg_graph;
+
+/*
+ * Components and their partition (Sections 4.2 and 4.3).  Component arrays
+ * hold the ELIGIBLE components (not a branch vertex, at least min_reads
+ * reads) in ascending label order; capacity n each, the first *d_n_comp are
+ * valid.
+ *   comp_label  smallest vertex id of the component
+ *   comp_size   q = number of reads
+ *   comp_kind   CG_KIND_*
+ *   comp_bin    bin (process) chosen by LPT, 0..P-1
+ *   comp_rank   position of the component in (bin, label) order
+ *   comp_start  number of reads of the components before it in that order
+ *   bin_load    uint64[P]: reads per bin
+ *   label_comp  int32[n]: for vertex id r, the index of the eligible
+ *               component labelled r, else -1
+ *   d_n_comp    int32[1]
+ */
+typedef struct {
+  int32_t  *comp_label;
+  int32_t  *comp_size;
+  uint8_t  *comp_kind;
+  int32_t  *comp_bin;
+  int32_t  *comp_rank;
+  int32_t  *comp_start;
+  uint64_t *bin_load;
+  int32_t  *label_comp;
+  int32_t  *d_n_comp;
+} cg_parts;
+
+/*
+ * Induced subgraphs of all bins in one local numbering (Section 4.3,
+ * InducedSubgraph): local vertex i is read perm[i]; vertices are numbered by
+ * (bin, label, id), so bin b owns local vertices bin_vptr[b] ..
+ * bin_vptr[b+1]-1 and each component a contiguous block.  Row i of the local
+ * CSR lists the kept entries of read perm[i] in the row order of S, with the
+ * column renumbered locally (loc_col) and the entry's index in S (loc_eid).
+ *   perm int32[n], bin_vptr int32[P+1], loc_row_ptr int32[n+1],
+ *   loc_col int32[2n], loc_eid int32[2n], d_sizes int32[2] = (n_e, m_e).
+ */
+typedef struct {
+  int32_t *perm;
+  int32_t *bin_vptr;
+  int32_t *loc_row_ptr;
+  int32_t *loc_col;
+  int32_t *loc_eid;
+  int32_t *d_sizes;
+} cg_local;
+
+/*
+ * Contigs (Section 4.4, LocalAssembly): one record per eligible component,
+ * records in (bin, label) order (record k belongs to the component with
+ * comp_rank == k).  Record arrays have capacity n.
+ *   label, bin      of the component
+ *   start           read the walk starts from
+ *   n_reads         q
+ *   len             bases in the contig
+ *   base_off        base offset of the contig in `bases` (multiple of 16)
+ *   cflags          CG_CONTIG_*
+ *   layout_off      first layout entry of the contig (= its comp_start)
+ *   layout_vid      int32[n]: reads in walk order
+ *   layout_rev      uint8[n]: 1 if that read is reverse-complemented
+ *   bases           uint32[cap_words]: contigs 2-bit packed like seq, each
+ *                   starting on a word boundary, padding bits zero
+ *   d_total_words   uint64[1]: words the contigs need; when it exceeds
+ *                   cap_words nothing is written to `bases` and
+ *                   CG_STATUS_BASES_OVERFLOW is raised.  cap_words =
+ *                   seq_words always suffices.
+ */
+typedef struct {
+  int32_t  *label;
+  int32_t  *bin;
+  int32_t  *start;
+  int32_t  *n_reads;
+  uint64_t *len;
+  uint64_t *base_off;
+  uint32_t *cflags;
+  int32_t  *layout_off;
+  int32_t  *layout_vid;
+  uint8_t  *layout_rev;
+  uint32_t *bases;
+  uint64_t  cap_words;
+  uint64_t *d_total_words;
+} cg_contigs;
+
+typedef struct cg_ctx cg_ctx;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on `device` with a device scratch area of scratch_bytes
+ * (see cg_footprint).  *out receives the context.  Errors: CG_EINVAL (bad
+ * device or NULL out), CG_EHIP. */
+int cg_ctx_create(int device, size_t scratch_bytes, cg_ctx **out);
+
+/* Release the context and its scratch.  The caller must make sure no work
+ * that uses it is still in flight. */
+int cg_ctx_destroy(cg_ctx *ctx);
+
+/* Scratch bytes a context needs for graphs of up to n vertices, m entries
+ * and P bins.  bytes is [host]. */
+int cg_footprint(int32_t n, int32_t m, int32_t P, uint64_t *bytes);
+
+/* Device status bits (CG_STATUS_*) raised since the last clear.  Waits for
+ * `stream`, then copies the word to *status [host]; clears it if `clear`. */
+int cg_ctx_status(cg_ctx *ctx, void *stream, uint32_t *status, int clear);
+
+/* Thread-local text of the last error. */
+const char *cg_last_error(void);
+
+/* ---- the five steps of Algorithm 2 ------------------------------------- */
+
+/* Input checks: row_ptr frame and monotonicity, read length >= 1, read
+ * offsets 16-aligned and inside seq, column range, no self loop, strictly
+ * increasing columns, twin entry present with equal ovl and strand bits
+ * (!d, !s), 1 <= ovl < min read length.  d_bad int64[2] receives (index, why)
+ * of the first failure in the order just listed ((-1, 0) when valid; index
+ * -2 for a bad frame).  why: 1 frame/monotone, 2 column range, 3 self loop,
+ * 4 order/duplicate, 5 missing twin, 6 twin ovl, 7 twin strand bits,
+ * 8 ovl bounds, 9 read_len, 10 read_off alignment, 11 read past seq. */
+int cg_validate(cg_ctx *ctx, const cg_graph *g, int64_t *d_bad, void *stream);
+
+/* BranchRemoval(S) -> L (Section 4.2).  The degree of a vertex is the number
+ * of entries in its row; a branch vertex has degree >= 3.  L keeps the
+ * entries of S whose two ends are not branch vertices, in place (same
+ * indexing).  flags uint8[n]: bit0 = branch, bit1 / bit2 = entry 0 / 1 of the
+ * row is kept (only rows of degree <= 2 keep entries).  d_counts int32[2] =
+ * (branch vertices, kept directed entries). */
+int cg_mask_branches(cg_ctx *ctx, const cg_graph *g, uint8_t *flags, int32_t *d_counts,
+                     void *stream);
+
+/* ConnectedComponent(L) -> v (Section 4.2).  label int32[n]: the smallest
+ * vertex id of the vertex's component in L (branch and isolated vertices
+ * label themselves). */
+int cg_components(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, int32_t *label,
+                  void *stream);
+
+/* Contig sizes and GreedyPartitioning(v, P) -> p (Sections 4.2 and 4.3):
+ * component sizes and kinds, eligible components (min_reads <= 1 is taken
+ * as 1), then LPT: sizes in decreasing order (ties: ascending label), each
+ * to the least loaded of the P bins (ties: lowest bin index).  Fills `out`
+ * (cg_parts above).  1 <= P <= 65536. */
+int cg_partition(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
+                 int32_t P, int32_t min_reads, const cg_parts *out, void *stream);
+
+/* InducedSubgraph(L, p) (Section 4.3): the bins' induced subgraphs in one
+ * local numbering; fills `out` (cg_local above). */
+int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
+              const cg_parts *parts, int32_t P, const cg_local *out, void *stream);
+
+/* LocalAssembly(P, sequences) -> cset (Section 4.4): walks every chain and
+ * concatenates l_r[alpha:pre(e0)] + l_c1[post(e0):pre(e1)] + ... +
+ * l_r'[post(e_{q-2}):beta]: each read but the last contributes its part before
+ * the overlap with the next read (in its walking orientation), the last read
+ * contributes all of its bases.  A path starts at its smaller-id root; a cycle
+ * starts at its smallest read, steps to that read's smaller-id neighbour and
+ * does not traverse its closing edge.  The first read's orientation is the s
+ * bit of the first edge, every other read's the d bit of the edge it is
+ * entered by.  Fills `out` (cg_contigs above). */
+int cg_assemble(cg_ctx *ctx, const cg_graph *g, const cg_parts *parts, const cg_local *local,
+                int32_t P, const cg_contigs *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CG_H */

@@ -1,0 +1,240 @@
+// C ABI of libcg (include/cg.h): contexts, scratch sizing, host-side
+// argument checks and the five steps of Algorithm 2.  No exception leaves
+// this file; every entry point returns a status code.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "cg_internal.h"
+
+namespace cg {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return CG_OK;
+  return set_error(CG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout(int64_t n, int64_t m, int64_t P) {
+  (void)m;
+  Layout L{};
+  const int64_t nn = n > 0 ? n : 1;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    size_t here = at;
+    at += align_up(bytes);
+    return here;
+  };
+  L.scan_status = take(sizeof(unsigned long long) * (size_t)(scan_blocks(nn + 1) + 1));
+  L.tmp = take(4 * (size_t)nn);
+  L.lidx = take(4 * (size_t)nn);
+  L.fill = take(4 * (size_t)nn);
+  L.piece_off = take(8 * (size_t)nn);
+  L.piece_len = take(4 * (size_t)nn);
+  L.lay_contig = take(4 * (size_t)nn);
+  L.keys = take(8 * (size_t)(2 * nn + 2));
+  L.bins = take(8 * (size_t)(2 * (P > 0 ? P : 1)));
+  L.aux = take(4 * (size_t)nn);
+  L.walk = take(4 * 16 * (size_t)nn);
+  L.total = at;
+  return L;
+}
+
+bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
+  Layout L = layout(n, m, P);
+  if (L.total > ctx->scratch_bytes) return false;
+  char *b = ctx->scratch;
+  s->scan_status = (unsigned long long *)(b + L.scan_status);
+  s->tmp = (int32_t *)(b + L.tmp);
+  s->lidx = (int32_t *)(b + L.lidx);
+  s->fill = (uint32_t *)(b + L.fill);
+  s->piece_off = (uint64_t *)(b + L.piece_off);
+  s->piece_len = (uint32_t *)(b + L.piece_len);
+  s->lay_contig = (int32_t *)(b + L.lay_contig);
+  s->keys = (uint64_t *)(b + L.keys);
+  s->bins = (uint64_t *)(b + L.bins);
+  s->aux = (int32_t *)(b + L.aux);
+  s->walk = (int32_t *)(b + L.walk);
+  return true;
+}
+
+}  // namespace cg
+
+using namespace cg;
+
+static int check_graph(const cg_graph *g, bool need_seq) {
+  if (!g) return set_error(CG_EINVAL, "graph is NULL");
+  if (g->n < 0 || g->n >= (1 << 30)) return set_error(CG_EINVAL, "n=%d outside [0, 2^30)", g->n);
+  if (g->m < 0) return set_error(CG_EINVAL, "m=%d is negative", g->m);
+  if (!g->row_ptr) return set_error(CG_EINVAL, "row_ptr is NULL");
+  if (g->m > 0 && (!g->col || !g->ovl || !g->strand))
+    return set_error(CG_EINVAL, "col/ovl/strand is NULL");
+  if (need_seq && g->n > 0 && (!g->read_len || !g->read_off || !g->seq))
+    return set_error(CG_EINVAL, "read_len/read_off/seq is NULL");
+  return CG_OK;
+}
+
+static int check_ctx(cg_ctx *ctx, const cg_graph *g, int32_t P, Scratch *s) {
+  if (!ctx) return set_error(CG_EINVAL, "context is NULL");
+  if (!carve(ctx, g->n, g->m, P, s))
+    return set_error(CG_ENOMEM, "context scratch of %zu bytes is below the %zu bytes needed",
+                     ctx->scratch_bytes, layout(g->n, g->m, P).total);
+  return CG_OK;
+}
+
+static int check_P(int32_t P) {
+  if (P < 1 || P > 65536) return set_error(CG_EINVAL, "P=%d outside [1, 65536]", P);
+  return CG_OK;
+}
+
+extern "C" {
+
+const char *cg_last_error(void) { return g_err; }
+
+int cg_footprint(int32_t n, int32_t m, int32_t P, uint64_t *bytes) {
+  if (!bytes || n < 0 || m < 0 || P < 1) return set_error(CG_EINVAL, "bad footprint arguments");
+  *bytes = (uint64_t)layout(n, m, P).total;
+  return CG_OK;
+}
+
+int cg_ctx_create(int device, size_t scratch_bytes, cg_ctx **out) {
+  if (!out) return set_error(CG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  int rc = hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (rc) return rc;
+  if (device < 0 || device >= ndev) return set_error(CG_EINVAL, "device %d of %d", device, ndev);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if ((rc = hip_check(hipSetDevice(device), "hipSetDevice"))) return rc;
+  cg_ctx *c = new (std::nothrow) cg_ctx();
+  if (!c) return set_error(CG_EINVAL, "out of host memory");
+  c->device = device;
+  c->scratch_bytes = scratch_bytes;
+  c->scratch = nullptr;
+  c->fixed = nullptr;
+  rc = hip_check(hipMalloc((void **)&c->fixed, sizeof(Fixed)), "hipMalloc(fixed)");
+  if (!rc) rc = hip_check(hipMemset(c->fixed, 0, sizeof(Fixed)), "hipMemset(fixed)");
+  if (!rc && scratch_bytes)
+    rc = hip_check(hipMalloc((void **)&c->scratch, scratch_bytes), "hipMalloc(scratch)");
+  if (!rc && scratch_bytes)
+    rc = hip_check(hipMemset(c->scratch, 0, scratch_bytes), "hipMemset(scratch)");
+  if (!rc) rc = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  (void)hipSetDevice(prev);
+  if (rc) {
+    if (c->scratch) (void)hipFree(c->scratch);
+    if (c->fixed) (void)hipFree(c->fixed);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return CG_OK;
+}
+
+int cg_ctx_destroy(cg_ctx *ctx) {
+  if (!ctx) return CG_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  int rc = CG_OK;
+  if (ctx->scratch) rc = hip_check(hipFree(ctx->scratch), "hipFree(scratch)");
+  if (ctx->fixed && !rc) rc = hip_check(hipFree(ctx->fixed), "hipFree(fixed)");
+  (void)hipSetDevice(prev);
+  delete ctx;
+  return rc;
+}
+
+int cg_ctx_status(cg_ctx *ctx, void *stream, uint32_t *status, int clear) {
+  if (!ctx || !status) return set_error(CG_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (rc) return rc;
+  rc = hip_check(hipMemcpy(status, &ctx->fixed->status, sizeof(uint32_t), hipMemcpyDeviceToHost),
+                 "hipMemcpy(status)");
+  if (rc) return rc;
+  if (clear)
+    rc = hip_check(hipMemset(&ctx->fixed->status, 0, sizeof(uint32_t)), "hipMemset(status)");
+  return rc;
+}
+
+int cg_validate(cg_ctx *ctx, const cg_graph *g, int64_t *d_bad, void *stream) {
+  int rc = check_graph(g, true);
+  if (rc) return rc;
+  if (!ctx || !d_bad) return set_error(CG_EINVAL, "NULL argument");
+  return launch_validate(ctx, *g, d_bad, (hipStream_t)stream);
+}
+
+int cg_mask_branches(cg_ctx *ctx, const cg_graph *g, uint8_t *flags, int32_t *d_counts,
+                     void *stream) {
+  int rc = check_graph(g, false);
+  if (rc) return rc;
+  if (!ctx || !d_counts || (g->n > 0 && !flags)) return set_error(CG_EINVAL, "NULL argument");
+  return launch_mask(ctx, *g, flags, d_counts, (hipStream_t)stream);
+}
+
+int cg_components(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, int32_t *label,
+                  void *stream) {
+  int rc = check_graph(g, false);
+  if (rc) return rc;
+  if (!ctx || (g->n > 0 && (!flags || !label))) return set_error(CG_EINVAL, "NULL argument");
+  return launch_components(ctx, *g, flags, label, (hipStream_t)stream);
+}
+
+static int check_parts(const cg_parts *p) {
+  if (!p || !p->comp_label || !p->comp_size || !p->comp_kind || !p->comp_bin || !p->comp_rank ||
+      !p->comp_start || !p->bin_load || !p->label_comp || !p->d_n_comp)
+    return set_error(CG_EINVAL, "cg_parts has a NULL member");
+  return CG_OK;
+}
+
+int cg_partition(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
+                 int32_t P, int32_t min_reads, const cg_parts *out, void *stream) {
+  int rc = check_graph(g, false);
+  if (rc || (rc = check_P(P)) || (rc = check_parts(out))) return rc;
+  if (g->n > 0 && (!flags || !label)) return set_error(CG_EINVAL, "NULL argument");
+  Scratch s;
+  if ((rc = check_ctx(ctx, g, P, &s))) return rc;
+  return launch_partition(ctx, *g, s, flags, label, P, min_reads, *out, (hipStream_t)stream);
+}
+
+int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
+              const cg_parts *parts, int32_t P, const cg_local *out, void *stream) {
+  int rc = check_graph(g, false);
+  if (rc || (rc = check_P(P)) || (rc = check_parts(parts))) return rc;
+  if (!out || !out->perm || !out->bin_vptr || !out->loc_row_ptr || !out->loc_col ||
+      !out->loc_eid || !out->d_sizes)
+    return set_error(CG_EINVAL, "cg_local has a NULL member");
+  if (g->n > 0 && (!flags || !label)) return set_error(CG_EINVAL, "NULL argument");
+  Scratch s;
+  if ((rc = check_ctx(ctx, g, P, &s))) return rc;
+  return launch_induce(ctx, *g, s, flags, label, *parts, P, *out, (hipStream_t)stream);
+}
+
+int cg_assemble(cg_ctx *ctx, const cg_graph *g, const cg_parts *parts, const cg_local *local,
+                int32_t P, const cg_contigs *out, void *stream) {
+  int rc = check_graph(g, true);
+  if (rc || (rc = check_P(P)) || (rc = check_parts(parts))) return rc;
+  if (!local || !local->perm || !local->bin_vptr || !local->loc_row_ptr || !local->loc_col ||
+      !local->loc_eid)
+    return set_error(CG_EINVAL, "cg_local has a NULL member");
+  if (!out || !out->label || !out->bin || !out->start || !out->n_reads || !out->len ||
+      !out->base_off || !out->cflags || !out->layout_off || !out->layout_vid ||
+      !out->layout_rev || !out->d_total_words || (out->cap_words > 0 && !out->bases))
+    return set_error(CG_EINVAL, "cg_contigs has a NULL member");
+  Scratch s;
+  if ((rc = check_ctx(ctx, g, P, &s))) return rc;
+  return launch_assemble(ctx, *g, s, *parts, *local, P, *out, (hipStream_t)stream);
+}
+
+}  // extern "C"

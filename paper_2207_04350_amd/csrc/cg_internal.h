@@ -1,0 +1,235 @@
+// Internal declarations of libcg: context layout, scratch carving, device
+// utilities (wave / block scans, the single-pass look-back scan) and the
+// kernel launchers each step's source file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cg.h"
+
+namespace cg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Fixed device state of a context: small counters that kernels clean up
+// themselves after use, so that every launch finds them zero.
+// ---------------------------------------------------------------------------
+struct Fixed {
+  unsigned long long mask_acc[2];  // branch count, kept-entry count
+  unsigned int mask_ticket;
+  unsigned int status;             // CG_STATUS_* bits
+  unsigned long long valid_best;   // packed first failure of cg_validate
+  unsigned int scan_ticket;        // look-back scan: block ticket
+  unsigned int scan_done;          // look-back scan: exited blocks
+  unsigned int pad[8];
+};
+
+// Items per block of the look-back scan (one item per thread).
+constexpr int kScanBlock = 1024;
+
+struct Scratch {
+  unsigned long long *scan_status;  // [scan_blocks]
+  int32_t *tmp;        // [n] induce: reads bucketed by component
+  int32_t *lidx;       // [n] induce: local number of each read
+  uint32_t *fill;      // [n] induce: bucket cursors
+  uint64_t *piece_off; // [n] assemble: base offset of each piece in its contig
+  uint32_t *piece_len; // [n] assemble: bases of each piece
+  int32_t *lay_contig; // [n] assemble: record index of each layout entry
+  uint64_t *keys;      // [2n] partition fallback: sort keys
+  uint64_t *bins;      // [2P] partition fallback: sorted bin keys
+  int32_t *aux;        // [n] partition fallback: bin of each component
+  int32_t *walk;       // [16n] assemble: chain arrays of components too big for LDS
+};
+
+}  // namespace cg
+
+struct cg_ctx {
+  int device;
+  char *scratch;
+  size_t scratch_bytes;
+  cg::Fixed *fixed;
+};
+
+namespace cg {
+
+// Scratch carving shared by cg_footprint and the calls.
+struct Layout {
+  size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
+      total;
+};
+Layout layout(int64_t n, int64_t m, int64_t P);
+bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);
+
+// error text (thread local) and HIP error translation
+int set_error(int code, const char *fmt, ...);
+int hip_check(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------------------
+// Device utilities
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ int ld_relaxed(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(int32_t *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+
+// Block-wide exclusive scan; returns the exclusive prefix, *total the block
+// sum.  `sh` needs BLOCK/64 + 1 entries of T.  All threads must call it.
+template <typename T, int BLOCK>
+__device__ __forceinline__ T block_excl_scan(T x, T *sh, T *total) {
+  constexpr int NW = BLOCK / kWave;
+  const int w = threadIdx.x / kWave, l = lane_id();
+  T inc = wave_incl_scan(x);
+  if (l == kWave - 1) sh[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    T v = l < NW ? sh[l] : T(0);
+    T vi = wave_incl_scan(v);
+    if (l < NW) sh[l] = vi - v;
+    if (l == NW - 1) sh[NW] = vi;
+  }
+  __syncthreads();
+  T r = sh[w] + inc - x;
+  *total = sh[NW];
+  __syncthreads();
+  return r;
+}
+
+// Single-pass decoupled look-back scan over `n_items` items, one per thread,
+// blocks of kScanBlock.  Block order comes from an atomic ticket, so a block
+// only waits on blocks that already run.  The last block to exit resets the
+// ticket, the exit counter and the status words, so the next launch finds
+// them zero.  status words: bits 63..62 = 0 none / 1 block aggregate /
+// 2 inclusive prefix, bits 61..0 = value.
+struct ScanCtx {
+  unsigned long long *status;
+  unsigned int *ticket;
+  unsigned int *done;
+};
+
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagPre = 2ull << 62;
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
+
+// Block ticket of a look-back scan launch (all threads of the block call it).
+__device__ __forceinline__ int lookback_ticket(ScanCtx sc) {
+  __shared__ int blk;
+  if (threadIdx.x == 0) blk = (int)atomicAdd(sc.ticket, 1u);
+  __syncthreads();
+  return blk;
+}
+
+__device__ __forceinline__ unsigned long long atomic_ld64(unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish the block aggregate, look back, publish the inclusive prefix;
+// returns the exclusive prefix of the block.  Thread 0 only.
+__device__ __forceinline__ unsigned long long lookback_publish(ScanCtx sc, int blk,
+                                                               unsigned long long agg) {
+  if (blk == 0) {
+    __hip_atomic_store(&sc.status[0], kFlagPre | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  __hip_atomic_store(&sc.status[blk], kFlagAgg | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long excl = 0;
+  int p = blk - 1;
+  while (true) {
+    unsigned long long s = __hip_atomic_load(&sc.status[p], __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long f = s & ~kValMask;
+    if (f == 0) continue;  // predecessor has not published yet (it is running)
+    excl += s & kValMask;
+    if (f == kFlagPre) break;
+    --p;
+  }
+  __hip_atomic_store(&sc.status[blk], kFlagPre | (excl + agg), __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
+// Called by every thread of every block at the very end of a look-back scan
+// kernel: the last block out clears the state for the next launch.
+__device__ __forceinline__ void lookback_finish(ScanCtx sc, int nblocks) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned d = atomicAdd(sc.done, 1u);
+    last = (d == (unsigned)nblocks - 1);
+  }
+  __syncthreads();
+  if (last) {
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) sc.status[i] = 0;
+    if (threadIdx.x == 0) {
+      *sc.ticket = 0;
+      *sc.done = 0;
+    }
+    __threadfence();
+  }
+}
+
+// Block-wide exclusive scan of one item per thread with the look-back
+// across blocks.  `val` is this thread's item value.  Returns the exclusive
+// prefix; *total receives the sum over all blocks up to and including this
+// one (the grand total in the last block).
+__device__ __forceinline__ unsigned long long lookback_block_scan(ScanCtx sc, int blk,
+                                                                  unsigned long long val,
+                                                                  unsigned long long *incl_end) {
+  __shared__ unsigned long long sh[kScanBlock / kWave + 1];
+  __shared__ unsigned long long base;
+  unsigned long long agg;
+  unsigned long long ex = block_excl_scan<unsigned long long, kScanBlock>(val, sh, &agg);
+  if (threadIdx.x == 0) base = lookback_publish(sc, blk, agg);
+  __syncthreads();
+  *incl_end = base + agg;
+  return base + ex;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (one per step; each returns CG_OK or an error code)
+// ---------------------------------------------------------------------------
+int launch_validate(cg_ctx *ctx, const cg_graph &g, int64_t *d_bad, hipStream_t st);
+int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_counts,
+                hipStream_t st);
+int launch_components(cg_ctx *ctx, const cg_graph &g, const uint8_t *flags, int32_t *label,
+                      hipStream_t st);
+int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
+                     const int32_t *label, int32_t P, int32_t min_reads, const cg_parts &out,
+                     hipStream_t st);
+int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
+                  const int32_t *label, const cg_parts &parts, int32_t P, const cg_local &out,
+                  hipStream_t st);
+int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_parts &parts,
+                    const cg_local &local, int32_t P, const cg_contigs &out, hipStream_t st);
+
+inline ScanCtx scan_ctx(cg_ctx *ctx, const Scratch &s) {
+  return ScanCtx{s.scan_status, &ctx->fixed->scan_ticket, &ctx->fixed->scan_done};
+}
+
+inline int scan_blocks(int64_t items) { return (int)((items + kScanBlock - 1) / kScanBlock); }
+
+}  // namespace cg

@@ -1,0 +1,167 @@
+// InducedSubgraph (Section 4.3): V_i = reads owned by bin i, E_i = entries of
+// L with both ends in V_i, renumbered locally with the global ids kept.  All
+// bins share one local numbering ordered by (bin, label, id): a component's
+// reads form the block [comp_start, comp_start + q).
+//
+//  k_ind_zero   bucket cursors; bin_vptr (scan of bin_load); n_e
+//  k_ind_fill   each eligible read claims a slot in its component's block
+//  k_ind_local  one workgroup per component: sort the block by read id
+//               (LDS bitonic up to 1024 reads, rank counting above)
+//  k_ind_rows   local CSR rows (look-back scan of kept degrees), columns
+//               renumbered through the local numbers, entry index kept
+#include "cg_internal.h"
+
+namespace cg {
+
+constexpr int kIndBlock = 256;
+constexpr int kIndLocalCap = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_t *__restrict__ d_n_comp,
+                                                         const uint64_t *__restrict__ bin_load,
+                                                         uint32_t *__restrict__ fill,
+                                                         int32_t *__restrict__ bin_vptr,
+                                                         int32_t *__restrict__ d_sizes) {
+  const int nc = *d_n_comp;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc;
+       c += (int64_t)gridDim.x * blockDim.x)
+    fill[c] = 0;
+  if (blockIdx.x == 0) {
+    __shared__ int64_t sh[kScanBlock / kWave + 1];
+    int64_t carry = 0;
+    for (int base = 0; base < P; base += kScanBlock) {
+      const int b = base + threadIdx.x;
+      const int64_t x = b < P ? (int64_t)bin_load[b] : 0;
+      int64_t tot;
+      const int64_t ex = block_excl_scan<int64_t, kScanBlock>(x, sh, &tot);
+      if (b < P) bin_vptr[b] = (int32_t)(carry + ex);
+      carry += tot;
+    }
+    if (threadIdx.x == 0) {
+      bin_vptr[P] = (int32_t)carry;
+      d_sizes[0] = (int32_t)carry;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kIndBlock) void k_ind_fill(int32_t n, const int32_t *__restrict__ label,
+                                                        const int32_t *__restrict__ label_comp,
+                                                        const int32_t *__restrict__ comp_start,
+                                                        uint32_t *fill, int32_t *__restrict__ tmp) {
+  const int64_t v = (int64_t)blockIdx.x * kIndBlock + threadIdx.x;
+  if (v >= n) return;
+  const int32_t c = label_comp[label[v]];
+  if (c < 0) return;
+  const uint32_t slot = atomicAdd(fill + c, 1u);
+  tmp[comp_start[c] + slot] = (int32_t)v;
+}
+
+__global__ __launch_bounds__(kIndBlock) void k_ind_local(const int32_t *__restrict__ d_n_comp,
+                                                         const int32_t *__restrict__ comp_size,
+                                                         const int32_t *__restrict__ comp_start,
+                                                         const int32_t *__restrict__ tmp,
+                                                         int32_t *__restrict__ perm,
+                                                         int32_t *__restrict__ lidx) {
+  __shared__ int32_t a[kIndLocalCap];
+  const int nc = *d_n_comp;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int q = comp_size[c];
+    const int st = comp_start[c];
+    if (q <= kIndLocalCap) {
+      int N2 = 1;
+      while (N2 < q) N2 <<= 1;
+      for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? tmp[st + i] : 0x7FFFFFFF;
+      __syncthreads();
+      for (int k = 2; k <= N2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = threadIdx.x; i < N2; i += kIndBlock) {
+            const int ixj = i ^ j;
+            if (ixj > i) {
+              const int32_t x = a[i], y = a[ixj];
+              if ((x > y) == ((i & k) == 0)) {
+                a[i] = y;
+                a[ixj] = x;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (int i = threadIdx.x; i < q; i += kIndBlock) {
+        const int32_t v = a[i];
+        perm[st + i] = v;
+        lidx[v] = st + i;
+      }
+    } else {
+      // large component: the rank of a read is the number of smaller ids in
+      // its block (ids are distinct)
+      for (int i = threadIdx.x; i < q; i += kIndBlock) {
+        const int32_t x = tmp[st + i];
+        int r = 0;
+        for (int t = 0; t < q; ++t) r += tmp[st + t] < x;
+        perm[st + r] = x;
+        lidx[x] = st + r;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_ind_rows(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const uint8_t *__restrict__ flags, const int32_t *__restrict__ bin_vptr, int32_t P,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ lidx,
+    int32_t *__restrict__ loc_row_ptr, int32_t *__restrict__ loc_col,
+    int32_t *__restrict__ loc_eid, int32_t *__restrict__ d_sizes, ScanCtx sc, int nblocks) {
+  const int blk = lookback_ticket(sc);
+  const int64_t i = (int64_t)blk * kScanBlock + threadIdx.x;
+  const int32_t n_e = bin_vptr[P];
+  int32_t v = -1;
+  uint32_t f = 0;
+  if (i < n_e) {
+    v = perm[i];
+    f = flags[v];
+  }
+  const uint32_t deg = ((f >> 1) & 1) + ((f >> 2) & 1);
+  unsigned long long incl_end;
+  const unsigned long long ex = lookback_block_scan(sc, blk, deg, &incl_end);
+  if (i <= n_e) loc_row_ptr[i] = (int32_t)ex;
+  if (i == n_e) d_sizes[1] = (int32_t)ex;
+  if (i < n_e && deg) {
+    const int32_t b = row_ptr[v];
+    int32_t t = (int32_t)ex;
+    if (f & 2) {
+      loc_col[t] = lidx[col[b]];
+      loc_eid[t] = b;
+      ++t;
+    }
+    if (f & 4) {
+      loc_col[t] = lidx[col[b + 1]];
+      loc_eid[t] = b + 1;
+    }
+  }
+  lookback_finish(sc, nblocks);
+}
+
+int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
+                  const int32_t *label, const cg_parts &parts, int32_t P, const cg_local &out,
+                  hipStream_t st) {
+  const int32_t n = g.n;
+  const int zgrid = n > 0 ? (int)((n + kScanBlock - 1) / kScanBlock) : 1;
+  hipLaunchKernelGGL(k_ind_zero, dim3(zgrid < 256 ? zgrid : 256), dim3(kScanBlock), 0, st, P,
+                     parts.d_n_comp, parts.bin_load, s.fill, out.bin_vptr, out.d_sizes);
+  if (n > 0) {
+    const int grid = (int)((n + kIndBlock - 1) / kIndBlock);
+    hipLaunchKernelGGL(k_ind_fill, dim3(grid), dim3(kIndBlock), 0, st, n, label, parts.label_comp,
+                       parts.comp_start, s.fill, s.tmp);
+    const int lgrid = n < 4096 ? n : 4096;
+    hipLaunchKernelGGL(k_ind_local, dim3(lgrid), dim3(kIndBlock), 0, st, parts.d_n_comp,
+                       parts.comp_size, parts.comp_start, s.tmp, out.perm, s.lidx);
+  }
+  const int nb = scan_blocks((int64_t)n + 1);
+  hipLaunchKernelGGL(k_ind_rows, dim3(nb), dim3(kScanBlock), 0, st, g.row_ptr, g.col, flags,
+                     out.bin_vptr, P, out.perm, s.lidx, out.loc_row_ptr, out.loc_col, out.loc_eid,
+                     out.d_sizes, scan_ctx(ctx, s), nb);
+  return hip_check(hipGetLastError(), "k_ind");
+}
+
+}  // namespace cg

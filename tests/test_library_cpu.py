@@ -1,0 +1,51 @@
+"""Host-side checks of libcg that need no GPU: the library loads, exports
+every entry point include/cg.h declares, sizes scratch, and rejects bad
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2207_04350_amd import cg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "cg.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(cg_\w+)\(", text, re.M)))
+
+
+def test_header_declares_the_five_steps():
+    names = _declared()
+    for step in ("cg_mask_branches", "cg_components", "cg_partition", "cg_induce", "cg_assemble"):
+        assert step in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cg.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_footprint_grows_with_the_graph():
+    a = cg.footprint(1000, 2000, 8)
+    b = cg.footprint(100000, 200000, 8)
+    c = cg.footprint(100000, 200000, 4096)
+    assert 0 < a < b < c
+    with pytest.raises(cg.CgError):
+        cg.footprint(-1, 0, 8)
+
+
+def test_null_arguments_rejected_on_host():
+    lib = cg.lib()
+    g = cg.CgGraph()
+    g.n, g.m = 10, 0
+    assert lib.cg_mask_branches(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
+    assert b"NULL" in lib.cg_last_error() or lib.cg_last_error()
+    assert lib.cg_partition(None, ctypes.byref(g), None, None, 0, 2, None, None) == cg.CG_EINVAL
+    assert lib.cg_partition(None, ctypes.byref(g), None, None, 70000, 2, None, None) == cg.CG_EINVAL
+    g.n = 1 << 30
+    assert lib.cg_components(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
