@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the contig-generation path on one MI355X.
+
+One step = one pass of the whole path (branch removal, connected components,
+LPT partitioning, induced subgraphs, local assembly) over one batch of
+synthetic string graphs already resident in HBM.  The default workload is the
+batched configuration: 512 independent graphs (genomes log-uniform in
+0.2-20 Mbp, 10-40x coverage, reads lognormal with mean 10 kbp and sd 3 kbp,
+0.5-3% extra branch edges, P = 64 bins per graph).
+
+Printed on the last stdout line, as JSON: throughput in contig bases/s, the
+string-graph edges/s of the mask + components phase, the roofline of the
+dominant kernel (HIP events, algorithmic bytes) and the oracle's CPU
+throughput on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch|plain50|large1g]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "string-graph edges/s + contig bases/s, batched vs plain, % of HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic bytes per kernel (each array counted once; gathers, re-reads and
+# atomics traffic are not counted).  `s` holds the workload's sizes for the
+# graphs one launch processes.
+# ---------------------------------------------------------------------------
+
+def algo_bytes(kernel, s):
+    N, m, m_nb, n_e, m_e, nc, Cb, W = (s["N"], s["m"], s["m_nb"], s["n_e"], s["m_e"], s["n_comp"],
+                                       s["contig_bases"], s["words"])
+    table = {
+        # row_ptr (N+1), the columns of rows of degree <= 2, flags written
+        "k_mask": 4 * (N + 1) + 4 * m_nb + N,
+        "k_cc_init": 4 * N,
+        # flags + row_ptr + kept columns read; label updates not counted
+        "k_cc_hook": N + 4 * N + 4 * m_nb,
+        "k_cc_compress": 4 * N + 4 * N,
+        "k_part_zero": 4 * N,
+        "k_part_count": N + 4 * N,
+        "k_part_compact": N + 4 * N + 4 * N + 9 * nc,
+        "k_part_lpt": 4 * nc + 16 * nc,
+        "k_ind_zero": 4 * nc,
+        "k_ind_fill": 4 * N + 4 * N + 8 * n_e,
+        "k_ind_local": 8 * n_e + 4 * n_e,
+        "k_ind_rows": 4 * n_e + n_e + 4 * (n_e + 1) + 8 * m_e + 4 * n_e,
+        "k_asm_walk": 4 * n_e + 8 * n_e + 8 * m_e + 9 * m_e + 4 * n_e + 5 * n_e + 16 * n_e,
+        "k_asm_offsets": 16 * nc,
+        # packed source bases read + contig words written + per-piece,
+        # per-read and per-contig descriptors
+        "k_asm_copy": Cb // 4 + 4 * W + 33 * n_e + 16 * nc,
+    }
+    return table.get(kernel)
+
+
+def workload_graphs(name):
+    import synth
+    if name == "batch":
+        return synth.batch_graphs(512), "batched: 512 independent string graphs (genome 0.2-20 Mbp " \
+            "log-uniform, 10-40x, reads LN(10k,3k), 0.5-3% branch edges, P=64 per graph)"
+    if name == "plain50":
+        return [synth.config_graph(2)], "plain: one string graph, 50 Mbp genome + 200x8 kbp " \
+            "repeats, 30x, reads LN(12k,4k), 2% branch edges, P=64"
+    if name == "large1g":
+        return [synth.config_graph(3)], "plain: one string graph, 1 Gbp genome with 5% repeats, " \
+            "20x, reads LN(15k,5k), 1% branch edges, P=1024"
+    raise SystemExit("unknown workload %s" % name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="bound on the oracle's CPU baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build runs the path on one GPU's share of "
+              "the graphs and has no multi-GPU mode (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2207_04350_amd import cg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cg.lib()
+
+    t0 = time.time()
+    graphs, desc = workload_graphs(args.workload)
+    log("generated %d graphs in %.1fs" % (len(graphs), time.time() - t0))
+    Ps = [g.meta["P"] for g in graphs]
+    t0 = time.time()
+    dgs = [cg.DeviceGraph(g, dev) for g in graphs]
+    outs = [cg.Outputs(g.n, P, g.seq_words, dev) for g, P in zip(graphs, Ps)]
+    big = max(range(len(graphs)), key=lambda i: cg.footprint(graphs[i].n, graphs[i].m, Ps[i]))
+    ctx = cg.Context.for_graph(graphs[big].n, graphs[big].m, Ps[big])
+    torch.cuda.synchronize()
+    log("resident in HBM in %.1fs" % (time.time() - t0))
+    stream = torch.cuda.current_stream()
+
+    def plain_step():
+        for dg, out, P in zip(dgs, outs, Ps):
+            cg.run_path(ctx, dg, out, P, 2, stream)
+
+    # ---- plain per-graph launches: warmup, then K timed steps -------------
+    for _ in range(args.warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plain_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
+    log("plain: %.3f ms/step wall, %.3f ms/step between events" % (wall_ms, gpu_ms))
+
+    # ---- workload sizes (from one step's device-side counts) ---------------
+    st = dict(N=0, m=0, m_nb=0, n_e=0, m_e=0, n_comp=0, contig_bases=0, words=0)
+    for g, out in zip(graphs, outs):
+        deg = np.diff(g.row_ptr)
+        st["N"] += g.n
+        st["m"] += g.m
+        st["m_nb"] += int(deg[deg <= 2].sum())
+        sz = out.sizes.cpu().numpy()
+        st["n_e"] += int(sz[0])
+        st["m_e"] += int(sz[1])
+        nc = int(out.n_comp.item())
+        st["n_comp"] += nc
+        st["contig_bases"] += int(out.c_len[:nc].sum().item())
+        st["words"] += int(out.total_words.item())
+
+    # ---- per-kernel HIP-event timing over K more steps ---------------------
+    launches_per_step = 16 * len(graphs)
+    ctx.profile(launches_per_step * args.steps + 64)
+    for _ in range(args.steps):
+        plain_step()
+    prof = ctx.profile_read()
+    ctx.profile(0)
+    kern = {k: (c / args.steps, ms / args.steps) for k, (c, ms) in prof.items() if k[0] != "_"}
+    phase_ms = {
+        "mask": sum(v[1] for k, v in kern.items() if k == "k_mask"),
+        "components": sum(v[1] for k, v in kern.items() if k.startswith("k_cc")),
+        "partition": sum(v[1] for k, v in kern.items() if k.startswith("k_part")),
+        "induce": sum(v[1] for k, v in kern.items() if k.startswith("k_ind")),
+        "assemble": sum(v[1] for k, v in kern.items() if k.startswith("k_asm")),
+    }
+    for k, (c, ms) in sorted(kern.items(), key=lambda kv: -kv[1][1]):
+        log("  %-16s %6d launches/step %9.3f ms/step %8.2f us/launch" % (k, c, ms, 1e3 * ms / c))
+
+    maskcc_ms = phase_ms["mask"] + phase_ms["components"]
+    maskcc_bytes = sum(algo_bytes(k, st) for k in ("k_mask", "k_cc_init", "k_cc_hook",
+                                                   "k_cc_compress"))
+    dom = max(kern, key=lambda k: kern[k][1])
+    dom_launches, dom_ms = kern[dom]
+    dom_avg_us = 1e3 * dom_ms / dom_launches
+    dom_bytes_per_launch = algo_bytes(dom, st) / dom_launches
+    achieved = dom_bytes_per_launch / (dom_avg_us * 1e-6) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": st["contig_bases"] / (wall_ms * 1e-3),
+        "unit": "contig bases/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded simulated genomes and reads; exact reduced string graphs)",
+        "config": {"workload": desc, "form": "plain per-graph launches", "graphs": len(graphs),
+                   "reads": st["N"], "directed_entries": st["m"], "contig_reads": st["n_e"],
+                   "contigs": st["n_comp"], "contig_bases": st["contig_bases"],
+                   "packed_read_bytes": int(sum(g.seq_words for g in graphs) * 4)},
+        "edges_per_s_mask_cc": st["m"] / (maskcc_ms * 1e-3) if maskcc_ms else None,
+        "mask_cc": {"ms_per_step": maskcc_ms, "algorithmic_bytes": maskcc_bytes,
+                    "hbm_frac": maskcc_bytes / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                    if maskcc_ms else None},
+        "phase_kernel_ms_per_step": phase_ms,
+        "gpu_ms_per_step_events": gpu_ms,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": dom_avg_us, "bytes_per_launch": dom_bytes_per_launch,
+                     "timing": "HIP events around each launch on its stream, %d steps"
+                               % args.steps},
+    }
+
+    # ---- CPU oracle on a bounded sample, with parity of the same graphs ----
+    if not args.no_cpu:
+        import oracle
+        from tests.parity import mismatches
+        spent, bases, done, ok = 0.0, 0, 0, 0
+        order = list(range(len(graphs)))
+        for i in order:
+            g = graphs[i]
+            tm = {}
+            want = oracle.run(g, P=Ps[i], min_reads=2, timings=tm)
+            spent += tm["total"]
+            bases += int(want["contigs"]["len"].sum())
+            done += 1
+            got = cg.to_host(outs[i], g.n)
+            ok += int(mismatches(got, want) == [])
+            if spent >= args.cpu_seconds:
+                break
+        result["cpu_baseline"] = {
+            "value": bases / spent, "unit": "contig bases/s", "cores": 1, "kind": "oracle",
+            "sample": "graphs 0..%d of the %d (%d contig bases), single-threaded C oracle, "
+                      "whole path" % (done - 1, len(graphs), bases),
+            "seconds": spent}
+        result["parity_sample"] = {"graphs": done, "identical": ok}
+        log("oracle: %d graphs in %.1fs, parity %d/%d" % (done, spent, ok, done))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

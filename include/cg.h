@@ -197,6 +197,20 @@ int cg_footprint(int32_t n, int32_t m, int32_t P, uint64_t *bytes);
  * `stream`, then copies the word to *status [host]; clears it if `clear`. */
 int cg_ctx_status(cg_ctx *ctx, void *stream, uint32_t *status, int clear);
 
+/* Per-kernel timing (benchmarks): with max_launches > 0 every kernel launch
+ * of the library, up to max_launches of them, is bracketed by two HIP events
+ * recorded on the stream it is launched on; 0 switches timing off.  Recording
+ * events adds a little time between kernels. */
+int cg_ctx_profile(cg_ctx *ctx, int32_t max_launches);
+
+/* Waits for the recorded events and reports, per kernel name, the number of
+ * launches and their summed duration in ms, then clears the record.  names,
+ * launches and ms are [host] arrays of `cap` entries; names[i] point to
+ * static strings; *n_kernels [host] receives the count, *dropped [host,
+ * optional] the launches that found no free event pair. */
+int cg_ctx_profile_read(cg_ctx *ctx, int32_t cap, const char **names, int64_t *launches,
+                        double *ms, int32_t *n_kernels, int64_t *dropped);
+
 /* Thread-local text of the last error. */
 const char *cg_last_error(void);
 

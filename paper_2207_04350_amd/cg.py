@@ -77,7 +77,12 @@ def lib():
                                 P(CgLocal), _vp]
         L.cg_assemble.argtypes = [_vp, P(CgGraph), P(CgParts), P(CgLocal), ctypes.c_int32,
                                   P(CgContigs), _vp]
-        for name in ("cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
+        L.cg_ctx_profile.argtypes = [_vp, ctypes.c_int32]
+        L.cg_ctx_profile_read.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_char_p),
+                                          P(ctypes.c_int64), P(ctypes.c_double),
+                                          P(ctypes.c_int32), P(ctypes.c_int64)]
+        for name in ("cg_ctx_profile", "cg_ctx_profile_read",
+                     "cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
                      "cg_validate", "cg_mask_branches", "cg_components", "cg_partition",
                      "cg_induce", "cg_assemble"):
             getattr(L, name).restype = ctypes.c_int
@@ -123,6 +128,25 @@ class Context:
         s = ctypes.c_uint32(0)
         _check(lib().cg_ctx_status(self.handle, _stream(stream), ctypes.byref(s), int(clear)))
         return int(s.value)
+
+    def profile(self, max_launches):
+        """Bracket each kernel launch with HIP events (0 switches it off)."""
+        _check(lib().cg_ctx_profile(self.handle, int(max_launches)))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since the last read."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        launches = (ctypes.c_int64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        nk = ctypes.c_int32(0)
+        dropped = ctypes.c_int64(0)
+        _check(lib().cg_ctx_profile_read(self.handle, cap, names, launches, ms,
+                                         ctypes.byref(nk), ctypes.byref(dropped)))
+        out = {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(nk.value)}
+        if dropped.value:
+            out["_dropped"] = (int(dropped.value), 0.0)
+        return out
 
     def close(self):
         if self.handle and self.handle.value:

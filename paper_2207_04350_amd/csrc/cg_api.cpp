@@ -69,6 +69,34 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   return true;
 }
 
+int prof_begin(cg_ctx *ctx, hipStream_t st, const char *name) {
+  if (!ctx || !ctx->prof) return -1;
+  if (ctx->prof_used >= ctx->prof_cap) {
+    ++ctx->prof_dropped;
+    return -1;
+  }
+  const int slot = ctx->prof_used++;
+  ctx->prof[slot].name = name;
+  (void)hipEventRecord(ctx->prof[slot].a, st);
+  return slot;
+}
+
+void prof_end(cg_ctx *ctx, hipStream_t st, int slot) {
+  if (slot >= 0) (void)hipEventRecord(ctx->prof[slot].b, st);
+}
+
+static void prof_free(cg_ctx *ctx) {
+  if (!ctx->prof) return;
+  for (int i = 0; i < ctx->prof_cap; ++i) {
+    (void)hipEventDestroy(ctx->prof[i].a);
+    (void)hipEventDestroy(ctx->prof[i].b);
+  }
+  delete[] ctx->prof;
+  ctx->prof = nullptr;
+  ctx->prof_cap = ctx->prof_used = 0;
+  ctx->prof_dropped = 0;
+}
+
 }  // namespace cg
 
 using namespace cg;
@@ -124,6 +152,9 @@ int cg_ctx_create(int device, size_t scratch_bytes, cg_ctx **out) {
   c->scratch_bytes = scratch_bytes;
   c->scratch = nullptr;
   c->fixed = nullptr;
+  c->prof = nullptr;
+  c->prof_cap = c->prof_used = 0;
+  c->prof_dropped = 0;
   rc = hip_check(hipMalloc((void **)&c->fixed, sizeof(Fixed)), "hipMalloc(fixed)");
   if (!rc) rc = hip_check(hipMemset(c->fixed, 0, sizeof(Fixed)), "hipMemset(fixed)");
   if (!rc && scratch_bytes)
@@ -148,6 +179,7 @@ int cg_ctx_destroy(cg_ctx *ctx) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
   int rc = CG_OK;
+  prof_free(ctx);
   if (ctx->scratch) rc = hip_check(hipFree(ctx->scratch), "hipFree(scratch)");
   if (ctx->fixed && !rc) rc = hip_check(hipFree(ctx->fixed), "hipFree(fixed)");
   (void)hipSetDevice(prev);
@@ -166,6 +198,57 @@ int cg_ctx_status(cg_ctx *ctx, void *stream, uint32_t *status, int clear) {
   if (clear)
     rc = hip_check(hipMemset(&ctx->fixed->status, 0, sizeof(uint32_t)), "hipMemset(status)");
   return rc;
+}
+
+int cg_ctx_profile(cg_ctx *ctx, int32_t max_launches) {
+  if (!ctx || max_launches < 0) return set_error(CG_EINVAL, "bad profile arguments");
+  prof_free(ctx);
+  if (max_launches == 0) return CG_OK;
+  ctx->prof = new (std::nothrow) ProfEntry[max_launches];
+  if (!ctx->prof) return set_error(CG_EINVAL, "out of host memory");
+  for (int i = 0; i < max_launches; ++i) {
+    ctx->prof[i].name = nullptr;
+    int rc = hip_check(hipEventCreate(&ctx->prof[i].a), "hipEventCreate");
+    if (!rc) rc = hip_check(hipEventCreate(&ctx->prof[i].b), "hipEventCreate");
+    if (rc) {
+      ctx->prof_cap = i;
+      prof_free(ctx);
+      return rc;
+    }
+    ctx->prof_cap = i + 1;
+  }
+  ctx->prof_used = 0;
+  return CG_OK;
+}
+
+int cg_ctx_profile_read(cg_ctx *ctx, int32_t cap, const char **names, int64_t *launches,
+                        double *ms, int32_t *n_kernels, int64_t *dropped) {
+  if (!ctx || !n_kernels || cap < 0 || (cap > 0 && (!names || !launches || !ms)))
+    return set_error(CG_EINVAL, "bad profile_read arguments");
+  int k = 0;
+  for (int i = 0; i < ctx->prof_used; ++i) {
+    int rc = hip_check(hipEventSynchronize(ctx->prof[i].b), "hipEventSynchronize");
+    if (rc) return rc;
+    float t = 0.f;
+    rc = hip_check(hipEventElapsedTime(&t, ctx->prof[i].a, ctx->prof[i].b), "hipEventElapsedTime");
+    if (rc) return rc;
+    int j = 0;
+    while (j < k && strcmp(names[j], ctx->prof[i].name) != 0) ++j;
+    if (j == k) {
+      if (k == cap) return set_error(CG_ECAPACITY, "more than %d kernel names", cap);
+      names[k] = ctx->prof[i].name;
+      launches[k] = 0;
+      ms[k] = 0.0;
+      ++k;
+    }
+    launches[j] += 1;
+    ms[j] += t;
+  }
+  *n_kernels = k;
+  if (dropped) *dropped = ctx->prof_dropped;
+  ctx->prof_used = 0;
+  ctx->prof_dropped = 0;
+  return CG_OK;
 }
 
 int cg_validate(cg_ctx *ctx, const cg_graph *g, int64_t *d_bad, void *stream) {

@@ -45,11 +45,23 @@ struct Scratch {
 
 }  // namespace cg
 
+namespace cg {
+struct ProfEntry {
+  const char *name;
+  hipEvent_t a, b;
+};
+}  // namespace cg
+
 struct cg_ctx {
   int device;
   char *scratch;
   size_t scratch_bytes;
   cg::Fixed *fixed;
+  // optional per-kernel event timing (cg_ctx_profile)
+  int prof_cap;
+  int prof_used;
+  long long prof_dropped;
+  cg::ProfEntry *prof;
 };
 
 namespace cg {
@@ -208,6 +220,18 @@ __device__ __forceinline__ unsigned long long lookback_block_scan(ScanCtx sc, in
   *incl_end = base + agg;
   return base + ex;
 }
+
+// Kernel launch, bracketed by two events on its stream when the context's
+// per-kernel timing is on.
+int prof_begin(cg_ctx *ctx, hipStream_t st, const char *name);
+void prof_end(cg_ctx *ctx, hipStream_t st, int slot);
+
+#define CG_LAUNCH(ctx, kern, grid, block, st, ...)                 \
+  do {                                                             \
+    const int cg_prof_slot_ = ::cg::prof_begin((ctx), (st), #kern); \
+    hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);     \
+    ::cg::prof_end((ctx), (st), cg_prof_slot_);                    \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // Launchers (one per step; each returns CG_OK or an error code)

@@ -355,17 +355,17 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
                     const cg_local &local, int32_t P, const cg_contigs &out, hipStream_t st) {
   const int32_t n = g.n;
   if (n == 0) {
-    hipLaunchKernelGGL(k_asm_offsets, dim3(1), dim3(kScanBlock), 0, st, parts.d_n_comp, out.len,
+    CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,
                        out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
     return hip_check(hipGetLastError(), "k_asm");
   }
   const int wgrid = n < 4096 ? n : 4096;
-  hipLaunchKernelGGL(k_asm_walk, dim3(wgrid), dim3(kWalkBlock), 0, st, g, parts, local, out, s,
+  CG_LAUNCH(ctx, k_asm_walk, dim3(wgrid), dim3(kWalkBlock), st, g, parts, local, out, s,
                      s.walk);
-  hipLaunchKernelGGL(k_asm_offsets, dim3(1), dim3(kScanBlock), 0, st, parts.d_n_comp, out.len,
+  CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,
                      out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
   const int cgrid = n < 8192 ? n : 8192;
-  hipLaunchKernelGGL(k_asm_copy, dim3(cgrid), dim3(kCopyBlock), 0, st, g.seq, g.seq_words,
+  CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
                      g.read_len,
                      g.read_off, local.bin_vptr, P, out.layout_vid, out.layout_rev, s.piece_off,
                      s.piece_len, s.lay_contig, out.len, out.base_off, out.d_total_words,

@@ -147,18 +147,18 @@ int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_
                   hipStream_t st) {
   const int32_t n = g.n;
   const int zgrid = n > 0 ? (int)((n + kScanBlock - 1) / kScanBlock) : 1;
-  hipLaunchKernelGGL(k_ind_zero, dim3(zgrid < 256 ? zgrid : 256), dim3(kScanBlock), 0, st, P,
+  CG_LAUNCH(ctx, k_ind_zero, dim3(zgrid < 256 ? zgrid : 256), dim3(kScanBlock), st, P,
                      parts.d_n_comp, parts.bin_load, s.fill, out.bin_vptr, out.d_sizes);
   if (n > 0) {
     const int grid = (int)((n + kIndBlock - 1) / kIndBlock);
-    hipLaunchKernelGGL(k_ind_fill, dim3(grid), dim3(kIndBlock), 0, st, n, label, parts.label_comp,
+    CG_LAUNCH(ctx, k_ind_fill, dim3(grid), dim3(kIndBlock), st, n, label, parts.label_comp,
                        parts.comp_start, s.fill, s.tmp);
     const int lgrid = n < 4096 ? n : 4096;
-    hipLaunchKernelGGL(k_ind_local, dim3(lgrid), dim3(kIndBlock), 0, st, parts.d_n_comp,
+    CG_LAUNCH(ctx, k_ind_local, dim3(lgrid), dim3(kIndBlock), st, parts.d_n_comp,
                        parts.comp_size, parts.comp_start, s.tmp, out.perm, s.lidx);
   }
   const int nb = scan_blocks((int64_t)n + 1);
-  hipLaunchKernelGGL(k_ind_rows, dim3(nb), dim3(kScanBlock), 0, st, g.row_ptr, g.col, flags,
+  CG_LAUNCH(ctx, k_ind_rows, dim3(nb), dim3(kScanBlock), st, g.row_ptr, g.col, flags,
                      out.bin_vptr, P, out.perm, s.lidx, out.loc_row_ptr, out.loc_col, out.loc_eid,
                      out.d_sizes, scan_ctx(ctx, s), nb);
   return hip_check(hipGetLastError(), "k_ind");

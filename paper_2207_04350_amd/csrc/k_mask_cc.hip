@@ -72,7 +72,7 @@ int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_count
                 hipStream_t st) {
   int grid = (int)((g.n + kMaskBlock - 1) / kMaskBlock);
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kMaskBlock), 0, st, g.n, g.row_ptr, g.col, flags,
+  CG_LAUNCH(ctx, k_mask, dim3(grid), dim3(kMaskBlock), st, g.n, g.row_ptr, g.col, flags,
                      ctx->fixed, d_counts);
   return hip_check(hipGetLastError(), "k_mask");
 }
@@ -157,10 +157,10 @@ int launch_components(cg_ctx *ctx, const cg_graph &g, const uint8_t *flags, int3
   (void)ctx;
   if (g.n == 0) return CG_OK;
   int grid = (int)((g.n + kCcBlock - 1) / kCcBlock);
-  hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(kCcBlock), 0, st, g.n, label);
-  hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(kCcBlock), 0, st, g.n, g.row_ptr, g.col, flags,
+  CG_LAUNCH(ctx, k_cc_init, dim3(grid), dim3(kCcBlock), st, g.n, label);
+  CG_LAUNCH(ctx, k_cc_hook, dim3(grid), dim3(kCcBlock), st, g.n, g.row_ptr, g.col, flags,
                      label);
-  hipLaunchKernelGGL(k_cc_compress, dim3(grid), dim3(kCcBlock), 0, st, g.n, label);
+  CG_LAUNCH(ctx, k_cc_compress, dim3(grid), dim3(kCcBlock), st, g.n, label);
   return hip_check(hipGetLastError(), "k_cc");
 }
 
@@ -252,9 +252,9 @@ __global__ void k_val_final(Fixed *fx, int64_t *d_bad) {
 int launch_validate(cg_ctx *ctx, const cg_graph &g, int64_t *d_bad, hipStream_t st) {
   int grid = (int)((g.n + kValBlock - 1) / kValBlock);
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_val_init, dim3(1), dim3(1), 0, st, ctx->fixed);
-  hipLaunchKernelGGL(k_val_check, dim3(grid), dim3(kValBlock), 0, st, g, ctx->fixed);
-  hipLaunchKernelGGL(k_val_final, dim3(1), dim3(1), 0, st, ctx->fixed, d_bad);
+  CG_LAUNCH(ctx, k_val_init, dim3(1), dim3(1), st, ctx->fixed);
+  CG_LAUNCH(ctx, k_val_check, dim3(grid), dim3(kValBlock), st, g, ctx->fixed);
+  CG_LAUNCH(ctx, k_val_final, dim3(1), dim3(1), st, ctx->fixed, d_bad);
   return hip_check(hipGetLastError(), "k_val");
 }
 

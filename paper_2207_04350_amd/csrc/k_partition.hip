@@ -229,15 +229,15 @@ int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uin
   if (min_reads < 1) min_reads = 1;
   const int grid = n > 0 ? (int)((n + kPartBlock - 1) / kPartBlock) : 1;
   if (n > 0) {
-    hipLaunchKernelGGL(k_part_zero, dim3(grid), dim3(kPartBlock), 0, st, n, out.label_comp);
-    hipLaunchKernelGGL(k_part_count, dim3(grid), dim3(kPartBlock), 0, st, n, flags, label,
+    CG_LAUNCH(ctx, k_part_zero, dim3(grid), dim3(kPartBlock), st, n, out.label_comp);
+    CG_LAUNCH(ctx, k_part_count, dim3(grid), dim3(kPartBlock), st, n, flags, label,
                        out.label_comp);
   }
   const int nb = scan_blocks(n > 0 ? n : 1);
-  hipLaunchKernelGGL(k_part_compact, dim3(nb), dim3(kScanBlock), 0, st, n, flags, out.label_comp,
+  CG_LAUNCH(ctx, k_part_compact, dim3(nb), dim3(kScanBlock), st, n, flags, out.label_comp,
                      min_reads, out.comp_label, out.comp_size, out.comp_kind, out.d_n_comp,
                      scan_ctx(ctx, s), nb);
-  hipLaunchKernelGGL(k_part_lpt, dim3(1), dim3(kLptBlock), 0, st, P, out.d_n_comp, out.comp_size,
+  CG_LAUNCH(ctx, k_part_lpt, dim3(1), dim3(kLptBlock), st, P, out.d_n_comp, out.comp_size,
                      out.comp_bin, out.comp_rank, out.comp_start, out.bin_load, s.keys, s.aux,
                      s.bins);
   return hip_check(hipGetLastError(), "k_part");
