@@ -60,6 +60,8 @@ extern "C" {
 
 /* device status bits reported by cg_ctx_status() */
 #define CG_STATUS_BASES_OVERFLOW 1u /* cg_assemble: contigs need more than cap_words */
+#define CG_STATUS_SCAN_STALLED   2u /* a scan stopped waiting for a block that never
+                                       published (results of that call are invalid) */
 
 /*
  * The string graph S (Section 2: a bidirected graph, stored as a symmetric
@@ -265,6 +267,52 @@ int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_
  * entered by.  Fills `out` (cg_contigs above). */
 int cg_assemble(cg_ctx *ctx, const cg_graph *g, const cg_parts *parts, const cg_local *local,
                 int32_t P, const cg_contigs *out, void *stream);
+
+/* ---- batched form -------------------------------------------------------- */
+
+/* One graph of a batch: its inputs, its parameters and the same output
+ * buffers the single-graph calls fill (same sizes and meaning). */
+typedef struct {
+  cg_graph g;
+  int32_t P;          /* bins, 1..65536 */
+  int32_t min_reads;  /* as in cg_partition */
+  uint8_t *flags;     /* [n]  as in cg_mask_branches */
+  int32_t *d_counts;  /* [2]  as in cg_mask_branches */
+  int32_t *label;     /* [n]  as in cg_components */
+  cg_parts parts;
+  cg_local local;
+  cg_contigs contigs;
+} cg_job;
+
+/* Launch shapes of the batched kernels (0 = default).  They change speed,
+ * never results. */
+typedef struct {
+  int32_t vertex_tile;     /* vertices per workgroup in vertex passes: 256 (default), 512, 1024 */
+  int32_t copy_block;      /* threads per workgroup of the base copy, multiple of 64 (256) */
+  int32_t persist_blocks;  /* workgroups of the persistent passes (4 per compute unit) */
+} cg_batch_params;
+
+typedef struct cg_batch cg_batch;
+
+/* Plan a batch of n_jobs independent graphs (jobs is [host]): copies the job
+ * descriptors to the device and allocates the tile table, scan state and
+ * per-job scratch (device memory owned by the batch).  The buffers the jobs
+ * point to must stay valid and unmoved while the batch exists.  Runs every
+ * step of Algorithm 2 for all jobs with one launch per phase; each job's
+ * outputs are identical to the five single-graph calls on that job. */
+int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
+                    const cg_batch_params *params, cg_batch **out);
+
+/* Enqueue the whole path for every job of the batch on `stream`. */
+int cg_batch_run(cg_batch *b, void *stream);
+
+/* Capture cg_batch_run into a HIP graph on `stream` (must not be the NULL
+ * stream) and instantiate it; cg_batch_launch then replays it. */
+int cg_batch_capture(cg_batch *b, void *stream);
+int cg_batch_launch(cg_batch *b, void *stream);
+
+/* Release the batch (the caller makes sure none of its work is in flight). */
+int cg_batch_destroy(cg_batch *b);
 
 #ifdef __cplusplus
 }

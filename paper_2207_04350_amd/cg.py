@@ -19,6 +19,7 @@ CG_OK, CG_EINVAL, CG_ENOMEM, CG_EHIP, CG_ECAPACITY, CG_EUNSUPPORTED = 0, -1, -2,
 KIND_SINGLE, KIND_PATH, KIND_CYCLE = 0, 1, 2
 CONTIG_CIRCULAR, CONTIG_SAME_END_JOIN, CONTIG_SINGLE = 1, 2, 4
 STATUS_BASES_OVERFLOW = 1
+STATUS_SCAN_STALLED = 2
 
 _vp = ctypes.c_void_p
 
@@ -45,6 +46,17 @@ class CgContigs(ctypes.Structure):
                 ("base_off", _vp), ("cflags", _vp), ("layout_off", _vp), ("layout_vid", _vp),
                 ("layout_rev", _vp), ("bases", _vp), ("cap_words", ctypes.c_uint64),
                 ("d_total_words", _vp)]
+
+
+class CgJob(ctypes.Structure):
+    _fields_ = [("g", CgGraph), ("P", ctypes.c_int32), ("min_reads", ctypes.c_int32),
+                ("flags", _vp), ("d_counts", _vp), ("label", _vp), ("parts", CgParts),
+                ("local", CgLocal), ("contigs", CgContigs)]
+
+
+class CgBatchParams(ctypes.Structure):
+    _fields_ = [("vertex_tile", ctypes.c_int32), ("copy_block", ctypes.c_int32),
+                ("persist_blocks", ctypes.c_int32)]
 
 
 class CgError(RuntimeError):
@@ -81,7 +93,13 @@ def lib():
         L.cg_ctx_profile_read.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_char_p),
                                           P(ctypes.c_int64), P(ctypes.c_double),
                                           P(ctypes.c_int32), P(ctypes.c_int64)]
-        for name in ("cg_ctx_profile", "cg_ctx_profile_read",
+        L.cg_batch_create.argtypes = [_vp, ctypes.c_int32, P(CgJob), P(CgBatchParams), P(_vp)]
+        L.cg_batch_run.argtypes = [_vp, _vp]
+        L.cg_batch_capture.argtypes = [_vp, _vp]
+        L.cg_batch_launch.argtypes = [_vp, _vp]
+        L.cg_batch_destroy.argtypes = [_vp]
+        for name in ("cg_batch_create", "cg_batch_run", "cg_batch_capture", "cg_batch_launch",
+                     "cg_batch_destroy", "cg_ctx_profile", "cg_ctx_profile_read",
                      "cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
                      "cg_validate", "cg_mask_branches", "cg_components", "cg_partition",
                      "cg_induce", "cg_assemble"):
@@ -310,3 +328,48 @@ def to_host(out, n):
                           else np.zeros(0, np.uint32)))
     return dict(flags=h(out.flags)[:n], counts=h(out.counts), label=h(out.label)[:n],
                 parts=parts, local=local, contigs=contigs)
+
+
+class Batch:
+    """A cg_batch over resident graphs: `jobs` is a list of (DeviceGraph,
+    Outputs, P, min_reads).  Keeps the tensors alive while it exists."""
+
+    def __init__(self, ctx, jobs, vertex_tile=0, copy_block=0, persist_blocks=0):
+        self.ctx = ctx
+        self._keep = jobs
+        arr = (CgJob * len(jobs))()
+        for i, (dg, out, P, mr) in enumerate(jobs):
+            arr[i].g = dg.struct
+            arr[i].P = int(P)
+            arr[i].min_reads = int(mr)
+            arr[i].flags = _ptr(out.flags)
+            arr[i].d_counts = _ptr(out.counts)
+            arr[i].label = _ptr(out.label)
+            arr[i].parts = out.parts
+            arr[i].local = out.local
+            arr[i].contigs = out.contigs
+        prm = CgBatchParams(int(vertex_tile), int(copy_block), int(persist_blocks))
+        self.handle = _vp(0)
+        _check(lib().cg_batch_create(ctx.handle, len(jobs), arr, ctypes.byref(prm),
+                                     ctypes.byref(self.handle)))
+        self.params = (vertex_tile, copy_block, persist_blocks)
+
+    def run(self, stream=None):
+        _check(lib().cg_batch_run(self.handle, _stream(stream)))
+
+    def capture(self, stream):
+        _check(lib().cg_batch_capture(self.handle, _stream(stream)))
+
+    def launch(self, stream):
+        _check(lib().cg_batch_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle and self.handle.value:
+            _check(lib().cg_batch_destroy(self.handle))
+            self.handle = _vp(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,536 @@
+// Device code shared by the single-graph kernels and the batched kernels:
+// union-find, the sort + LPT body, the per-component walk and the packed
+// base access.  Each part names the step of Algorithm 2 it serves.
+#pragma once
+
+#include "cg_internal.h"
+
+namespace cg {
+
+// ---------------------------------------------------------------------------
+// BranchRemoval: flags of a vertex whose row starts at b and has `deg`
+// entries: bit0 branch (deg >= 3); bit1 / bit2 entry 0 / 1 kept (neither end
+// is a branch vertex).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t vertex_flags(const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ col, int32_t b,
+                                                 int32_t deg) {
+  if (deg >= 3) return 1u;
+  uint32_t f = 0;
+  if (deg > 0) {
+    const int32_t u0 = col[b];
+    if (row_ptr[u0 + 1] - row_ptr[u0] < 3) f |= 2;
+    if (deg == 2) {
+      const int32_t u1 = col[b + 1];
+      if (row_ptr[u1 + 1] - row_ptr[u1] < 3) f |= 4;
+    }
+  }
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// ConnectedComponent: union-find with min-id roots
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x) {
+  while (true) {
+    int32_t p = ld_relaxed(P + x);
+    if (p == x) return x;
+    int32_t gp = ld_relaxed(P + p);
+    if (gp == p) return p;
+    st_relaxed(P + x, gp);  // path halving: gp is an ancestor of x
+    x = gp;
+  }
+}
+
+__device__ __forceinline__ void uf_union(int32_t *P, int32_t a, int32_t b) {
+  a = uf_find(P, a);
+  b = uf_find(P, b);
+  while (a != b) {
+    if (a < b) {
+      int32_t old = atomicCAS(P + b, b, a);  // link the larger root under the smaller
+      if (old == b) return;
+      b = old;
+    } else {
+      int32_t old = atomicCAS(P + a, a, b);
+      if (old == a) return;
+      a = old;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GreedyPartitioning: sort + LPT on one workgroup
+// ---------------------------------------------------------------------------
+constexpr int kLptBlock = 1024;
+constexpr int kSortCapLds = 8192;  // components sorted in LDS
+constexpr int kBinCapLds = 2048;   // bins kept in LDS
+
+__device__ __forceinline__ int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+template <typename K>
+__device__ __forceinline__ void bitonic_sort(K *a, int N2) {
+  for (int k = 2; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          K x = a[i], y = a[ixj];
+          bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// number of elements of the sorted array a[0..len) that are < x
+__device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int len, uint64_t x) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Bin keys are (load << 16) | bin: ascending key order is ascending
+// (load, bin), i.e. the least loaded bin with the lowest index first.
+constexpr int kBinBits = 16;
+
+__device__ __forceinline__ void lpt_body(int nc, int P, const int32_t *__restrict__ comp_size,
+                                         uint64_t *keys, int32_t *bin_of, uint64_t *binA,
+                                         uint64_t *binB, int32_t *__restrict__ comp_bin,
+                                         int32_t *__restrict__ comp_rank,
+                                         int32_t *__restrict__ comp_start,
+                                         uint64_t *__restrict__ bin_load) {
+  __shared__ uint64_t win[kWave];
+  __shared__ int32_t sh_scan[kLptBlock / kWave + 1];
+  const int tid = threadIdx.x;
+  const int N2 = next_pow2(nc > 0 ? nc : 1);
+
+  // 1. sort by (size desc, label asc); components are indexed in label order
+  for (int i = tid; i < N2; i += blockDim.x)
+    keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)comp_size[i]) << 32) | (uint32_t)i
+                     : ~0ull;
+  for (int b = tid; b < P; b += blockDim.x) binA[b] = (uint64_t)b;  // load 0, sorted
+  __syncthreads();
+  bitonic_sort(keys, N2);
+
+  // 2. LPT.  The bins are kept sorted by (load, bin).  A window holds the W
+  // least loaded bins in the lanes of wave 0 (sorted across lanes): each
+  // component goes to lane 0's bin, whose new key is then re-inserted by
+  // ballot + shift.  Within W steps of a window only its W bins can be the
+  // minimum (step t picks a bin of initial rank <= t), so after W steps the
+  // window is merged back into the sorted bin list.
+  const int W = P < kWave ? P : kWave;
+  const bool single_window = P <= kWave;
+  int i0 = 0;
+  while (i0 < nc) {
+    const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
+    if (tid < kWave) {
+      const int l = tid;
+      uint64_t key = l < W ? binA[l] : ~0ull;
+      for (int base = 0; base < T; base += kWave) {
+        const int cnt = T - base < kWave ? T - base : kWave;
+        const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
+        for (int t = 0; t < cnt; ++t) {
+          const uint64_t it = __shfl(item, t);
+          const uint32_t c = (uint32_t)it;
+          const uint64_t q = 0xFFFFFFFFu - (uint32_t)(it >> 32);
+          const uint64_t k0 = __shfl(key, 0);
+          if (l == 0) bin_of[c] = (int32_t)(k0 & ((1u << kBinBits) - 1));
+          const uint64_t nk = k0 + (q << kBinBits);
+          const int p = __popcll(__ballot(key < nk)) - 1;  // lanes 1.. below nk
+          const uint64_t nxt = __shfl_down(key, 1);
+          key = l < p ? nxt : (l == p ? nk : key);
+        }
+      }
+      if (l < W) win[l] = key;
+    }
+    __syncthreads();
+    if (single_window) {
+      if (tid < W) binA[tid] = win[tid];
+    } else {
+      // merge the window (sorted) with binA[W..P) (sorted) into binB
+      for (int idx = tid; idx < P; idx += blockDim.x) {
+        uint64_t x;
+        int pos;
+        if (idx < W) {
+          x = win[idx];
+          pos = idx + lower_bound_u64(binA + W, P - W, x);
+        } else {
+          x = binA[idx];
+          pos = (idx - W) + lower_bound_u64(win, W, x);
+        }
+        binB[pos] = x;
+      }
+      __syncthreads();
+      uint64_t *t = binA;
+      binA = binB;
+      binB = t;
+    }
+    __syncthreads();
+    i0 += T;
+  }
+  for (int b = tid; b < P; b += blockDim.x) {
+    const uint64_t k = binA[b];
+    bin_load[k & ((1u << kBinBits) - 1)] = k >> kBinBits;
+  }
+
+  // 3. (bin, label) order and read offsets
+  for (int i = tid; i < N2; i += blockDim.x)
+    keys[i] = i < nc ? ((uint64_t)(uint32_t)bin_of[i] << 32) | (uint32_t)i : ~0ull;
+  __syncthreads();
+  bitonic_sort(keys, N2);
+  for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
+  int carry = 0;
+  for (int base = 0; base < nc; base += kLptBlock) {
+    const int i = base + tid;
+    const uint32_t c = i < nc ? (uint32_t)keys[i] : 0u;
+    const int32_t sz = i < nc ? comp_size[c] : 0;
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, kLptBlock>(sz, sh_scan, &tot);
+    if (i < nc) {
+      comp_start[c] = carry + ex;
+      comp_rank[c] = i;
+    }
+    carry += tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// InducedSubgraph: sort one component's block of reads by id (local numbers
+// follow (bin, label, id)); one workgroup of kIndBlock threads
+// ---------------------------------------------------------------------------
+constexpr int kIndBlock = 256;
+constexpr int kIndLocalCap = 1024;
+
+__device__ __forceinline__ void sort_component_block(int q, int st, const int32_t *__restrict__ tmp,
+                                                     int32_t *__restrict__ perm,
+                                                     int32_t *__restrict__ lidx, int32_t *a) {
+  if (q <= kIndLocalCap) {
+    int N2 = 1;
+    while (N2 < q) N2 <<= 1;
+    for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? tmp[st + i] : 0x7FFFFFFF;
+    __syncthreads();
+    for (int k = 2; k <= N2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < N2; i += kIndBlock) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const int32_t x = a[i], y = a[ixj];
+            if ((x > y) == ((i & k) == 0)) {
+              a[i] = y;
+              a[ixj] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < q; i += kIndBlock) {
+      const int32_t v = a[i];
+      perm[st + i] = v;
+      lidx[v] = st + i;
+    }
+  } else {
+    // large component: the rank of a read is the number of smaller ids in
+    // its block (ids are distinct)
+    for (int i = threadIdx.x; i < q; i += kIndBlock) {
+      const int32_t x = tmp[st + i];
+      int r = 0;
+      for (int t = 0; t < q; ++t) r += tmp[st + t] < x;
+      perm[st + r] = x;
+      lidx[x] = st + r;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// LocalAssembly: chain walk of one component, packed base access
+// ---------------------------------------------------------------------------
+constexpr int kWalkBlock = 256;
+constexpr int kWalkCap = 1024;               // reads per component handled in LDS
+constexpr int kRaysPerThread = 2 * kWalkCap / kWalkBlock;
+
+struct WalkArrays {
+  int32_t *nb;     // [2q] local neighbour of slot k of read i (-1: none / cut)
+  int32_t *eid;    // [2q] entry index in S of that slot
+  int32_t *nxt;    // [2q] ray successor
+  int32_t *dist;   // [2q] ray length
+  int32_t *endv;   // [2q] ray end
+};
+
+template <bool kLds>
+__device__ __forceinline__ void walk_component(
+    int c, int q, int st, WalkArrays w, const cg_graph &g, const cg_parts &parts,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ loc_row_ptr,
+    const int32_t *__restrict__ loc_col, const int32_t *__restrict__ loc_eid,
+    const cg_contigs &out, const Scratch &s, int32_t *sh_small, uint32_t *sh_scan) {
+  const int tid = threadIdx.x;
+  __shared__ int s_start, s_cyc, s_sej;
+  __shared__ uint64_t s_carry;
+  if (tid == 0) {
+    s_start = 0x7FFFFFFF;
+    s_cyc = 0;
+    s_sej = 0;
+    s_carry = 0;
+  }
+  // 1. local rows of the component's block
+  for (int i = tid; i < q; i += kWalkBlock) {
+    const int a = loc_row_ptr[st + i], b = loc_row_ptr[st + i + 1];
+    const int deg = b - a;
+    w.nb[2 * i] = deg >= 1 ? loc_col[a] - st : -1;
+    w.nb[2 * i + 1] = deg >= 2 ? loc_col[a + 1] - st : -1;
+    w.eid[2 * i] = deg >= 1 ? loc_eid[a] : -1;
+    w.eid[2 * i + 1] = deg >= 2 ? loc_eid[a + 1] : -1;
+  }
+  __syncthreads();
+  // 2. start: the first read of local degree 1 (the smaller-id root, since
+  // the block is in id order); a cycle starts at its first read and loses
+  // the edge to the larger-numbered neighbour of it
+  for (int i = tid; i < q; i += kWalkBlock)
+    if ((w.nb[2 * i] >= 0) != (w.nb[2 * i + 1] >= 0)) atomicMin(&s_start, i);
+  __syncthreads();
+  if (tid == 0) {
+    if (s_start == 0x7FFFFFFF) {
+      s_start = 0;
+      if (q > 1) {
+        s_cyc = 1;
+        const int x = w.nb[0], y = w.nb[1];
+        const int t = x > y ? x : y;  // closing neighbour
+        if (x > y) w.nb[0] = -1; else w.nb[1] = -1;
+        if (w.nb[2 * t] == 0) w.nb[2 * t] = -1; else w.nb[2 * t + 1] = -1;
+      }
+    }
+  }
+  __syncthreads();
+  const int s0 = s_start;
+  // 3. rays (i, k): leave read i through slot k.  A ray jumps along the
+  // chain; after ceil(log2 q) doublings it knows the chain end it reaches and
+  // how many steps away that end is.
+  for (int r = tid; r < 2 * q; r += kWalkBlock) {
+    const int y = w.nb[r];
+    if (y < 0) {
+      w.nxt[r] = -1;
+      w.dist[r] = 0;
+      w.endv[r] = -1;
+    } else {
+      const int i = r >> 1;
+      const int k2 = w.nb[2 * y] == i ? 1 : 0;  // y's slot that does not lead back
+      const int z = w.nb[2 * y + k2];
+      w.nxt[r] = z >= 0 ? 2 * y + k2 : -1;
+      w.dist[r] = 1;
+      w.endv[r] = y;
+    }
+  }
+  __syncthreads();
+  for (int span = 1; span < q; span <<= 1) {
+    if (kLds) {
+      int rn[kRaysPerThread], rd[kRaysPerThread], re[kRaysPerThread];
+#pragma unroll
+      for (int u = 0; u < kRaysPerThread; ++u) {
+        const int r = tid + u * kWalkBlock;
+        rn[u] = -2;
+        if (r < 2 * q) {
+          const int x = w.nxt[r];
+          if (x >= 0) {
+            rn[u] = w.nxt[x];
+            rd[u] = w.dist[r] + w.dist[x];
+            re[u] = w.endv[x];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kRaysPerThread; ++u) {
+        const int r = tid + u * kWalkBlock;
+        if (rn[u] != -2) {
+          w.nxt[r] = rn[u];
+          w.dist[r] = rd[u];
+          w.endv[r] = re[u];
+        }
+      }
+      __syncthreads();
+    } else {
+      // large component (global arrays): ray r's successor x is only
+      // rewritten by its own owner, so read all then write all in two passes
+      // with the new values parked in the endv/dist of the high half
+      for (int r = tid; r < 2 * q; r += kWalkBlock) {
+        const int x = w.nxt[r];
+        if (x >= 0) {
+          // encode the update next to the ray: (new nxt, new dist, new end)
+          w.nxt[2 * q + r] = w.nxt[x];
+          w.dist[2 * q + r] = w.dist[r] + w.dist[x];
+          w.endv[2 * q + r] = w.endv[x];
+        } else {
+          w.nxt[2 * q + r] = -2;
+        }
+      }
+      __syncthreads();
+      for (int r = tid; r < 2 * q; r += kWalkBlock) {
+        const int x = w.nxt[2 * q + r];
+        if (x != -2) {
+          w.nxt[r] = x;
+          w.dist[r] = w.dist[2 * q + r];
+          w.endv[r] = w.endv[2 * q + r];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // 4. rank, predecessor, successor, orientation and piece of every read
+  int32_t *R_vid = out.layout_vid + st;
+  uint8_t *R_rev = out.layout_rev + st;
+  uint32_t *R_len = s.piece_len + st;
+  const int rank_c = parts.comp_rank[c];
+  for (int i = tid; i < q; i += kWalkBlock) {
+    int rank = 0, pred = -1, succ = -1, succ_e = -1;
+    if (i == s0) {
+      if (w.nb[2 * i] >= 0) { succ = w.nb[2 * i]; succ_e = w.eid[2 * i]; }
+      else if (w.nb[2 * i + 1] >= 0) { succ = w.nb[2 * i + 1]; succ_e = w.eid[2 * i + 1]; }
+    } else {
+      for (int k = 0; k < 2; ++k) {
+        if (w.nb[2 * i + k] >= 0 && w.endv[2 * i + k] == s0) {
+          rank = w.dist[2 * i + k];
+          pred = w.nb[2 * i + k];
+          const int o = 1 - k;
+          if (w.nb[2 * i + o] >= 0) { succ = w.nb[2 * i + o]; succ_e = w.eid[2 * i + o]; }
+        }
+      }
+    }
+    const int32_t v = perm[st + i];
+    int orient;
+    if (i == s0) {
+      orient = succ_e >= 0 ? (g.strand[succ_e] & 1) : 0;
+    } else if (pred >= 0) {
+      // the entry pred -> i, read in pred's row
+      const int pe = w.nb[2 * pred] == i ? w.eid[2 * pred] : w.eid[2 * pred + 1];
+      orient = (g.strand[pe] >> 1) & 1;
+    } else {
+      orient = 0;  // unreachable for a chain: every read but the start has a predecessor
+    }
+    uint32_t plen = g.read_len[v];
+    if (succ_e >= 0) {
+      plen -= g.ovl[succ_e];
+      if ((int)(g.strand[succ_e] & 1) != orient) s_sej = 1;
+    }
+    R_vid[rank] = v;
+    R_rev[rank] = (uint8_t)orient;
+    R_len[rank] = plen;
+    s.lay_contig[st + rank] = rank_c;
+    (void)succ;
+  }
+  __syncthreads();
+  // 5. piece offsets in walk order
+  for (int base = 0; base < q; base += kWalkBlock) {
+    const int i = base + tid;
+    const uint32_t x = i < q ? R_len[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t, kWalkBlock>(x, sh_scan, &tot);
+    if (i < q) s.piece_off[st + i] = s_carry + ex;
+    __syncthreads();
+    if (tid == 0) s_carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out.label[rank_c] = parts.comp_label[c];
+    out.bin[rank_c] = parts.comp_bin[c];
+    out.start[rank_c] = perm[st + s0];
+    out.n_reads[rank_c] = q;
+    out.len[rank_c] = s_carry;
+    out.cflags[rank_c] = (q == 1 ? CG_CONTIG_SINGLE : 0u) | (s_cyc ? CG_CONTIG_CIRCULAR : 0u) |
+                         (s_sej ? CG_CONTIG_SAME_END_JOIN : 0u);
+    out.layout_off[rank_c] = st;
+  }
+  (void)sh_small;
+  __syncthreads();
+}
+
+// k bases (1..16) starting at base index b of the store, LSB first; words
+// past the end of the store read as zero
+__device__ __forceinline__ uint32_t fetch_bases(const uint32_t *__restrict__ seq, uint64_t nwords,
+                                                uint64_t b, int k) {
+  const uint64_t wi = b >> 4;
+  const int sh = (int)(b & 15) * 2;
+  uint64_t x = wi < nwords ? seq[wi] : 0u;
+  if (sh + 2 * k > 32 && wi + 1 < nwords) x |= (uint64_t)seq[wi + 1] << 32;
+  x >>= sh;
+  return k == 16 ? (uint32_t)x : (uint32_t)x & ((1u << (2 * k)) - 1u);
+}
+
+// reverse the order of the k low 2-bit fields and complement them
+__device__ __forceinline__ uint32_t revcomp_fields(uint32_t x, int k) {
+  uint32_t y = __builtin_bitreverse32(x);
+  y = ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
+  y >>= 32 - 2 * k;
+  return y ^ (k == 16 ? 0xFFFFFFFFu : ((1u << (2 * k)) - 1u));
+}
+
+// Output words of one piece (Section 4.4: the piece is the part of a read, in
+// its walking orientation, that the contig keeps).  A word belongs to the
+// piece that holds its first base; if the word runs past the piece it takes
+// its remaining bases from the following pieces of the same contig, so every
+// word has exactly one writer.  Lanes lane, lane + stride, ... take the
+// piece's words in turn.
+__device__ __forceinline__ void copy_piece(
+    const uint32_t *__restrict__ seq, uint64_t seq_words, const uint32_t *__restrict__ read_len,
+    const uint64_t *__restrict__ read_off, const int32_t *__restrict__ layout_vid,
+    const uint8_t *__restrict__ layout_rev, const uint64_t *__restrict__ piece_off,
+    const uint32_t *__restrict__ piece_len, const int32_t *__restrict__ lay_contig,
+    const uint64_t *__restrict__ clen, const uint64_t *__restrict__ cbase, int32_t n_e, int32_t p,
+    uint32_t *__restrict__ bases, int lane, int stride) {
+  const int32_t k = lay_contig[p];
+  const uint64_t L = clen[k];
+  const uint64_t cb = cbase[k] >> 4;
+  const uint64_t poff = piece_off[p];
+  const uint32_t plen = piece_len[p];
+  const uint64_t j0 = (poff + 15) >> 4, j1 = (poff + plen + 15) >> 4;
+  for (uint64_t j = j0 + lane; j < j1; j += stride) {
+    uint64_t pos = j << 4;
+    int32_t pp = p;
+    uint64_t o_off = poff;
+    uint32_t o_len = plen;
+    int32_t v = layout_vid[pp];
+    int rev = layout_rev[pp];
+    uint32_t out = 0;
+    int filled = 0;
+    while (filled < 16 && pos < L) {
+      while (pos >= o_off + o_len && pp + 1 < n_e) {  // continue into the next piece
+        o_off += o_len;
+        ++pp;
+        o_len = piece_len[pp];
+        v = layout_vid[pp];
+        rev = layout_rev[pp];
+      }
+      const uint64_t t = pos - o_off;
+      const uint64_t avail = o_off + o_len > pos ? o_off + o_len - pos : 0;
+      int kk = 16 - filled;
+      if (avail < (uint64_t)kk) kk = (int)avail;
+      if (kk <= 0) break;  // only on inconsistent pieces
+      uint32_t x;
+      if (!rev) {
+        x = fetch_bases(seq, seq_words, read_off[v] + t, kk);
+      } else {
+        const uint64_t Lr = read_len[v];
+        x = revcomp_fields(fetch_bases(seq, seq_words, read_off[v] + Lr - t - kk, kk), kk);
+      }
+      out |= x << (2 * filled);
+      filled += kk;
+      pos += kk;
+    }
+    bases[cb + j] = out;
+  }
+}
+
+}  // namespace cg

@@ -140,7 +140,13 @@ struct ScanCtx {
   unsigned long long *status;
   unsigned int *ticket;
   unsigned int *done;
+  unsigned int *error;  // CG_STATUS_* word raised if a look-back gives up
 };
+
+// Polls of a predecessor's status before a look-back gives up (raising
+// CG_STATUS_SCAN_STALLED); far beyond any real wait, it only bounds a wait
+// that would otherwise never end.
+constexpr long long kLookbackSpinLimit = 1ll << 26;
 
 constexpr unsigned long long kFlagAgg = 1ull << 62;
 constexpr unsigned long long kFlagPre = 2ull << 62;
@@ -161,19 +167,27 @@ __device__ __forceinline__ unsigned long long atomic_ld64(unsigned long long *p)
 // Publish the block aggregate, look back, publish the inclusive prefix;
 // returns the exclusive prefix of the block.  Thread 0 only.
 __device__ __forceinline__ unsigned long long lookback_publish(ScanCtx sc, int blk,
-                                                               unsigned long long agg) {
-  if (blk == 0) {
-    __hip_atomic_store(&sc.status[0], kFlagPre | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                                                               unsigned long long agg,
+                                                               int seg_first = 0) {
+  if (blk == seg_first) {
+    __hip_atomic_store(&sc.status[blk], kFlagPre | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
   __hip_atomic_store(&sc.status[blk], kFlagAgg | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  // the segment's first block publishes an inclusive prefix, so the walk
+  // below never leaves the segment
   unsigned long long excl = 0;
   int p = blk - 1;
+  long long spins = 0;
   while (true) {
     unsigned long long s = __hip_atomic_load(&sc.status[p], __ATOMIC_ACQUIRE,
                                              __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long f = s & ~kValMask;
-    if (f == 0) continue;  // predecessor has not published yet (it is running)
+    if (f == 0) {  // predecessor has not published yet (it is running)
+      if (++spins < kLookbackSpinLimit) continue;
+      atomicOr(sc.error, CG_STATUS_SCAN_STALLED);
+      break;
+    }
     excl += s & kValMask;
     if (f == kFlagPre) break;
     --p;
@@ -208,14 +222,16 @@ __device__ __forceinline__ void lookback_finish(ScanCtx sc, int nblocks) {
 // across blocks.  `val` is this thread's item value.  Returns the exclusive
 // prefix; *total receives the sum over all blocks up to and including this
 // one (the grand total in the last block).
+template <int BLOCK = kScanBlock>
 __device__ __forceinline__ unsigned long long lookback_block_scan(ScanCtx sc, int blk,
                                                                   unsigned long long val,
-                                                                  unsigned long long *incl_end) {
-  __shared__ unsigned long long sh[kScanBlock / kWave + 1];
+                                                                  unsigned long long *incl_end,
+                                                                  int seg_first = 0) {
+  __shared__ unsigned long long sh[BLOCK / kWave + 1];
   __shared__ unsigned long long base;
   unsigned long long agg;
-  unsigned long long ex = block_excl_scan<unsigned long long, kScanBlock>(val, sh, &agg);
-  if (threadIdx.x == 0) base = lookback_publish(sc, blk, agg);
+  unsigned long long ex = block_excl_scan<unsigned long long, BLOCK>(val, sh, &agg);
+  if (threadIdx.x == 0) base = lookback_publish(sc, blk, agg, seg_first);
   __syncthreads();
   *incl_end = base + agg;
   return base + ex;
@@ -251,7 +267,8 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
                     const cg_local &local, int32_t P, const cg_contigs &out, hipStream_t st);
 
 inline ScanCtx scan_ctx(cg_ctx *ctx, const Scratch &s) {
-  return ScanCtx{s.scan_status, &ctx->fixed->scan_ticket, &ctx->fixed->scan_done};
+  return ScanCtx{s.scan_status, &ctx->fixed->scan_ticket, &ctx->fixed->scan_done,
+                 &ctx->fixed->status};
 }
 
 inline int scan_blocks(int64_t items) { return (int)((items + kScanBlock - 1) / kScanBlock); }

@@ -9,12 +9,10 @@
 //               (LDS bitonic up to 1024 reads, rank counting above)
 //  k_ind_rows   local CSR rows (look-back scan of kept degrees), columns
 //               renumbered through the local numbers, entry index kept
-#include "cg_internal.h"
+#include "cg_device.h"
 
 namespace cg {
 
-constexpr int kIndBlock = 256;
-constexpr int kIndLocalCap = 1024;
 
 __global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_t *__restrict__ d_n_comp,
                                                          const uint64_t *__restrict__ bin_load,
@@ -63,47 +61,8 @@ __global__ __launch_bounds__(kIndBlock) void k_ind_local(const int32_t *__restri
                                                          int32_t *__restrict__ lidx) {
   __shared__ int32_t a[kIndLocalCap];
   const int nc = *d_n_comp;
-  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
-    const int q = comp_size[c];
-    const int st = comp_start[c];
-    if (q <= kIndLocalCap) {
-      int N2 = 1;
-      while (N2 < q) N2 <<= 1;
-      for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? tmp[st + i] : 0x7FFFFFFF;
-      __syncthreads();
-      for (int k = 2; k <= N2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-          for (int i = threadIdx.x; i < N2; i += kIndBlock) {
-            const int ixj = i ^ j;
-            if (ixj > i) {
-              const int32_t x = a[i], y = a[ixj];
-              if ((x > y) == ((i & k) == 0)) {
-                a[i] = y;
-                a[ixj] = x;
-              }
-            }
-          }
-          __syncthreads();
-        }
-      }
-      for (int i = threadIdx.x; i < q; i += kIndBlock) {
-        const int32_t v = a[i];
-        perm[st + i] = v;
-        lidx[v] = st + i;
-      }
-    } else {
-      // large component: the rank of a read is the number of smaller ids in
-      // its block (ids are distinct)
-      for (int i = threadIdx.x; i < q; i += kIndBlock) {
-        const int32_t x = tmp[st + i];
-        int r = 0;
-        for (int t = 0; t < q; ++t) r += tmp[st + t] < x;
-        perm[st + r] = x;
-        lidx[x] = st + r;
-      }
-    }
-    __syncthreads();
-  }
+  for (int c = blockIdx.x; c < nc; c += gridDim.x)
+    sort_component_block(comp_size[c], comp_start[c], tmp, perm, lidx, a);
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_ind_rows(

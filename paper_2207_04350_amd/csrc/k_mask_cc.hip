@@ -5,7 +5,7 @@
 //
 // Layout in HBM: CSR row_ptr/col of S, one flag byte per vertex (bit0 branch,
 // bit1/bit2 entry 0/1 of the row kept), one int32 label per vertex.
-#include "cg_internal.h"
+#include "cg_device.h"
 
 namespace cg {
 
@@ -28,18 +28,7 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask(int32_t n, const int32_t *_
   const int32_t deg = live ? nxt - b : 0;
   uint32_t f = 0;
   if (live) {
-    if (deg >= 3) {
-      f = 1;
-    } else if (deg > 0) {
-      int32_t u0 = col[b];
-      int32_t du0 = row_ptr[u0 + 1] - row_ptr[u0];
-      if (du0 < 3) f |= 2;
-      if (deg == 2) {
-        int32_t u1 = col[b + 1];
-        int32_t du1 = row_ptr[u1 + 1] - row_ptr[u1];
-        if (du1 < 3) f |= 4;
-      }
-    }
+    f = vertex_flags(row_ptr, col, b, deg);
     flags[v] = (uint8_t)f;
   }
   // counts: ballots per wave, one atomic per wave, last block publishes
@@ -89,33 +78,6 @@ constexpr int kCcBlock = 256;
 __global__ __launch_bounds__(kCcBlock) void k_cc_init(int32_t n, int32_t *__restrict__ label) {
   const int64_t v = (int64_t)blockIdx.x * kCcBlock + threadIdx.x;
   if (v < n) label[v] = (int32_t)v;
-}
-
-__device__ __forceinline__ int32_t uf_find(int32_t *P, int32_t x) {
-  while (true) {
-    int32_t p = ld_relaxed(P + x);
-    if (p == x) return x;
-    int32_t gp = ld_relaxed(P + p);
-    if (gp == p) return p;
-    st_relaxed(P + x, gp);  // path halving: gp is an ancestor of x
-    x = gp;
-  }
-}
-
-__device__ __forceinline__ void uf_union(int32_t *P, int32_t a, int32_t b) {
-  a = uf_find(P, a);
-  b = uf_find(P, b);
-  while (a != b) {
-    if (a < b) {
-      int32_t old = atomicCAS(P + b, b, a);  // link the larger root under the smaller
-      if (old == b) return;
-      b = old;
-    } else {
-      int32_t old = atomicCAS(P + a, a, b);
-      if (old == a) return;
-      a = old;
-    }
-  }
 }
 
 __global__ __launch_bounds__(kCcBlock) void k_cc_hook(int32_t n, const int32_t *__restrict__ row_ptr,

@@ -1,0 +1,137 @@
+"""GPU parity of the batched form: every job of a batch equals the oracle on
+that graph, for every launch shape, eagerly and replayed from a HIP graph."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.parity import mismatches
+from tests.test_gpu_parity import _chain_graph
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2207_04350_amd import cg as _cg
+    _cg.lib()
+    return _cg
+
+
+def _mixed_graphs():
+    rng = np.random.default_rng(17)
+    gs = [synth.adversarial(rng) for _ in range(40)]
+    gs.append(synth.graph_from_edges([], []))                       # empty graph
+    gs.append(synth.config_graph(1))
+    gs += synth.batch_graphs(only=[0, 7, 300])
+    r = np.random.default_rng(5)
+    gs.append(_chain_graph(r, [1500, 40, 2], cycles=[1200, 7]))   # beyond the LDS tiles
+    gs.append(_chain_graph(r, [2] * 2500 + [5] * 30))              # beyond the batch LDS sort
+    return gs
+
+
+def _params(i, g):
+    r = np.random.default_rng(100 + i)
+    P = int(r.integers(1, 9)) if g.n <= 16 else [64, 300, 8, 1024][i % 4]
+    return P, int(r.integers(0, 3)) if g.n <= 16 else 2
+
+
+def _make(cg, graphs, params, **shape):
+    import torch
+    dev = torch.device("cuda")
+    big = max(range(len(graphs)), key=lambda i: cg.footprint(graphs[i].n, graphs[i].m,
+                                                             params[i][0]))
+    ctx = cg.Context.for_graph(graphs[big].n, graphs[big].m, params[big][0])
+    dgs = [cg.DeviceGraph(g, dev) for g in graphs]
+    outs = [cg.Outputs(g.n, P, g.seq_words, dev) for g, (P, _) in zip(graphs, params)]
+    b = cg.Batch(ctx, [(dg, o, P, mr) for dg, o, (P, mr) in zip(dgs, outs, params)], **shape)
+    return ctx, dgs, outs, b
+
+
+def _scrub(outs):
+    for o in outs:
+        for t in (o.flags, o.label, o.comp_label, o.comp_bin, o.comp_start, o.perm,
+                  o.loc_col, o.layout_vid, o.c_len, o.c_base_off, o.bases, o.n_comp,
+                  o.total_words, o.sizes):
+            t.fill_(-1 if t.dtype != __import__("torch").uint8 else 255)
+
+
+def _check_all(cg, graphs, params, outs, wants, tag):
+    for i, (g, o) in enumerate(zip(graphs, outs)):
+        got = cg.to_host(o, g.n)
+        bad = mismatches(got, wants[i])
+        assert bad == [], (tag, i, g.meta.get("name"), bad)
+
+
+def test_batch_mixed_all_shapes(cg):
+    import torch
+    graphs = _mixed_graphs()
+    params = [_params(i, g) for i, g in enumerate(graphs)]
+    wants = [oracle.run(g, P=P, min_reads=mr) for g, (P, mr) in zip(graphs, params)]
+    for shape in (dict(), dict(vertex_tile=512, copy_block=128, persist_blocks=64),
+                  dict(vertex_tile=1024, copy_block=1024, persist_blocks=7),
+                  dict(vertex_tile=256, copy_block=64, persist_blocks=2048)):
+        _say("batch shape", shape, "jobs", len(graphs))
+        ctx, dgs, outs, b = _make(cg, graphs, params, **shape)
+        b.run()
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        _check_all(cg, graphs, params, outs, wants, "eager %s" % shape)
+        # the launch state resets itself: a second run gives the same result
+        _scrub(outs)
+        b.run()
+        torch.cuda.synchronize()
+        _check_all(cg, graphs, params, outs, wants, "rerun %s" % shape)
+        b.close()
+        ctx.close()
+
+
+def test_batch_graph_replay(cg):
+    import torch
+    graphs = _mixed_graphs()[30:]
+    params = [_params(i, g) for i, g in enumerate(graphs)]
+    wants = [oracle.run(g, P=P, min_reads=mr) for g, (P, mr) in zip(graphs, params)]
+    ctx, dgs, outs, b = _make(cg, graphs, params)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.run(s)
+    s.synchronize()
+    _check_all(cg, graphs, params, outs, wants, "eager")
+    with torch.cuda.stream(s):
+        b.capture(s)
+    for rep in range(4):
+        _say("replay", rep)
+        _scrub(outs)                       # eager work between replays
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            b.launch(s)
+        s.synchronize()
+        assert ctx.status(s) == 0
+        _check_all(cg, graphs, params, outs, wants, "replay %d" % rep)
+    b.close()
+    ctx.close()
+
+
+def test_batch_512_graphs(cg):
+    """The batched workload in full: 512 graphs in one batch."""
+    import torch
+    graphs = synth.batch_graphs(512)
+    params = [(g.meta["P"], 2) for g in graphs]
+    ctx, dgs, outs, b = _make(cg, graphs, params)
+    b.run()
+    torch.cuda.synchronize()
+    for i, g in enumerate(graphs):
+        want = oracle.run(g, P=params[i][0], min_reads=2)
+        bad = mismatches(cg.to_host(outs[i], g.n), want)
+        assert bad == [], (i, bad)
+    b.close()
+    ctx.close()
