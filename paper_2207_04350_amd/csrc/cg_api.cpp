@@ -47,6 +47,7 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
   L.bins = take(8 * (size_t)(2 * (P > 0 ? P : 1)));
   L.aux = take(4 * (size_t)nn);
   L.walk = take(4 * 16 * (size_t)nn);
+  L.estart = take(4 * (size_t)nn);
   L.total = at;
   return L;
 }
@@ -66,6 +67,7 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   s->bins = (uint64_t *)(b + L.bins);
   s->aux = (int32_t *)(b + L.aux);
   s->walk = (int32_t *)(b + L.walk);
+  s->estart = (int32_t *)(b + L.estart);
   return true;
 }
 

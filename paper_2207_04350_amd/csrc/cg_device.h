@@ -106,12 +106,17 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int len, uint6
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
 
-__device__ __forceinline__ void lpt_body(int nc, int P, const int32_t *__restrict__ comp_size,
-                                         uint64_t *keys, int32_t *bin_of, uint64_t *binA,
-                                         uint64_t *binB, int32_t *__restrict__ comp_bin,
-                                         int32_t *__restrict__ comp_rank,
-                                         int32_t *__restrict__ comp_start,
-                                         uint64_t *__restrict__ bin_load) {
+// With comp_kind and comp_estart given, it also writes each component's
+// first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
+// a single read, in (bin, label) order) and returns their total.
+__device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict__ comp_size,
+                                        uint64_t *keys, int32_t *bin_of, uint64_t *binA,
+                                        uint64_t *binB, int32_t *__restrict__ comp_bin,
+                                        int32_t *__restrict__ comp_rank,
+                                        int32_t *__restrict__ comp_start,
+                                        uint64_t *__restrict__ bin_load,
+                                        const uint8_t *__restrict__ comp_kind = nullptr,
+                                        int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
   __shared__ int32_t sh_scan[kLptBlock / kWave + 1];
   const int tid = threadIdx.x;
@@ -192,7 +197,7 @@ __device__ __forceinline__ void lpt_body(int nc, int P, const int32_t *__restric
   __syncthreads();
   bitonic_sort(keys, N2);
   for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
-  int carry = 0;
+  int carry = 0, ecarry = 0;
   for (int base = 0; base < nc; base += kLptBlock) {
     const int i = base + tid;
     const uint32_t c = i < nc ? (uint32_t)keys[i] : 0u;
@@ -204,7 +209,19 @@ __device__ __forceinline__ void lpt_body(int nc, int P, const int32_t *__restric
       comp_rank[c] = i;
     }
     carry += tot;
+    if (comp_estart) {
+      int32_t e2 = 0;
+      if (i < nc) {
+        const uint8_t kd = comp_kind[c];
+        e2 = kd == CG_KIND_PATH ? 2 * (sz - 1) : (kd == CG_KIND_CYCLE ? 2 * sz : 0);
+      }
+      int32_t etot;
+      const int32_t eex = block_excl_scan<int32_t, kLptBlock>(e2, sh_scan, &etot);
+      if (i < nc) comp_estart[c] = ecarry + eex;
+      ecarry += etot;
+    }
   }
+  return ecarry;
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +269,60 @@ __device__ __forceinline__ void sort_component_block(int q, int st, const int32_
       perm[st + r] = x;
       lidx[x] = st + r;
     }
+  }
+  __syncthreads();
+}
+
+// InducedSubgraph for one component, all in one workgroup: sort the block
+// of reads by id, number them st, st+1, ..., and write their local CSR rows
+// (kept entries in row order of S, neighbours renumbered, entry index kept)
+// starting at entry estart.  Neighbours of a kept entry lie in the same
+// component, so their local numbers come from the sorted block itself.
+__device__ __forceinline__ void induce_component(
+    int q, int st, int estart, const int32_t *__restrict__ tmp, const uint8_t *__restrict__ flags,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    int32_t *__restrict__ perm, int32_t *__restrict__ lidx, int32_t *__restrict__ loc_row_ptr,
+    int32_t *__restrict__ loc_col, int32_t *__restrict__ loc_eid, int32_t *a,
+    int32_t *sh_scan) {
+  sort_component_block(q, st, tmp, perm, lidx, a);  // ends with a barrier
+  const bool in_lds = q <= kIndLocalCap;
+  int carry = 0;
+  for (int base = 0; base < q; base += kIndBlock) {
+    const int i = base + threadIdx.x;
+    int32_t v = -1;
+    uint32_t f = 0;
+    if (i < q) {
+      v = in_lds ? a[i] : perm[st + i];
+      f = flags[v];
+    }
+    const int32_t deg = (int32_t)(((f >> 1) & 1) + ((f >> 2) & 1));
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, kIndBlock>(deg, sh_scan, &tot);
+    if (i < q) {
+      int32_t r = estart + carry + ex;
+      loc_row_ptr[st + i] = r;
+      const int32_t b = row_ptr[v];
+      for (int j = 0; j < 2; ++j) {
+        if (!(f & (2u << j))) continue;
+        const int32_t u = col[b + j];
+        int32_t li;
+        if (in_lds) {
+          int lo = 0, hi = q - 1;  // u is in the sorted block
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (a[mid] < u) lo = mid + 1;
+            else hi = mid;
+          }
+          li = st + lo;
+        } else {
+          li = lidx[u];
+        }
+        loc_col[r] = li;
+        loc_eid[r] = b + j;
+        ++r;
+      }
+    }
+    carry += tot;
   }
   __syncthreads();
 }
@@ -530,6 +601,173 @@ __device__ __forceinline__ void copy_piece(
       pos += kk;
     }
     bases[cb + j] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed base copy, 64 bases (four output words) per lane.
+// ---------------------------------------------------------------------------
+typedef unsigned __int128 u128;
+
+// up to 64 bases (k >= 1) starting at base index b of the store, LSB first;
+// words past the end of the store read as zero
+__device__ __forceinline__ u128 fetch_bases64(const CG_GLOBAL uint32_t *__restrict__ seq,
+                                              uint64_t nwords, uint64_t b, int k) {
+  const uint64_t w0 = b >> 4;
+  const int sh = (int)(b & 15) * 2;
+  const int nw = (sh + 2 * k + 31) >> 5;  // words touched, 1..5
+  uint32_t w[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w[i] = (i < nw && w0 + i < nwords) ? seq[w0 + i] : 0u;
+  u128 x = (u128)w[0] | ((u128)w[1] << 32) | ((u128)w[2] << 64) | ((u128)w[3] << 96);
+  x >>= sh;
+  if (sh) x |= (u128)w[4] << (128 - sh);
+  if (k < 64) x &= ((u128)1 << (2 * k)) - 1;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t rev_fields32(uint32_t v) {
+  const uint32_t y = __builtin_bitreverse32(v);
+  return ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
+}
+
+// reverse the order of the k low 2-bit fields of x and complement them
+__device__ __forceinline__ u128 revcomp_fields64(u128 x, int k) {
+  u128 y = (u128)rev_fields32((uint32_t)(x >> 96)) | ((u128)rev_fields32((uint32_t)(x >> 64)) << 32) |
+           ((u128)rev_fields32((uint32_t)(x >> 32)) << 64) | ((u128)rev_fields32((uint32_t)x) << 96);
+  y >>= 2 * (64 - k);
+  const u128 mask = k == 64 ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
+  return y ^ mask;
+}
+
+// One piece as the copy needs it.
+struct PieceD {
+  uint64_t src;   // base offset of the piece's read in the store
+  uint64_t poff;  // first base of the piece in its contig
+  uint64_t L;     // contig length
+  uint64_t cb;    // first output word of the contig
+  uint32_t rlen;  // read length
+  uint32_t plen;  // piece length
+  int32_t rev;    // read walked reverse-complemented
+};
+
+struct PieceArrays {
+  const CG_GLOBAL int32_t *lay_contig;
+  const CG_GLOBAL int32_t *layout_vid;
+  const CG_GLOBAL uint8_t *layout_rev;
+  const CG_GLOBAL uint64_t *piece_off;
+  const CG_GLOBAL uint32_t *piece_len;
+  const CG_GLOBAL uint64_t *read_off;
+  const CG_GLOBAL uint32_t *read_len;
+  const CG_GLOBAL uint64_t *clen;
+  const CG_GLOBAL uint64_t *cbase;
+};
+
+__device__ __forceinline__ PieceArrays piece_arrays(const int32_t *lay_contig,
+                                                    const int32_t *layout_vid,
+                                                    const uint8_t *layout_rev,
+                                                    const uint64_t *piece_off,
+                                                    const uint32_t *piece_len,
+                                                    const uint64_t *read_off,
+                                                    const uint32_t *read_len, const uint64_t *clen,
+                                                    const uint64_t *cbase) {
+  return PieceArrays{(const CG_GLOBAL int32_t *)lay_contig,  (const CG_GLOBAL int32_t *)layout_vid,
+                     (const CG_GLOBAL uint8_t *)layout_rev,  (const CG_GLOBAL uint64_t *)piece_off,
+                     (const CG_GLOBAL uint32_t *)piece_len,  (const CG_GLOBAL uint64_t *)read_off,
+                     (const CG_GLOBAL uint32_t *)read_len,   (const CG_GLOBAL uint64_t *)clen,
+                     (const CG_GLOBAL uint64_t *)cbase};
+}
+
+__device__ __forceinline__ PieceD load_piece(const PieceArrays &A, int32_t p) {
+  PieceD d;
+  const int32_t k = A.lay_contig[p];
+  const int32_t v = A.layout_vid[p];
+  d.src = A.read_off[v];
+  d.rlen = A.read_len[v];
+  d.plen = A.piece_len[p];
+  d.poff = A.piece_off[p];
+  d.rev = A.layout_rev[p];
+  d.L = A.clen[k];
+  d.cb = A.cbase[k] >> 4;
+  return d;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int t) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, t);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), t);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ PieceD readlane_piece(const PieceD &d, int t) {
+  PieceD r;
+  r.src = readlane64(d.src, t);
+  r.poff = readlane64(d.poff, t);
+  r.L = readlane64(d.L, t);
+  r.cb = readlane64(d.cb, t);
+  r.rlen = __builtin_amdgcn_readlane(d.rlen, t);
+  r.plen = __builtin_amdgcn_readlane(d.plen, t);
+  r.rev = __builtin_amdgcn_readlane(d.rev, t);
+  return r;
+}
+
+// The output words owned by piece p (those whose first base lies in it),
+// four consecutive words per lane.  A word that runs past the piece takes
+// its remaining bases from the next pieces of the contig: `nxt` (when
+// has_nxt), then pieces loaded from A.
+__device__ __forceinline__ void copy_piece_words(const CG_GLOBAL uint32_t *__restrict__ seq,
+                                                 uint64_t nwords, CG_GLOBAL uint32_t *__restrict__ bases,
+                                                 const PieceD &cur,
+                                                 const PieceD &nxt, bool has_nxt,
+                                                 const PieceArrays &A, int32_t p, int lane) {
+  const uint64_t j0 = (cur.poff + 15) >> 4, j1 = (cur.poff + cur.plen + 15) >> 4;
+  for (uint64_t w4 = j0 + 4 * (uint64_t)lane; w4 < j1; w4 += 4 * kWave) {
+    const int nw = j1 - w4 < 4 ? (int)(j1 - w4) : 4;
+    uint64_t pos = w4 << 4;
+    uint64_t end = (w4 + nw) << 4;
+    if (end > cur.L) end = cur.L;
+    PieceD d = cur;
+    int32_t pp = p;
+    u128 acc = 0;
+    int filled = 0;
+    while (pos < end) {
+      if (pos >= d.poff + d.plen) {  // continue into the next piece
+        const uint64_t at = d.poff + d.plen;
+        d = (pp == p && has_nxt) ? nxt : load_piece(A, pp + 1);
+        d.poff = at;
+        ++pp;
+      }
+      const uint64_t t = pos - d.poff;
+      uint64_t kk = end - pos;
+      if (d.poff + d.plen - pos < kk) kk = d.poff + d.plen - pos;
+      if (kk == 0) break;  // only on inconsistent pieces
+      const int k = (int)kk;
+      const u128 x = d.rev ? revcomp_fields64(fetch_bases64(seq, nwords, d.src + d.rlen - t - k, k), k)
+                           : fetch_bases64(seq, nwords, d.src + t, k);
+      acc |= x << (2 * filled);
+      filled += k;
+      pos += kk;
+    }
+    CG_GLOBAL uint32_t *o = bases + cur.cb + w4;
+    for (int i = 0; i < nw; ++i) o[i] = (uint32_t)(acc >> (32 * i));
+  }
+}
+
+// One wave copies the chunk of (up to) 64 consecutive pieces starting at
+// piece c0 of a graph with n_e pieces: lanes gather the chunk's descriptors
+// once, then the wave writes the words of piece after piece.  c0 and n_e
+// are wave-uniform.
+__device__ __forceinline__ void copy_chunk(const uint32_t *seq_, uint64_t nwords, uint32_t *bases_,
+                                           const PieceArrays &A, int32_t c0, int32_t n_e, int lane) {
+  const CG_GLOBAL uint32_t *seq = (const CG_GLOBAL uint32_t *)seq_;
+  CG_GLOBAL uint32_t *bases = (CG_GLOBAL uint32_t *)bases_;
+  PieceD my{};
+  if (c0 + lane < n_e) my = load_piece(A, c0 + lane);
+  const int cnt = n_e - c0 < kWave ? n_e - c0 : kWave;
+  for (int t = 0; t < cnt; ++t) {
+    const PieceD cur = readlane_piece(my, t);
+    const bool has_nxt = t + 1 < cnt;
+    const PieceD nxt = has_nxt ? readlane_piece(my, t + 1) : cur;
+    copy_piece_words(seq, nwords, bases, cur, nxt, has_nxt, A, c0 + t, lane);
   }
 }
 

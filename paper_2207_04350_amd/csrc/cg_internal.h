@@ -41,6 +41,7 @@ struct Scratch {
   uint64_t *bins;      // [2P] partition fallback: sorted bin keys
   int32_t *aux;        // [n] partition fallback: bin of each component
   int32_t *walk;       // [16n] assemble: chain arrays of components too big for LDS
+  int32_t *estart;     // [n] batched induce: first local CSR entry of each component
 };
 
 }  // namespace cg
@@ -69,7 +70,7 @@ namespace cg {
 // Scratch carving shared by cg_footprint and the calls.
 struct Layout {
   size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
-      total;
+      estart, total;
 };
 Layout layout(int64_t n, int64_t m, int64_t P);
 bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);
@@ -82,6 +83,11 @@ int hip_check(hipError_t e, const char *what);
 // Device utilities
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Device global memory.  Pointers a kernel reads out of a descriptor in
+// memory are generic to the compiler; typing them as global lets it use
+// global (not flat) memory instructions.
+#define CG_GLOBAL __attribute__((address_space(1)))
 
 __device__ __forceinline__ int ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

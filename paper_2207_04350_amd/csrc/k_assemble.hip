@@ -88,9 +88,14 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
                                                          uint32_t *__restrict__ bases) {
   if (*d_total_words > cap_words) return;
   const int32_t n_e = bin_vptr[P];
-  for (int32_t p = blockIdx.x; p < n_e; p += gridDim.x)
-    copy_piece(seq, seq_words, read_len, read_off, layout_vid, layout_rev, piece_off, piece_len,
-               lay_contig, clen, cbase, n_e, p, bases, threadIdx.x, kCopyBlock);
+  const PieceArrays A = piece_arrays(lay_contig, layout_vid, layout_rev, piece_off, piece_len,
+                                     read_off, read_len, clen, cbase);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
+  const int32_t nwv = gridDim.x * (blockDim.x / kWave);
+  const int32_t n_chunks = (n_e + kWave - 1) / kWave;
+  for (int32_t ch = gw; ch < n_chunks; ch += nwv)
+    copy_chunk(seq, seq_words, bases, A, ch * kWave, n_e, lane_id());
 }
 
 int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_parts &parts,
@@ -106,7 +111,7 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
                      s.walk);
   CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,
                      out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
-  const int cgrid = n < 8192 ? n : 8192;
+  const int cgrid = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
   CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
                      g.read_len,
                      g.read_off, local.bin_vptr, P, out.layout_vid, out.layout_rev, s.piece_off,

@@ -3,8 +3,8 @@
 //
 //  vertex passes   each job is cut into tiles of T vertices; a launch covers
 //                  the tiles of every job (tile -> job table)
-//  scans           single-pass look-back scans segmented per job (a job's
-//                  first tile starts from zero)
+//  compaction      reduce-then-scan per job: tiles count, then each tile adds
+//                  up the counts of the tiles before it in its job
 //  component and   persistent grids stride over the batch-wide item ranges
 //  piece passes    (components, pieces) whose per-job bases the last LPT
 //                  workgroup computes on the device
@@ -36,12 +36,11 @@ struct BJob {
 struct BatchDev {
   BJob *jobs;                       // [n_jobs]
   int32_t *tile_job;                // [n_vtiles]
-  unsigned long long *scan_status;  // [n_vtiles]
-  unsigned long long *job_acc;      // [2 n_jobs] branch / kept-entry counts
-  unsigned int *job_ticket;         // [n_jobs]
+  int32_t *tile_cnt;                // [n_vtiles] eligible roots per tile
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
-  unsigned int *counters;           // [8] 0/1 scan ticket/done, 2 LPT ticket
+  int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
+  unsigned int *counters;           // [8] 2: LPT ticket
   Fixed *fixed;
   int32_t n_jobs, n_vtiles;
 };
@@ -58,7 +57,8 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 }
 
 // ---------------------------------------------------------------------------
-// 1. mask + label init + size-counter reset (one thread per vertex)
+// 1. mask + label init + size-counter reset (one thread per vertex); the
+// branch / kept-entry counts are summed later by the job's LPT workgroup
 // ---------------------------------------------------------------------------
 template <int T>
 __global__ __launch_bounds__(T) void kb_mask(BatchDev B) {
@@ -72,32 +72,10 @@ __global__ __launch_bounds__(T) void kb_mask(BatchDev B) {
   int32_t b = v <= n ? row_ptr[v] : 0;
   int32_t nxt = __shfl_down(b, 1);
   if (lane_id() == kWave - 1 && live) nxt = row_ptr[v + 1];
-  uint32_t f = 0;
   if (live) {
-    f = vertex_flags(row_ptr, J.g.col, b, nxt - b);
-    J.flags[v] = (uint8_t)f;
+    J.flags[v] = (uint8_t)vertex_flags(row_ptr, J.g.col, b, nxt - b);
     J.label[v] = (int32_t)v;
     J.parts.label_comp[v] = 0;
-  }
-  const unsigned long long nb = __popcll(__ballot(f & 1));
-  const unsigned long long ml = __popcll(__ballot(f & 2)) + __popcll(__ballot(f & 4));
-  if (lane_id() == 0 && (nb | ml)) {
-    if (nb) atomicAdd(&B.job_acc[2 * j], nb);
-    if (ml) atomicAdd(&B.job_acc[2 * j + 1], ml);
-    __threadfence();
-  }
-  __shared__ int last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(&B.job_ticket[j], 1u) == (unsigned)J.vt_count - 1;
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    J.counts[0] = (int32_t)atomicExch(&B.job_acc[2 * j], 0ull);
-    J.counts[1] = (int32_t)atomicExch(&B.job_acc[2 * j + 1], 0ull);
-    B.job_ticket[j] = 0;
-    __threadfence();
   }
 }
 
@@ -145,35 +123,66 @@ __global__ __launch_bounds__(T) void kb_compress_count(BatchDev B) {
   atomicAdd((uint32_t *)J.parts.label_comp + p, 4u + (degL == 1 ? 1u : 0u));
 }
 
-// 4. eligible components in label order (segmented look-back scan)
+// 4. eligible components in label order, reduce-then-scan: each tile counts
+// its eligible roots, then each tile adds up the counts of the tiles before
+// it in its job (plain loads, no waiting) and scatters
+template <int T>
+__device__ __forceinline__ bool eligible(const BJob &J, int64_t v, uint32_t *c_out) {
+  if (v >= J.g.n) return false;
+  const uint32_t c = (uint32_t)J.parts.label_comp[v];
+  *c_out = c;
+  const uint32_t mr = J.min_reads < 1 ? 1u : (uint32_t)J.min_reads;
+  return (c >> 2) >= mr && !(J.flags[v] & 1);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void kb_tilecount(BatchDev B) {
+  __shared__ int32_t sh[T / kWave];
+  const int t = blockIdx.x;
+  const BJob &J = B.jobs[B.tile_job[t]];
+  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
+  uint32_t c = 0;
+  const bool e = eligible<T>(J, v, &c);
+  const int cnt = __popcll(__ballot(e));
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < T / kWave; ++w) s += sh[w];
+    B.tile_cnt[t] = s;
+  }
+}
+
 template <int T>
 __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
-  const ScanCtx sc{B.scan_status, &B.counters[0], &B.counters[1], &B.fixed->status};
-  const int blk = lookback_ticket(sc);
-  const int j = B.tile_job[blk];
-  const BJob &J = B.jobs[j];
-  const int32_t n = J.g.n;
-  const int64_t v = (int64_t)(blk - J.vt_first) * T + threadIdx.x;
-  int32_t *cnt = J.parts.label_comp;
-  const uint32_t c = v < n ? (uint32_t)cnt[v] : 0u;
-  const uint32_t q = c >> 2;
-  const uint32_t mr = J.min_reads < 1 ? 1u : (uint32_t)J.min_reads;
-  const bool elig = v < n && q >= mr && !(J.flags[v] & 1);
-  unsigned long long incl_end;
-  const unsigned long long ex =
-      lookback_block_scan<T>(sc, blk, elig ? 1ull : 0ull, &incl_end, J.vt_first);
-  if (v < n) {
-    if (elig) {
+  __shared__ int32_t sh[T / kWave + 1];
+  const int t = blockIdx.x;
+  const BJob &J = B.jobs[B.tile_job[t]];
+  int32_t before = 0;
+  for (int i = J.vt_first + (int)threadIdx.x; i < t; i += T) before += B.tile_cnt[i];
+  before = wave_sum(before);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = before;
+  __syncthreads();
+  int32_t base = 0;
+  for (int w = 0; w < T / kWave; ++w) base += sh[w];
+  __syncthreads();
+  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
+  uint32_t c = 0;
+  const bool e = eligible<T>(J, v, &c);
+  int32_t tot;
+  const int32_t ex = base + block_excl_scan<int32_t, T>(e ? 1 : 0, sh, &tot);
+  if (v < J.g.n) {
+    if (e) {
+      const uint32_t q = c >> 2;
       J.parts.comp_label[ex] = (int32_t)v;
       J.parts.comp_size[ex] = (int32_t)q;
       J.parts.comp_kind[ex] = q == 1 ? CG_KIND_SINGLE : ((c & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
-      cnt[v] = (int32_t)ex;
+      J.parts.label_comp[v] = ex;
     } else {
-      cnt[v] = -1;
+      J.parts.label_comp[v] = -1;
     }
   }
-  if (blk == J.vt_first + J.vt_count - 1 && threadIdx.x == 0) *J.parts.d_n_comp = (int32_t)incl_end;
-  lookback_finish(sc, B.n_vtiles);
+  if (t == J.vt_first + J.vt_count - 1 && threadIdx.x == 0) *J.parts.d_n_comp = base + tot;
 }
 
 // 5. LPT per job (one workgroup each), bin offsets, bucket cursors; the last
@@ -190,13 +199,32 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   const BJob &J = B.jobs[j];
   const int P = J.P;
   const int nc = *J.parts.d_n_comp;
+  int m_e;
   if (nc <= kBatchSortCap && P <= kBatchBinCap)
-    lpt_body(nc, P, J.parts.comp_size, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
-             J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load);
+    m_e = lpt_body(nc, P, J.parts.comp_size, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
+                   J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.parts.comp_kind,
+                   J.s.estart);
   else
-    lpt_body(nc, P, J.parts.comp_size, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
-             J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load);
+    m_e = lpt_body(nc, P, J.parts.comp_size, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
+                   J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
+                   J.parts.comp_kind, J.s.estart);
   __syncthreads();
+  // branch vertices and kept entries of the job (BranchRemoval's counts)
+  {
+    int64_t nb = 0, ml = 0;
+    for (int64_t v = threadIdx.x; v < J.g.n; v += kLptBlock) {
+      const uint32_t f = J.flags[v];
+      nb += f & 1;
+      ml += ((f >> 1) & 1) + ((f >> 2) & 1);
+    }
+    int64_t tnb, tml;
+    (void)block_excl_scan<int64_t, kLptBlock>(nb, sh, &tnb);
+    (void)block_excl_scan<int64_t, kLptBlock>(ml, sh, &tml);
+    if (threadIdx.x == 0) {
+      J.counts[0] = (int32_t)tnb;
+      J.counts[1] = (int32_t)tml;
+    }
+  }
   int64_t carry = 0;
   for (int base = 0; base < P; base += kLptBlock) {
     const int b = base + threadIdx.x;
@@ -211,13 +239,15 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   if (threadIdx.x == 0) {
     J.local.bin_vptr[P] = (int32_t)carry;
     J.local.d_sizes[0] = (int32_t)carry;
+    J.local.d_sizes[1] = m_e;
+    J.local.loc_row_ptr[carry] = m_e;
     __threadfence();
     last = atomicAdd(&B.counters[2], 1u) == (unsigned)B.n_jobs - 1;
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
-  int64_t cc = 0, pc = 0;
+  int64_t cc = 0, pc = 0, hc = 0;
   for (int base = 0; base < B.n_jobs; base += kLptBlock) {
     const int i = base + threadIdx.x;
     int64_t xc = 0, xp = 0;
@@ -226,19 +256,24 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
       xc = __hip_atomic_load(K.parts.d_n_comp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       xp = __hip_atomic_load(K.local.bin_vptr + K.P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    int64_t tc, tp;
+    const int64_t xh = (xp + kWave - 1) / kWave;
+    int64_t tc, tp, th;
     const int64_t ec = block_excl_scan<int64_t, kLptBlock>(xc, sh, &tc);
     const int64_t ep = block_excl_scan<int64_t, kLptBlock>(xp, sh, &tp);
+    const int64_t eh = block_excl_scan<int64_t, kLptBlock>(xh, sh, &th);
     if (i < B.n_jobs) {
       B.comp_base[i] = (int32_t)(cc + ec);
       B.piece_base[i] = (int32_t)(pc + ep);
+      B.chunk_base[i] = (int32_t)(hc + eh);
     }
     cc += tc;
     pc += tp;
+    hc += th;
   }
   if (threadIdx.x == 0) {
     B.comp_base[B.n_jobs] = (int32_t)cc;
     B.piece_base[B.n_jobs] = (int32_t)pc;
+    B.chunk_base[B.n_jobs] = (int32_t)hc;
     B.counters[2] = 0;
     __threadfence();
   }
@@ -257,55 +292,23 @@ __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   J.s.tmp[J.parts.comp_start[c] + slot] = (int32_t)v;
 }
 
-// 7. sort each component's block by id (persistent, all components)
-__global__ __launch_bounds__(kIndBlock) void kb_local(BatchDev B) {
+// 7. induced subgraph of each component: sorted local numbers and local CSR
+// rows (persistent over all components of the batch)
+__global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t a[kIndLocalCap];
+  __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
   const int32_t total = B.comp_base[B.n_jobs];
   for (int32_t i = blockIdx.x; i < total; i += gridDim.x) {
     const int j = job_of(B.comp_base, B.n_jobs, i);
     const BJob &J = B.jobs[j];
     const int c = i - B.comp_base[j];
-    sort_component_block(J.parts.comp_size[c], J.parts.comp_start[c], J.s.tmp, J.local.perm,
-                         J.s.lidx, a);
+    induce_component(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c], J.s.tmp, J.flags,
+                     J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx, J.local.loc_row_ptr,
+                     J.local.loc_col, J.local.loc_eid, a, sh_scan);
   }
 }
 
-// 8. local CSR rows (segmented look-back scan over each job's 0..n_e)
-template <int T>
-__global__ __launch_bounds__(T) void kb_rows(BatchDev B) {
-  const ScanCtx sc{B.scan_status, &B.counters[0], &B.counters[1], &B.fixed->status};
-  const int blk = lookback_ticket(sc);
-  const BJob &J = B.jobs[B.tile_job[blk]];
-  const int64_t i = (int64_t)(blk - J.vt_first) * T + threadIdx.x;
-  const int32_t n_e = J.local.bin_vptr[J.P];
-  int32_t v = -1;
-  uint32_t f = 0;
-  if (i < n_e) {
-    v = J.local.perm[i];
-    f = J.flags[v];
-  }
-  const uint32_t deg = ((f >> 1) & 1) + ((f >> 2) & 1);
-  unsigned long long incl_end;
-  const unsigned long long ex = lookback_block_scan<T>(sc, blk, deg, &incl_end, J.vt_first);
-  if (i <= n_e) J.local.loc_row_ptr[i] = (int32_t)ex;
-  if (i == n_e) J.local.d_sizes[1] = (int32_t)ex;
-  if (i < n_e && deg) {
-    const int32_t b = J.g.row_ptr[v];
-    int32_t t = (int32_t)ex;
-    if (f & 2) {
-      J.local.loc_col[t] = J.s.lidx[J.g.col[b]];
-      J.local.loc_eid[t] = b;
-      ++t;
-    }
-    if (f & 4) {
-      J.local.loc_col[t] = J.s.lidx[J.g.col[b + 1]];
-      J.local.loc_eid[t] = b + 1;
-    }
-  }
-  lookback_finish(sc, B.n_vtiles);
-}
-
-// 9. walk every component (persistent, all components)
+// 8. walk every component (persistent, all components)
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap];
@@ -332,7 +335,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   }
 }
 
-// 10. contig word offsets per job
+// 9. contig word offsets per job
 __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   const BJob &J = B.jobs[blockIdx.x];
@@ -352,21 +355,25 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   }
 }
 
-// 11. packed copy: one wave per piece, persistent over every piece
+// 10. packed copy: waves take chunks of 64 consecutive pieces of the batch
+__device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
+  return piece_arrays(J.s.lay_contig, J.out.layout_vid, J.out.layout_rev, J.s.piece_off,
+                      J.s.piece_len, J.g.read_off, J.g.read_len, J.out.len, J.out.base_off);
+}
+
 __global__ void kb_copy(BatchDev B) {
-  const int wpb = blockDim.x / kWave;
-  const int32_t gw = blockIdx.x * wpb + threadIdx.x / kWave;
-  const int32_t nw = gridDim.x * wpb;
-  const int32_t total = B.piece_base[B.n_jobs];
-  for (int32_t it = gw; it < total; it += nw) {
-    const int j = job_of(B.piece_base, B.n_jobs, it);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
+  const int32_t nwv = gridDim.x * (blockDim.x / kWave);
+  const int32_t total = B.chunk_base[B.n_jobs];
+  for (int32_t ch = gw; ch < total; ch += nwv) {
+    // a chunk never spans two jobs, so the job is the same for the whole wave
+    const int j = job_of(B.chunk_base, B.n_jobs, ch);
     const BJob &J = B.jobs[j];
     if (*J.out.d_total_words > J.out.cap_words) continue;
-    const int32_t p = it - B.piece_base[j];
     const int32_t n_e = B.piece_base[j + 1] - B.piece_base[j];
-    copy_piece(J.g.seq, J.g.seq_words, J.g.read_len, J.g.read_off, J.out.layout_vid,
-               J.out.layout_rev, J.s.piece_off, J.s.piece_len, J.s.lay_contig, J.out.len,
-               J.out.base_off, n_e, p, J.out.bases, lane_id(), kWave);
+    copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), (ch - B.chunk_base[j]) * kWave,
+               n_e, lane_id());
   }
 }
 
@@ -411,12 +418,13 @@ static int check_job(const cg_job &J, int i) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 template <int T>
-static void launch_vertex_phases_a(cg_batch *b, hipStream_t st) {
+static void launch_vertex_phases(cg_batch *b, hipStream_t st) {
   cg_ctx *ctx = b->ctx;
   const BatchDev &B = b->dev;
   CG_LAUNCH(ctx, kb_mask<T>, dim3(b->n_vtiles), dim3(T), st, B);
   CG_LAUNCH(ctx, kb_hook<T>, dim3(b->n_vtiles), dim3(T), st, B);
   CG_LAUNCH(ctx, kb_compress_count<T>, dim3(b->n_vtiles), dim3(T), st, B);
+  CG_LAUNCH(ctx, kb_tilecount<T>, dim3(b->n_vtiles), dim3(T), st, B);
   CG_LAUNCH(ctx, kb_compact<T>, dim3(b->n_vtiles), dim3(T), st, B);
 }
 
@@ -424,12 +432,6 @@ template <int T>
 static void launch_vertex_fill(cg_batch *b, hipStream_t st) {
   cg_ctx *ctx = b->ctx;
   CG_LAUNCH(ctx, kb_fill<T>, dim3(b->n_vtiles), dim3(T), st, b->dev);
-}
-
-template <int T>
-static void launch_vertex_rows(cg_batch *b, hipStream_t st) {
-  cg_ctx *ctx = b->ctx;
-  CG_LAUNCH(ctx, kb_rows<T>, dim3(b->n_vtiles), dim3(T), st, b->dev);
 }
 
 extern "C" {
@@ -479,11 +481,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     nv += cnt;
   }
   const size_t o_tiles = take(sizeof(int32_t) * nv);
-  const size_t o_status = take(sizeof(unsigned long long) * nv);
-  const size_t o_acc = take(sizeof(unsigned long long) * 2 * n_jobs);
-  const size_t o_ticket = take(sizeof(unsigned int) * n_jobs);
+  const size_t o_tcnt = take(sizeof(int32_t) * nv);
   const size_t o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
+  const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_counters = take(sizeof(unsigned int) * 8);
   for (int i = 0; i < n_jobs; ++i)
     job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
@@ -536,11 +537,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   BatchDev &d = b->dev;
   d.jobs = (BJob *)(b->mem + o_jobs);
   d.tile_job = (int32_t *)(b->mem + o_tiles);
-  d.scan_status = (unsigned long long *)(b->mem + o_status);
-  d.job_acc = (unsigned long long *)(b->mem + o_acc);
-  d.job_ticket = (unsigned int *)(b->mem + o_ticket);
+  d.tile_cnt = (int32_t *)(b->mem + o_tcnt);
   d.comp_base = (int32_t *)(b->mem + o_cbase);
   d.piece_base = (int32_t *)(b->mem + o_pbase);
+  d.chunk_base = (int32_t *)(b->mem + o_hbase);
   d.counters = (unsigned int *)(b->mem + o_counters);
   d.fixed = ctx->fixed;
   d.n_jobs = n_jobs;
@@ -556,17 +556,14 @@ int cg_batch_run(cg_batch *b, void *stream) {
   const BatchDev &B = b->dev;
   const int T = b->prm.vertex_tile;
   const int PB = b->prm.persist_blocks;
-  if (T == 256) launch_vertex_phases_a<256>(b, st);
-  else if (T == 512) launch_vertex_phases_a<512>(b, st);
-  else launch_vertex_phases_a<1024>(b, st);
+  if (T == 256) launch_vertex_phases<256>(b, st);
+  else if (T == 512) launch_vertex_phases<512>(b, st);
+  else launch_vertex_phases<1024>(b, st);
   CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kLptBlock), st, B);
   if (T == 256) launch_vertex_fill<256>(b, st);
   else if (T == 512) launch_vertex_fill<512>(b, st);
   else launch_vertex_fill<1024>(b, st);
-  CG_LAUNCH(ctx, kb_local, dim3(PB), dim3(kIndBlock), st, B);
-  if (T == 256) launch_vertex_rows<256>(b, st);
-  else if (T == 512) launch_vertex_rows<512>(b, st);
-  else launch_vertex_rows<1024>(b, st);
+  CG_LAUNCH(ctx, kb_induce, dim3(PB), dim3(kIndBlock), st, B);
   CG_LAUNCH(ctx, kb_walk, dim3(PB), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);
   CG_LAUNCH(ctx, kb_copy, dim3(PB), dim3(b->prm.copy_block), st, B);

@@ -65,10 +65,28 @@ def _scrub(outs):
             t.fill_(-1 if t.dtype != __import__("torch").uint8 else 255)
 
 
+def _explain_bases(got, want):
+    a, b = got["contigs"]["bases"], want["contigs"]["bases"]
+    if a.shape != b.shape:
+        return "shape %s vs %s" % (a.shape, b.shape)
+    d = np.nonzero(a != b)[0]
+    c = want["contigs"]
+    words = (c["base_off"] // 16).astype(np.int64)
+    out = []
+    for w in d[:4]:
+        k = int(np.searchsorted(words, w, side="right") - 1)
+        out.append("word %d got %08x want %08x contig %d (len %d, words %d..%d, n_reads %d)" % (
+            w, a[w], b[w], k, c["len"][k], words[k], words[k] + (int(c["len"][k]) + 15) // 16,
+            c["n_reads"][k]))
+    return "%d words differ; " % len(d) + "; ".join(out)
+
+
 def _check_all(cg, graphs, params, outs, wants, tag):
     for i, (g, o) in enumerate(zip(graphs, outs)):
         got = cg.to_host(o, g.n)
         bad = mismatches(got, wants[i])
+        if bad == ["contigs.bases"]:
+            _say("bases mismatch", tag, i, _explain_bases(got, wants[i]))
         assert bad == [], (tag, i, g.meta.get("name"), bad)
 
 
@@ -131,7 +149,10 @@ def test_batch_512_graphs(cg):
     torch.cuda.synchronize()
     for i, g in enumerate(graphs):
         want = oracle.run(g, P=params[i][0], min_reads=2)
-        bad = mismatches(cg.to_host(outs[i], g.n), want)
+        got = cg.to_host(outs[i], g.n)
+        bad = mismatches(got, want)
+        if bad == ["contigs.bases"]:
+            _say("bases mismatch job", i, _explain_bases(got, want))
         assert bad == [], (i, bad)
     b.close()
     ctx.close()
