@@ -205,9 +205,9 @@ def main():
             "components": pick(lambda k: k.startswith("k_cc") or k.startswith("kb_hook")
                                or k.startswith("kb_compress")),
             "partition": pick(lambda k: k.startswith("k_part") or k.startswith("kb_compact")
-                              or k == "kb_lpt"),
+                              or k.startswith("kb_tilecount") or k == "kb_lpt"),
             "induce": pick(lambda k: k.startswith("k_ind") or k.startswith("kb_fill")
-                           or k == "kb_local" or k.startswith("kb_rows")),
+                           or k == "kb_induce"),
             "assemble": pick(lambda k: k.startswith("k_asm") or k in ("kb_walk", "kb_offsets",
                                                                        "kb_copy")),
         }
@@ -226,9 +226,11 @@ def main():
     dom = max(batch_kern, key=lambda k: batch_kern[k][1])
     dom_launches, dom_ms = batch_kern[dom]
     dom_avg_us = 1e3 * dom_ms / dom_launches
-    dom_map = {"kb_copy": "k_asm_copy", "kb_walk": "k_asm_walk", "kb_lpt": "k_part_lpt",
-               "kb_local": "k_ind_local"}
-    dom_bytes = algo_bytes(dom_map.get(dom, kname(dom)), st)
+    dom_map = {"kb_copy": ["k_asm_copy"], "kb_walk": ["k_asm_walk"], "kb_lpt": ["k_part_lpt"],
+               "kb_induce": ["k_ind_local", "k_ind_rows"], "kb_hook<T>": ["k_cc_hook"],
+               "kb_compress_count<T>": ["k_cc_compress"], "kb_fill<T>": ["k_ind_fill"],
+               "kb_mask<T>": ["k_mask"], "kb_offsets": ["k_asm_offsets"]}
+    dom_bytes = sum(algo_bytes(k, st) or 0 for k in dom_map.get(dom, [kname(dom)]))
     dom_bytes_per_launch = (dom_bytes or 0) / dom_launches
     achieved = dom_bytes_per_launch / (dom_avg_us * 1e-6) / 1e9
 

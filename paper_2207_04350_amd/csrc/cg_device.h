@@ -752,22 +752,142 @@ __device__ __forceinline__ void copy_piece_words(const CG_GLOBAL uint32_t *__res
   }
 }
 
-// One wave copies the chunk of (up to) 64 consecutive pieces starting at
-// piece c0 of a graph with n_e pieces: lanes gather the chunk's descriptors
-// once, then the wave writes the words of piece after piece.  c0 and n_e
-// are wave-uniform.
+// Five consecutive store words starting at word w (indices clamped into the
+// store, so the loads are unconditional and issue back to back).
+__device__ __forceinline__ void load5(const CG_GLOBAL uint32_t *__restrict__ seq, uint64_t nwords,
+                                      uint64_t w, uint32_t *o) {
+  const uint64_t last = nwords - 1;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) o[i] = seq[w + i < last ? w + i : last];
+}
+
+// k (1..64) bases from five loaded words whose first base sits at field sh
+// of word 0; reverse-complemented when rev.
+__device__ __forceinline__ u128 extract_bases(const uint32_t *w, int sh, int k, bool rev) {
+  u128 x = (u128)w[0] | ((u128)w[1] << 32) | ((u128)w[2] << 64) | ((u128)w[3] << 96);
+  x >>= 2 * sh;
+  if (sh) x |= (u128)w[4] << (128 - 2 * sh);
+  if (k < 64) x &= ((u128)1 << (2 * k)) - 1;
+  return rev ? revcomp_fields64(x, k) : x;
+}
+
+// First stored base of the k bases that start t bases into a piece, in the
+// piece's walking orientation (a reversed piece is read backwards).
+__device__ __forceinline__ uint64_t piece_src(const PieceD &d, uint64_t t, int k) {
+  return d.rev ? d.src + d.rlen - t - (uint64_t)k : d.src + t;
+}
+
+// One wave copies the chunk of cnt (<= 64) consecutive pieces starting at
+// piece c0 of a graph with n_e pieces.  Lane l gathers piece c0+l's
+// descriptor; the chunk's four-word groups (each owned by the piece holding
+// its first base) are then spread over the lanes, 64 groups per step, so
+// lanes of one step work on different pieces.  A group that runs into the
+// next piece loads both parts before combining them; a group that spans
+// three or more pieces (only with very short pieces) takes a slower loop.
+// c0, cnt and n_e are wave-uniform; all lanes run every step.
 __device__ __forceinline__ void copy_chunk(const uint32_t *seq_, uint64_t nwords, uint32_t *bases_,
-                                           const PieceArrays &A, int32_t c0, int32_t n_e, int lane) {
+                                           const PieceArrays &A, int32_t c0, int cnt,
+                                           int32_t n_e, int lane) {
   const CG_GLOBAL uint32_t *seq = (const CG_GLOBAL uint32_t *)seq_;
   CG_GLOBAL uint32_t *bases = (CG_GLOBAL uint32_t *)bases_;
-  PieceD my{};
-  if (c0 + lane < n_e) my = load_piece(A, c0 + lane);
-  const int cnt = n_e - c0 < kWave ? n_e - c0 : kWave;
-  for (int t = 0; t < cnt; ++t) {
-    const PieceD cur = readlane_piece(my, t);
-    const bool has_nxt = t + 1 < cnt;
-    const PieceD nxt = has_nxt ? readlane_piece(my, t + 1) : cur;
-    copy_piece_words(seq, nwords, bases, cur, nxt, has_nxt, A, c0 + t, lane);
+  PieceD my{}, nx{};
+  uint32_t ng = 0;
+  if (lane < cnt) {
+    my = load_piece(A, c0 + lane);
+    const uint64_t j0 = (my.poff + 15) >> 4, j1 = (my.poff + my.plen + 15) >> 4;
+    ng = (uint32_t)((j1 - j0 + 3) >> 2);
+  }
+  // the next piece of every lane's piece: from the next lane, or loaded for
+  // the chunk's last piece
+  {
+    PieceD up;
+    up.src = __shfl_down(my.src, 1);
+    up.poff = __shfl_down(my.poff, 1);
+    up.L = __shfl_down(my.L, 1);
+    up.cb = __shfl_down(my.cb, 1);
+    up.rlen = __shfl_down(my.rlen, 1);
+    up.plen = __shfl_down(my.plen, 1);
+    up.rev = __shfl_down(my.rev, 1);
+    nx = up;
+    if (lane == cnt - 1 && c0 + lane + 1 < n_e) nx = load_piece(A, c0 + lane + 1);
+  }
+  const uint32_t gincl = wave_incl_scan(ng);
+  const uint32_t gstart = gincl - ng;
+  const uint32_t G = __shfl(gincl, kWave - 1);
+  for (uint32_t base = 0; base < G; base += kWave) {
+    const uint32_t g = base + lane;
+    // piece of group g: the last lane t with gstart[t] <= g (gstart is
+    // non-decreasing and equals G from lane cnt on, so t < cnt when g < G).
+    // Six fixed steps, every lane shuffling in every step: a shuffle must
+    // never run with part of the wave switched off.
+    int t = 0;
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1) {
+      const uint32_t sm = __shfl(gstart, t + step);
+      if (sm <= g) t += step;
+    }
+    PieceD d;
+    d.src = __shfl(my.src, t);
+    d.poff = __shfl(my.poff, t);
+    d.L = __shfl(my.L, t);
+    d.cb = __shfl(my.cb, t);
+    d.rlen = __shfl(my.rlen, t);
+    d.plen = __shfl(my.plen, t);
+    d.rev = __shfl(my.rev, t);
+    PieceD e;
+    e.src = __shfl(nx.src, t);
+    e.rlen = __shfl(nx.rlen, t);
+    e.plen = __shfl(nx.plen, t);
+    e.rev = __shfl(nx.rev, t);
+    const uint32_t gs = __shfl(gstart, t);
+    if (g >= G) continue;
+    const uint64_t j0 = (d.poff + 15) >> 4, j1 = (d.poff + d.plen + 15) >> 4;
+    const uint64_t w4 = j0 + 4 * (uint64_t)(g - gs);
+    const int nw = j1 - w4 < 4 ? (int)(j1 - w4) : 4;
+    const uint64_t pos = w4 << 4;
+    uint64_t end = (w4 + nw) << 4;
+    if (end > d.L) end = d.L;
+    const uint64_t pend = d.poff + d.plen;  // first base after this piece
+    // part 1 from this piece, part 2 from the next one
+    const int k1 = (int)((end < pend ? end : pend) - pos);
+    uint64_t e_end = end;
+    const uint64_t nend = pend + e.plen;
+    if (e_end > nend) e_end = nend;
+    const int k2 = end > pend ? (int)(e_end - pend) : 0;
+    uint32_t w1[5], w2[5];
+    const uint64_t b1 = piece_src(d, pos - d.poff, k1);
+    load5(seq, nwords, b1 >> 4, w1);
+    uint64_t b2 = 0;
+    if (k2 > 0) {
+      e.poff = pend;
+      b2 = piece_src(e, 0, k2);
+      load5(seq, nwords, b2 >> 4, w2);
+    }
+    u128 acc = extract_bases(w1, (int)(b1 & 15), k1, d.rev != 0);
+    int filled = k1;
+    if (k2 > 0) {
+      acc |= extract_bases(w2, (int)(b2 & 15), k2, e.rev != 0) << (2 * filled);
+      filled += k2;
+      // a third and further pieces (pieces shorter than a group)
+      uint64_t at = nend;
+      int32_t pp = c0 + t + 1;
+      while (at < end && pp + 1 < n_e) {
+        const PieceD f = load_piece(A, pp + 1);
+        ++pp;
+        uint64_t fe = at + f.plen;
+        if (fe > end) fe = end;
+        const int k3 = (int)(fe - at);
+        if (k3 <= 0) break;
+        uint32_t w3[5];
+        const uint64_t b3 = piece_src(f, 0, k3);
+        load5(seq, nwords, b3 >> 4, w3);
+        acc |= extract_bases(w3, (int)(b3 & 15), k3, f.rev != 0) << (2 * filled);
+        filled += k3;
+        at = fe;
+      }
+    }
+    CG_GLOBAL uint32_t *o = bases + d.cb + w4;
+    for (int i = 0; i < nw; ++i) o[i] = (uint32_t)(acc >> (32 * i));
   }
 }
 

@@ -93,9 +93,16 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
-  const int32_t n_chunks = (n_e + kWave - 1) / kWave;
-  for (int32_t ch = gw; ch < n_chunks; ch += nwv)
-    copy_chunk(seq, seq_words, bases, A, ch * kWave, n_e, lane_id());
+  // pieces per wave: enough chunks to give every wave of the grid work,
+  // at most one piece per lane
+  int32_t C = (n_e + nwv - 1) / nwv;
+  C = C < 1 ? 1 : (C > kWave ? kWave : C);
+  const int32_t n_chunks = (n_e + C - 1) / C;
+  for (int32_t ch = gw; ch < n_chunks; ch += nwv) {
+    const int32_t c0 = ch * C;
+    const int cnt = n_e - c0 < C ? n_e - c0 : C;
+    copy_chunk(seq, seq_words, bases, A, c0, cnt, n_e, lane_id());
+  }
 }
 
 int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_parts &parts,
@@ -111,7 +118,8 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
                      s.walk);
   CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,
                      out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
-  const int cgrid = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+  // about eight pieces per wave, so a small graph still spreads over the chip
+  const int cgrid = (n + 31) / 32 < 8192 ? (n + 31) / 32 : 8192;
   CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
                      g.read_len,
                      g.read_off, local.bin_vptr, P, out.layout_vid, out.layout_rev, s.piece_off,

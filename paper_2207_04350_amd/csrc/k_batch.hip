@@ -372,8 +372,9 @@ __global__ void kb_copy(BatchDev B) {
     const BJob &J = B.jobs[j];
     if (*J.out.d_total_words > J.out.cap_words) continue;
     const int32_t n_e = B.piece_base[j + 1] - B.piece_base[j];
-    copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), (ch - B.chunk_base[j]) * kWave,
-               n_e, lane_id());
+    const int32_t c0 = (ch - B.chunk_base[j]) * kWave;
+    const int cnt = n_e - c0 < kWave ? n_e - c0 : kWave;
+    copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), c0, cnt, n_e, lane_id());
   }
 }
 
