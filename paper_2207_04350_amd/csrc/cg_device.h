@@ -58,6 +58,56 @@ __device__ __forceinline__ void uf_union(int32_t *P, int32_t a, int32_t b) {
   }
 }
 
+// Tagged forest: each entry holds (tag << 32) | parent, and an entry whose
+// tag is not the current run's stands for "no parent".  Bumping the tag
+// between runs therefore resets the whole forest without touching it, so
+// the hooks can run in the same pass that finds the kept entries.  Parents
+// are always smaller than their children, so every root is its tree's
+// minimum id.
+__device__ __forceinline__ uint64_t ld_relaxed64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t tf_entry(uint32_t tag, int32_t parent) {
+  return ((uint64_t)tag << 32) | (uint32_t)parent;
+}
+__device__ __forceinline__ int32_t tf_parent(const uint64_t *F, uint32_t tag, int32_t x) {
+  const uint64_t e = ld_relaxed64(F + x);
+  return (uint32_t)(e >> 32) == tag ? (int32_t)(uint32_t)e : x;
+}
+
+__device__ __forceinline__ int32_t tf_find(uint64_t *F, uint32_t tag, int32_t x) {
+  while (true) {
+    const int32_t p = tf_parent(F, tag, x);
+    if (p == x) return x;
+    const int32_t gp = tf_parent(F, tag, p);
+    if (gp == p) return p;
+    st_relaxed64(F + x, tf_entry(tag, gp));  // path halving
+    x = gp;
+  }
+}
+
+__device__ __forceinline__ void tf_union(uint64_t *F, uint32_t tag, int32_t a, int32_t b) {
+  a = tf_find(F, tag, a);
+  b = tf_find(F, tag, b);
+  while (a != b) {
+    const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    const uint64_t e = ld_relaxed64(F + hi);
+    if ((uint32_t)(e >> 32) == tag) {  // hi got a parent meanwhile: climb
+      const int32_t p = (int32_t)(uint32_t)e;
+      if (a == hi) a = p;
+      else b = p;
+      continue;
+    }
+    // link the larger root under the smaller one
+    if (atomicCAS((unsigned long long *)(F + hi), (unsigned long long)e,
+                  (unsigned long long)tf_entry(tag, lo)) == e)
+      return;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // GreedyPartitioning: sort + LPT on one workgroup
 // ---------------------------------------------------------------------------

@@ -9,10 +9,13 @@
 //  piece passes    (components, pieces) whose per-job bases the last LPT
 //                  workgroup computes on the device
 //
-// Every counter a launch uses is reset by the launch itself, so the eleven
-// launches can be captured once into a HIP graph and replayed.
+// Every counter a launch uses is reset by the launch itself, and the
+// union-find forest is reset by bumping its tag, so the ten launches can be
+// captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <new>
 #include <vector>
 
@@ -30,8 +33,28 @@ struct BJob {
   cg_local local;
   cg_contigs out;
   Scratch s;
+  uint64_t *forest;            // [n] tagged union-find forest (batch-owned, never reused)
+  int4 *conn_list;             // [n] reads with kept entries: (id, kept neighbours or -1, flags),
+                               // each mask tile's reads packed at the start of its slice
+  int32_t *conn_map;           // [n] slot of a read in conn_list
   int32_t vt_first, vt_count;  // the job's vertex tiles (covering 0..n)
+  int32_t mt_first, mt_count;  // the job's mask tiles
 };
+
+// One tile of the mask pass: kMaskTile consecutive reads of one job.
+struct MaskTile {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  uint8_t *flags;
+  int32_t *label;
+  int32_t *label_comp;
+  int4 *conn_list;
+  int32_t *conn_map;
+  int32_t *conn_cnt;  // this tile's number of listed reads
+  int32_t n, v0;
+};
+constexpr int kMaskThreads = 256;
+constexpr int kMaskTile = 4 * kMaskThreads;
 
 struct BatchDev {
   BJob *jobs;                       // [n_jobs]
@@ -40,9 +63,12 @@ struct BatchDev {
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
-  unsigned int *counters;           // [8] 2: LPT ticket
+  unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
+  int32_t *mt_conn;                 // [n_mtiles] listed reads of each mask tile
+  const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
+  const MaskTile *mtiles;           // [n_mtiles]
   Fixed *fixed;
-  int32_t n_jobs, n_vtiles;
+  int32_t n_jobs, n_vtiles, n_mtiles;
 };
 
 // index j with base[j] <= i < base[j+1] (base ascending, base[0] = 0)
@@ -57,73 +83,248 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 }
 
 // ---------------------------------------------------------------------------
-// 1. mask + label init + size-counter reset (one thread per vertex); the
-// branch / kept-entry counts are summed later by the job's LPT workgroup
+// 1. mask (four reads per thread, 16-byte loads and stores): branch flags and
+// kept entries, labels and size counters initialised (a read without kept
+// entries is its own one-read component: label = id, count final here), and
+// every read with kept entries listed with its kept neighbours.  The branch /
+// kept-entry counts are summed later by the job's LPT workgroup.
 // ---------------------------------------------------------------------------
-template <int T>
-__global__ __launch_bounds__(T) void kb_mask(BatchDev B) {
-  const int t = blockIdx.x;
-  const int j = B.tile_job[t];
-  const BJob &J = B.jobs[j];
-  const int32_t n = J.g.n;
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  const bool live = v < n;
-  const int32_t *row_ptr = J.g.row_ptr;
-  int32_t b = v <= n ? row_ptr[v] : 0;
-  int32_t nxt = __shfl_down(b, 1);
-  if (lane_id() == kWave - 1 && live) nxt = row_ptr[v + 1];
-  if (live) {
-    J.flags[v] = (uint8_t)vertex_flags(row_ptr, J.g.col, b, nxt - b);
-    J.label[v] = (int32_t)v;
-    J.parts.label_comp[v] = 0;
-  }
+__device__ __forceinline__ uint32_t forest_tag(const BatchDev &B) { return B.counters[3] + 1u; }
+
+__device__ __forceinline__ int32_t deg_of(const int32_t *__restrict__ row_ptr, int32_t u) {
+  return row_ptr[u + 1] - row_ptr[u];
 }
 
-// 2. union-find hooks
-template <int T>
-__global__ __launch_bounds__(T) void kb_hook(BatchDev B) {
-  const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  if (v >= J.g.n) return;
-  const uint32_t f = J.flags[v];
-  if (!(f & 6)) return;
-  const int32_t b = J.g.row_ptr[v];
-  if (f & 2) {
-    const int32_t u = J.g.col[b];
-    if (u > v) uf_union(J.label, (int32_t)v, u);
+__global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__restrict__ tiles) {
+  const MaskTile D = tiles[blockIdx.x];
+  const int32_t n = D.n;
+  const int32_t v0 = D.v0 + 4 * (int32_t)threadIdx.x;
+  const int lane = lane_id();
+  // row_ptr[v0 .. v0+4]
+  int4 a = make_int4(0, 0, 0, 0);
+  if (v0 + 3 <= n) {
+    a = *(const int4 *)(D.row_ptr + v0);
+  } else if (v0 <= n) {
+    a.x = D.row_ptr[v0];
+    if (v0 + 1 <= n) a.y = D.row_ptr[v0 + 1];
+    if (v0 + 2 <= n) a.z = D.row_ptr[v0 + 2];
   }
-  if (f & 4) {
-    const int32_t u = J.g.col[b + 1];
-    if (u > v) uf_union(J.label, (int32_t)v, u);
+  int32_t e4 = __shfl_down(a.x, 1);
+  if (lane == kWave - 1 && v0 + 4 <= n) e4 = D.row_ptr[v0 + 4];
+  const int32_t rp[5] = {a.x, a.y, a.z, a.w, e4};
+  // kept entries: the rows of degree 1-2 read their columns, then the
+  // neighbours' degrees (all loads issued before any is used)
+  int32_t u0[4], u1[4], dg[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const bool live = v0 + i < n;
+    dg[i] = live ? rp[i + 1] - rp[i] : 0;
+    u0[i] = (dg[i] == 1 || dg[i] == 2) ? D.col[rp[i]] : -1;
+    u1[i] = dg[i] == 2 ? D.col[rp[i] + 1] : -1;
   }
-}
-
-// 3. compression to the root (= smallest id) and component size counters:
-// a vertex's own root is final once all hooks are done, so it can count
-// itself without waiting for the other vertices
-template <int T>
-__global__ __launch_bounds__(T) void kb_compress_count(BatchDev B) {
-  const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  if (v >= J.g.n) return;
-  int32_t *label = J.label;
-  int32_t p = ld_relaxed(label + v);
-  if (p != (int32_t)v) {
-    while (true) {
-      const int32_t q = ld_relaxed(label + p);
-      if (q == p) break;
-      p = q;
+  int32_t d0[4], d1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    d0[i] = u0[i] >= 0 ? deg_of(D.row_ptr, u0[i]) : 3;
+    d1[i] = u1[i] >= 0 ? deg_of(D.row_ptr, u1[i]) : 3;
+  }
+  uint32_t f[4];
+  int cnt = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    f[i] = dg[i] >= 3 ? 1u : ((d0[i] < 3 ? 2u : 0u) | (d1[i] < 3 ? 4u : 0u));
+    cnt += (f[i] & 6) ? 1 : 0;
+  }
+  if (v0 + 3 < n) {
+    *(uint32_t *)(D.flags + v0) = f[0] | (f[1] << 8) | (f[2] << 16) | (f[3] << 24);
+    *(int4 *)(D.label + v0) = make_int4(v0, v0 + 1, v0 + 2, v0 + 3);
+    *(int4 *)(D.label_comp + v0) = make_int4((f[0] & 6) ? 0 : 4, (f[1] & 6) ? 0 : 4,
+                                             (f[2] & 6) ? 0 : 4, (f[3] & 6) ? 0 : 4);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (v0 + i < n) {
+        D.flags[v0 + i] = (uint8_t)f[i];
+        D.label[v0 + i] = v0 + i;
+        D.label_comp[v0 + i] = (f[i] & 6) ? 0 : 4;
+      }
+  }
+  // the tile's reads with kept entries, packed in id order at the start of
+  // the tile's slice of the list (a block scan, no global atomics)
+  __shared__ int32_t sh[kMaskThreads / kWave + 1];
+  int32_t tot;
+  int32_t pos = D.v0 + block_excl_scan<int32_t, kMaskThreads>(cnt, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (f[i] & 6) {
+      D.conn_list[pos] = make_int4(v0 + i, (f[i] & 2) ? u0[i] : -1, (f[i] & 4) ? u1[i] : -1,
+                                   (int32_t)f[i]);
+      D.conn_map[v0 + i] = pos;
+      ++pos;
     }
-    st_relaxed(label + v, p);
-  }
-  const uint32_t f = J.flags[v];
-  const uint32_t degL = ((f >> 1) & 1) + ((f >> 2) & 1);
-  atomicAdd((uint32_t *)J.parts.label_comp + p, 4u + (degL == 1 ? 1u : 0u));
+  if (threadIdx.x == 0) *D.conn_cnt = tot;
 }
 
-// 4. eligible components in label order, reduce-then-scan: each tile counts
+// 2. components of each job in one workgroup: union-find in LDS over the
+// job's listed reads (roots = smallest read id, exact per-root counts, no
+// global atomics).  A listed read's local number is its tile's offset plus
+// its slot in the tile, which orders local numbers like read ids, so the
+// smaller local number is the smaller id.  A job with more listed reads (or
+// mask tiles) than LDS holds uses the tagged global forest instead.  Largest
+// jobs are dispatched first.
+constexpr int kCcBlock = 1024;
+constexpr int kCcCap = 16384;
+constexpr int kCcPer = kCcCap / kCcBlock;
+constexpr int kCcTileCap = 1024;
+
+__device__ __forceinline__ int lds_find(int32_t *par, int x) {
+  volatile int32_t *vp = par;
+  while (true) {
+    const int p = vp[x];
+    if (p == x) return x;
+    const int gp = vp[p];
+    if (gp == p) return p;
+    vp[x] = gp;  // path halving: gp is an ancestor of x
+    x = gp;
+  }
+}
+
+// link the larger root under the smaller one
+__device__ __forceinline__ void lds_union(int32_t *par, int a, int b) {
+  while (true) {
+    a = lds_find(par, a);
+    b = lds_find(par, b);
+    if (a == b) return;
+    const int hi = a > b ? a : b;
+    const int lo = a > b ? b : a;
+    if (atomicCAS(par + hi, hi, lo) == hi) return;
+  }
+}
+
+__global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
+  __shared__ int32_t s_par[kCcCap];
+  __shared__ int32_t s_pref[kCcTileCap + 1];
+  __shared__ int32_t sh[kCcBlock / kWave + 1];
+  const int j = B.job_order[blockIdx.x];
+  const BJob &J = B.jobs[j];
+  const int nt = J.mt_count;
+  if (nt == 0) return;
+  const int32_t *cnt = B.mt_conn + J.mt_first;
+  const int4 *__restrict__ list = J.conn_list;
+  const int32_t *__restrict__ map = J.conn_map;
+  const int tid = threadIdx.x;
+  if (nt <= kCcTileCap) {
+    int32_t tot;
+    const int32_t c = tid < nt ? cnt[tid] : 0;
+    const int32_t ex = block_excl_scan<int32_t, kCcBlock>(c, sh, &tot);
+    if (tid < nt) s_pref[tid] = ex;
+    if (tid == 0) s_pref[nt] = tot;
+    __syncthreads();
+    const int32_t L = tot;
+    if (L == 0) return;
+    if (L <= kCcCap) {
+      // slot of local number l: its tile (binary search over s_pref) and rank
+      int32_t id[kCcPer], l0[kCcPer], l1[kCcPer];
+      uint32_t end[kCcPer];
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k) {
+        const int l = tid + k * kCcBlock;
+        id[k] = -1;
+        l0[k] = l1[k] = -1;
+        end[k] = 0;
+        if (l < L) {
+          int lo = 0, hi = nt - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= l) lo = mid;
+            else hi = mid - 1;
+          }
+          const int4 e = list[lo * kMaskTile + (l - s_pref[lo])];
+          id[k] = e.x;
+          end[k] = (((e.w >> 1) & 1) + ((e.w >> 2) & 1)) == 1 ? 1u : 0u;
+          // each kept entry is hooked once, by its larger endpoint
+          if (e.y >= 0 && e.y < e.x) {
+            const int32_t p = map[e.y];
+            l0[k] = s_pref[p / kMaskTile] + p % kMaskTile;
+          }
+          if (e.z >= 0 && e.z < e.x) {
+            const int32_t p = map[e.z];
+            l1[k] = s_pref[p / kMaskTile] + p % kMaskTile;
+          }
+          s_par[l] = l;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k) {
+        const int l = tid + k * kCcBlock;
+        if (l0[k] >= 0) lds_union(s_par, l, l0[k]);
+        if (l1[k] >= 0) lds_union(s_par, l, l1[k]);
+      }
+      __syncthreads();
+      int32_t r[kCcPer];
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k) {
+        const int l = tid + k * kCcBlock;
+        r[k] = l < L ? lds_find(s_par, l) : -1;
+      }
+      __syncthreads();
+      // roots publish their ids, members take them as labels
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k)
+        if (id[k] >= 0 && r[k] == tid + k * kCcBlock) s_par[r[k]] = id[k];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k)
+        if (id[k] >= 0) J.label[id[k]] = s_par[r[k]];
+      __syncthreads();
+      // s_par becomes the per-root counter: 4 per read + 1 per path end
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k)
+        if (id[k] >= 0) s_par[tid + k * kCcBlock] = 0;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k)
+        if (id[k] >= 0) atomicAdd(s_par + r[k], 4 + (int)end[k]);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kCcPer; ++k) {
+        const int l = tid + k * kCcBlock;
+        if (id[k] >= 0 && r[k] == l) J.parts.label_comp[id[k]] = s_par[l];
+      }
+      return;
+    }
+  }
+  // too many reads for LDS: the job's own forest in global memory (only this
+  // workgroup touches it), the list walked tile by tile
+  const uint32_t tag = forest_tag(B);
+  for (int t = 0; t < nt; ++t) {
+    const int32_t c = cnt[t];
+    for (int i = tid; i < c; i += kCcBlock) {
+      const int4 e = list[t * kMaskTile + i];
+      if (e.y >= 0 && e.y < e.x) tf_union(J.forest, tag, e.x, e.y);
+      if (e.z >= 0 && e.z < e.x) tf_union(J.forest, tag, e.x, e.z);
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    const int32_t c = cnt[t];
+    for (int i = tid; i < c; i += kCcBlock) {
+      const int4 e = list[t * kMaskTile + i];
+      int32_t r = e.x;
+      while (true) {
+        const int32_t p = tf_parent(J.forest, tag, r);
+        if (p == r) break;
+        r = p;
+      }
+      J.label[e.x] = r;
+      const uint32_t degL = ((e.w >> 1) & 1) + ((e.w >> 2) & 1);
+      atomicAdd((uint32_t *)J.parts.label_comp + r, 4u + (degL == 1 ? 1u : 0u));
+    }
+  }
+}
+
+// 3. eligible components in label order, reduce-then-scan: each tile counts
 // its eligible roots, then each tile adds up the counts of the tiles before
 // it in its job (plain loads, no waiting) and scatters
 template <int T>
@@ -185,7 +386,7 @@ __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
   if (t == J.vt_first + J.vt_count - 1 && threadIdx.x == 0) *J.parts.d_n_comp = base + tot;
 }
 
-// 5. LPT per job (one workgroup each), bin offsets, bucket cursors; the last
+// 4. LPT per job (one workgroup each), bin offsets, bucket cursors; the last
 // workgroup lays out the batch-wide component and piece item ranges
 constexpr int kBatchSortCap = 2048;
 constexpr int kBatchBinCap = 256;
@@ -275,11 +476,12 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
     B.piece_base[B.n_jobs] = (int32_t)pc;
     B.chunk_base[B.n_jobs] = (int32_t)hc;
     B.counters[2] = 0;
+    B.counters[3] += 1u;  // the next run's forest tag
     __threadfence();
   }
 }
 
-// 6. each eligible read claims a slot in its component's block
+// 5. each eligible read claims a slot in its component's block
 template <int T>
 __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   const int t = blockIdx.x;
@@ -292,7 +494,7 @@ __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   J.s.tmp[J.parts.comp_start[c] + slot] = (int32_t)v;
 }
 
-// 7. induced subgraph of each component: sorted local numbers and local CSR
+// 6. induced subgraph of each component: sorted local numbers and local CSR
 // rows (persistent over all components of the batch)
 __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t a[kIndLocalCap];
@@ -308,7 +510,7 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   }
 }
 
-// 8. walk every component (persistent, all components)
+// 7. walk every component (persistent, all components)
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap];
@@ -335,7 +537,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   }
 }
 
-// 9. contig word offsets per job
+// 8. contig word offsets per job
 __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   const BJob &J = B.jobs[blockIdx.x];
@@ -355,7 +557,7 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   }
 }
 
-// 10. packed copy: waves take chunks of 64 consecutive pieces of the batch
+// 9. packed copy: waves take chunks of 64 consecutive pieces of the batch
 __device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
   return piece_arrays(J.s.lay_contig, J.out.layout_vid, J.out.layout_rev, J.s.piece_off,
                       J.s.piece_len, J.g.read_off, J.g.read_len, J.out.len, J.out.base_off);
@@ -413,6 +615,12 @@ static int check_job(const cg_job &J, int i) {
       !c.cflags || !c.layout_off || !c.layout_vid || !c.layout_rev || !c.d_total_words ||
       (c.cap_words > 0 && !c.bases))
     return set_error(CG_EINVAL, "job %d: a buffer is NULL", i);
+  // the mask pass moves four reads per thread with 16-byte accesses
+  if (((uintptr_t)g.row_ptr & 15) || ((uintptr_t)J.label & 15) || ((uintptr_t)p.label_comp & 15) ||
+      ((uintptr_t)J.flags & 3))
+    return set_error(CG_EINVAL,
+                     "job %d: row_ptr, label and label_comp must be 16-byte aligned and flags "
+                     "4-byte aligned", i);
   return CG_OK;
 }
 
@@ -422,9 +630,6 @@ template <int T>
 static void launch_vertex_phases(cg_batch *b, hipStream_t st) {
   cg_ctx *ctx = b->ctx;
   const BatchDev &B = b->dev;
-  CG_LAUNCH(ctx, kb_mask<T>, dim3(b->n_vtiles), dim3(T), st, B);
-  CG_LAUNCH(ctx, kb_hook<T>, dim3(b->n_vtiles), dim3(T), st, B);
-  CG_LAUNCH(ctx, kb_compress_count<T>, dim3(b->n_vtiles), dim3(T), st, B);
   CG_LAUNCH(ctx, kb_tilecount<T>, dim3(b->n_vtiles), dim3(T), st, B);
   CG_LAUNCH(ctx, kb_compact<T>, dim3(b->n_vtiles), dim3(T), st, B);
 }
@@ -487,8 +692,20 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_counters = take(sizeof(unsigned int) * 8);
-  for (int i = 0; i < n_jobs; ++i)
+  const size_t o_order = take(sizeof(int32_t) * n_jobs);
+  int32_t n_mt = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    hj[i].mt_first = n_mt;
+    hj[i].mt_count = (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
+    n_mt += hj[i].mt_count;
+  }
+  const size_t o_mtiles = take(sizeof(MaskTile) * (n_mt > 0 ? n_mt : 1));
+  const size_t o_mtconn = take(sizeof(int32_t) * (n_mt > 0 ? n_mt : 1));
+  std::vector<size_t> forest_off(n_jobs);
+  for (int i = 0; i < n_jobs; ++i) {
     job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
+    forest_off[i] = take(sizeof(uint64_t) * (size_t)(jobs[i].g.n > 0 ? jobs[i].g.n : 1));
+  }
   cg_batch *b = new (std::nothrow) cg_batch();
   if (!b) return set_error(CG_EINVAL, "out of host memory");
   b->ctx = ctx;
@@ -522,7 +739,32 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
       view.scratch = b->mem + job_off[i];
       view.scratch_bytes = layout(J.g.n, J.g.m, J.P).total;
       carve(&view, J.g.n, J.g.m, J.P, &h.s);
+      // zeroed above: tag 0 never matches a run's tag (runs use 1, 2, ...)
+      h.forest = (uint64_t *)(b->mem + forest_off[i]);
+      // the list and its index live in scratch that later steps reuse
+      h.conn_list = (int4 *)h.s.walk;
+      h.conn_map = h.s.lidx;
     }
+    std::vector<MaskTile> mt;
+    mt.reserve(n_mt);
+    int32_t *d_mtconn = (int32_t *)(b->mem + o_mtconn);
+    for (int i = 0; i < n_jobs; ++i)
+      for (int32_t v0 = 0; v0 < jobs[i].g.n; v0 += kMaskTile)
+        mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, jobs[i].flags, jobs[i].label,
+                              jobs[i].parts.label_comp, hj[i].conn_list, hj[i].conn_map,
+                              d_mtconn + (int32_t)mt.size(), jobs[i].g.n, v0});
+    std::vector<int32_t> order(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return jobs[a].g.n > jobs[c].g.n; });
+    if (n_mt > 0)
+      rc = hip_check(hipMemcpy(b->mem + o_mtiles, mt.data(), sizeof(MaskTile) * n_mt,
+                               hipMemcpyHostToDevice), "hipMemcpy(mask tiles)");
+    if (!rc)
+      rc = hip_check(hipMemcpy(b->mem + o_order, order.data(), sizeof(int32_t) * n_jobs,
+                               hipMemcpyHostToDevice), "hipMemcpy(job order)");
+  }
+  if (!rc) {
     rc = hip_check(hipMemcpy(b->mem + o_jobs, hj.data(), sizeof(BJob) * n_jobs,
                              hipMemcpyHostToDevice), "hipMemcpy(jobs)");
   }
@@ -543,6 +785,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
   d.counters = (unsigned int *)(b->mem + o_counters);
+  d.mt_conn = (int32_t *)(b->mem + o_mtconn);
+  d.job_order = (const int32_t *)(b->mem + o_order);
+  d.mtiles = (const MaskTile *)(b->mem + o_mtiles);
+  d.n_mtiles = n_mt;
   d.fixed = ctx->fixed;
   d.n_jobs = n_jobs;
   d.n_vtiles = nv;
@@ -557,6 +803,9 @@ int cg_batch_run(cg_batch *b, void *stream) {
   const BatchDev &B = b->dev;
   const int T = b->prm.vertex_tile;
   const int PB = b->prm.persist_blocks;
+  if (B.n_mtiles > 0)
+    CG_LAUNCH(ctx, kb_mask_list, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
+  CG_LAUNCH(ctx, kb_cc_local, dim3(b->n_jobs), dim3(kCcBlock), st, B);
   if (T == 256) launch_vertex_phases<256>(b, st);
   else if (T == 512) launch_vertex_phases<512>(b, st);
   else launch_vertex_phases<1024>(b, st);

@@ -36,6 +36,7 @@ def _mixed_graphs():
     r = np.random.default_rng(5)
     gs.append(_chain_graph(r, [1500, 40, 2], cycles=[1200, 7]))   # beyond the LDS tiles
     gs.append(_chain_graph(r, [2] * 2500 + [5] * 30))              # beyond the batch LDS sort
+    gs.append(_chain_graph(r, [3000, 2900, 2400, 3]))              # beyond the LDS components
     return gs
 
 
