@@ -279,7 +279,7 @@ def main():
         "mask_cc": {"ms_per_step": maskcc_ms, "algorithmic_bytes": maskcc_bytes,
                     "hbm_frac": maskcc_bytes / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
                     if maskcc_ms else None,
-                    "kernels": "kb_mask_list + kb_cc_local"},
+                    "kernels": "kb_mask_list + kb_cc_local (the latter also builds the component table and groups members)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": dom_avg_us, "bytes_per_launch": dom_bytes_per_launch,

@@ -48,6 +48,7 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
   L.aux = take(4 * (size_t)nn);
   L.walk = take(4 * 16 * (size_t)nn);
   L.estart = take(4 * (size_t)nn);
+  L.memb = take(4 * (size_t)nn);
   L.total = at;
   return L;
 }
@@ -68,6 +69,7 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   s->aux = (int32_t *)(b + L.aux);
   s->walk = (int32_t *)(b + L.walk);
   s->estart = (int32_t *)(b + L.estart);
+  s->memb = (int32_t *)(b + L.memb);
   return true;
 }
 

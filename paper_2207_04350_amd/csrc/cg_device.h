@@ -281,13 +281,14 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
 constexpr int kIndBlock = 256;
 constexpr int kIndLocalCap = 1024;
 
-__device__ __forceinline__ void sort_component_block(int q, int st, const int32_t *__restrict__ tmp,
+__device__ __forceinline__ void sort_component_block(int q, int st,
+                                                     const int32_t *__restrict__ members,
                                                      int32_t *__restrict__ perm,
                                                      int32_t *__restrict__ lidx, int32_t *a) {
   if (q <= kIndLocalCap) {
     int N2 = 1;
     while (N2 < q) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? tmp[st + i] : 0x7FFFFFFF;
+    for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? members[i] : 0x7FFFFFFF;
     __syncthreads();
     for (int k = 2; k <= N2; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
@@ -313,9 +314,9 @@ __device__ __forceinline__ void sort_component_block(int q, int st, const int32_
     // large component: the rank of a read is the number of smaller ids in
     // its block (ids are distinct)
     for (int i = threadIdx.x; i < q; i += kIndBlock) {
-      const int32_t x = tmp[st + i];
+      const int32_t x = members[i];
       int r = 0;
-      for (int t = 0; t < q; ++t) r += tmp[st + t] < x;
+      for (int t = 0; t < q; ++t) r += members[t] < x;
       perm[st + r] = x;
       lidx[x] = st + r;
     }
@@ -323,18 +324,20 @@ __device__ __forceinline__ void sort_component_block(int q, int st, const int32_
   __syncthreads();
 }
 
-// InducedSubgraph for one component, all in one workgroup: sort the block
-// of reads by id, number them st, st+1, ..., and write their local CSR rows
-// (kept entries in row order of S, neighbours renumbered, entry index kept)
+// InducedSubgraph for one component, all in one workgroup: sort its reads
+// (members, in any order) by id, number them st, st+1, ..., and write their
+// local CSR rows (kept entries in row order of S, neighbours renumbered,
+// entry index kept)
 // starting at entry estart.  Neighbours of a kept entry lie in the same
 // component, so their local numbers come from the sorted block itself.
 __device__ __forceinline__ void induce_component(
-    int q, int st, int estart, const int32_t *__restrict__ tmp, const uint8_t *__restrict__ flags,
+    int q, int st, int estart, const int32_t *__restrict__ members,
+    const uint8_t *__restrict__ flags,
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
     int32_t *__restrict__ perm, int32_t *__restrict__ lidx, int32_t *__restrict__ loc_row_ptr,
     int32_t *__restrict__ loc_col, int32_t *__restrict__ loc_eid, int32_t *a,
     int32_t *sh_scan) {
-  sort_component_block(q, st, tmp, perm, lidx, a);  // ends with a barrier
+  sort_component_block(q, st, members, perm, lidx, a);  // ends with a barrier
   const bool in_lds = q <= kIndLocalCap;
   int carry = 0;
   for (int base = 0; base < q; base += kIndBlock) {

@@ -42,6 +42,7 @@ struct Scratch {
   int32_t *aux;        // [n] partition fallback: bin of each component
   int32_t *walk;       // [16n] assemble: chain arrays of components too big for LDS
   int32_t *estart;     // [n] batched induce: first local CSR entry of each component
+  int32_t *memb;       // [n] batched components: first member slot of each component
 };
 
 }  // namespace cg
@@ -70,7 +71,7 @@ namespace cg {
 // Scratch carving shared by cg_footprint and the calls.
 struct Layout {
   size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
-      estart, total;
+      estart, memb, total;
 };
 Layout layout(int64_t n, int64_t m, int64_t P);
 bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);

@@ -34,9 +34,9 @@ struct BJob {
   cg_contigs out;
   Scratch s;
   uint64_t *forest;            // [n] tagged union-find forest (batch-owned, never reused)
-  int4 *conn_list;             // [n] reads with kept entries: (id, kept neighbours or -1, flags),
-                               // each mask tile's reads packed at the start of its slice
-  int32_t *conn_map;           // [n] slot of a read in conn_list
+  int4 *conn_list;             // [n] reads of degree 1-2: (id, columns or -1, degree), each
+                               // mask tile's reads packed in id order at the start of its slice
+  int32_t *conn_map;           // [n] slot of a listed read in conn_list
   int32_t vt_first, vt_count;  // the job's vertex tiles (covering 0..n)
   int32_t mt_first, mt_count;  // the job's mask tiles
 };
@@ -50,11 +50,14 @@ struct MaskTile {
   int32_t *label_comp;
   int4 *conn_list;
   int32_t *conn_map;
-  int32_t *conn_cnt;  // this tile's number of listed reads
+  int2 *tile_cnt;   // (listed reads, branch reads) of this tile
   int32_t n, v0;
+  int32_t lc_init;  // first value of label_comp: -1, or 4 (one-read count) when
+                    // one-read components can be eligible
 };
 constexpr int kMaskThreads = 256;
-constexpr int kMaskTile = 4 * kMaskThreads;
+constexpr int kMaskGroups = 2;  // groups of 4 consecutive reads per thread
+constexpr int kMaskTile = 4 * kMaskThreads * kMaskGroups;
 
 struct BatchDev {
   BJob *jobs;                       // [n_jobs]
@@ -64,7 +67,7 @@ struct BatchDev {
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
   unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
-  int32_t *mt_conn;                 // [n_mtiles] listed reads of each mask tile
+  int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
   const MaskTile *mtiles;           // [n_mtiles]
   Fixed *fixed;
@@ -83,99 +86,121 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 }
 
 // ---------------------------------------------------------------------------
-// 1. mask (four reads per thread, 16-byte loads and stores): branch flags and
-// kept entries, labels and size counters initialised (a read without kept
-// entries is its own one-read component: label = id, count final here), and
-// every read with kept entries listed with its kept neighbours.  The branch /
-// kept-entry counts are summed later by the job's LPT workgroup.
+// 1. mask (eight reads per thread as two 16-byte row_ptr sweeps): branch
+// flags, labels and label_comp initialised, and every read of degree 1-2
+// listed with its columns, packed per tile in id order by a block scan.
+// Whether an entry is kept needs the other end's branch bit, which the
+// job's components workgroup reads next, from the job's flags.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t forest_tag(const BatchDev &B) { return B.counters[3] + 1u; }
 
-__device__ __forceinline__ int32_t deg_of(const int32_t *__restrict__ row_ptr, int32_t u) {
-  return row_ptr[u + 1] - row_ptr[u];
-}
-
 __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__restrict__ tiles) {
+  __shared__ int32_t sh[kMaskThreads / kWave + 1];
   const MaskTile D = tiles[blockIdx.x];
   const int32_t n = D.n;
-  const int32_t v0 = D.v0 + 4 * (int32_t)threadIdx.x;
   const int lane = lane_id();
-  // row_ptr[v0 .. v0+4]
-  int4 a = make_int4(0, 0, 0, 0);
-  if (v0 + 3 <= n) {
-    a = *(const int4 *)(D.row_ptr + v0);
-  } else if (v0 <= n) {
-    a.x = D.row_ptr[v0];
-    if (v0 + 1 <= n) a.y = D.row_ptr[v0 + 1];
-    if (v0 + 2 <= n) a.z = D.row_ptr[v0 + 2];
-  }
-  int32_t e4 = __shfl_down(a.x, 1);
-  if (lane == kWave - 1 && v0 + 4 <= n) e4 = D.row_ptr[v0 + 4];
-  const int32_t rp[5] = {a.x, a.y, a.z, a.w, e4};
-  // kept entries: the rows of degree 1-2 read their columns, then the
-  // neighbours' degrees (all loads issued before any is used)
-  int32_t u0[4], u1[4], dg[4];
+  int32_t v0[kMaskGroups];
+  int4 a[kMaskGroups];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const bool live = v0 + i < n;
-    dg[i] = live ? rp[i + 1] - rp[i] : 0;
-    u0[i] = (dg[i] == 1 || dg[i] == 2) ? D.col[rp[i]] : -1;
-    u1[i] = dg[i] == 2 ? D.col[rp[i] + 1] : -1;
-  }
-  int32_t d0[4], d1[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    d0[i] = u0[i] >= 0 ? deg_of(D.row_ptr, u0[i]) : 3;
-    d1[i] = u1[i] >= 0 ? deg_of(D.row_ptr, u1[i]) : 3;
-  }
-  uint32_t f[4];
-  int cnt = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    f[i] = dg[i] >= 3 ? 1u : ((d0[i] < 3 ? 2u : 0u) | (d1[i] < 3 ? 4u : 0u));
-    cnt += (f[i] & 6) ? 1 : 0;
-  }
-  if (v0 + 3 < n) {
-    *(uint32_t *)(D.flags + v0) = f[0] | (f[1] << 8) | (f[2] << 16) | (f[3] << 24);
-    *(int4 *)(D.label + v0) = make_int4(v0, v0 + 1, v0 + 2, v0 + 3);
-    *(int4 *)(D.label_comp + v0) = make_int4((f[0] & 6) ? 0 : 4, (f[1] & 6) ? 0 : 4,
-                                             (f[2] & 6) ? 0 : 4, (f[3] & 6) ? 0 : 4);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (v0 + i < n) {
-        D.flags[v0 + i] = (uint8_t)f[i];
-        D.label[v0 + i] = v0 + i;
-        D.label_comp[v0 + i] = (f[i] & 6) ? 0 : 4;
-      }
-  }
-  // the tile's reads with kept entries, packed in id order at the start of
-  // the tile's slice of the list (a block scan, no global atomics)
-  __shared__ int32_t sh[kMaskThreads / kWave + 1];
-  int32_t tot;
-  int32_t pos = D.v0 + block_excl_scan<int32_t, kMaskThreads>(cnt, sh, &tot);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (f[i] & 6) {
-      D.conn_list[pos] = make_int4(v0 + i, (f[i] & 2) ? u0[i] : -1, (f[i] & 4) ? u1[i] : -1,
-                                   (int32_t)f[i]);
-      D.conn_map[v0 + i] = pos;
-      ++pos;
+  for (int g = 0; g < kMaskGroups; ++g) {
+    v0[g] = D.v0 + g * 4 * kMaskThreads + 4 * (int32_t)threadIdx.x;
+    a[g] = make_int4(0, 0, 0, 0);
+    if (v0[g] + 3 <= n) {
+      a[g] = *(const int4 *)(D.row_ptr + v0[g]);
+    } else if (v0[g] <= n) {
+      a[g].x = D.row_ptr[v0[g]];
+      if (v0[g] + 1 <= n) a[g].y = D.row_ptr[v0[g] + 1];
+      if (v0[g] + 2 <= n) a[g].z = D.row_ptr[v0[g] + 2];
     }
-  if (threadIdx.x == 0) *D.conn_cnt = tot;
+  }
+  int32_t e4[kMaskGroups];
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    e4[g] = __shfl_down(a[g].x, 1);
+    if (lane == kWave - 1 && v0[g] + 4 <= n) e4[g] = D.row_ptr[v0[g] + 4];
+  }
+  constexpr int R = 4 * kMaskGroups;
+  int32_t dg[R], bb[R];
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    const int32_t rp[5] = {a[g].x, a[g].y, a[g].z, a[g].w, e4[g]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dg[4 * g + i] = v0[g] + i < n ? rp[i + 1] - rp[i] : 0;
+      bb[4 * g + i] = rp[i];
+    }
+  }
+  int32_t u0[R], u1[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    u0[k] = (dg[k] == 1 || dg[k] == 2) ? D.col[bb[k]] : -1;
+    u1[k] = dg[k] == 2 ? D.col[bb[k] + 1] : -1;
+  }
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    uint32_t fw = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fw |= (dg[4 * g + i] >= 3 ? 1u : 0u) << (8 * i);
+    const int32_t v = v0[g];
+    if (v + 3 < n) {
+      *(uint32_t *)(D.flags + v) = fw;
+      *(int4 *)(D.label + v) = make_int4(v, v + 1, v + 2, v + 3);
+      *(int4 *)(D.label_comp + v) = make_int4(D.lc_init, D.lc_init, D.lc_init, D.lc_init);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (v + i < n) {
+          D.flags[v + i] = (uint8_t)(fw >> (8 * i));
+          D.label[v + i] = v + i;
+          D.label_comp[v + i] = D.lc_init;
+        }
+    }
+  }
+  // listed reads packed in id order: group g of every thread precedes group
+  // g + 1, so the tile is scanned group by group
+  int32_t tot_all = 0;
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    int c = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c += (dg[4 * g + i] == 1 || dg[4 * g + i] == 2) ? 1 : 0;
+      b += dg[4 * g + i] >= 3 ? 1 : 0;
+    }
+    // listed count in the low 16 bits, branch count above (a tile holds
+    // fewer than 2^16 reads)
+    int32_t tot;
+    int32_t pos = D.v0 + (tot_all & 0xFFFF) +
+                  (block_excl_scan<int32_t, kMaskThreads>(c | (b << 16), sh, &tot) & 0xFFFF);
+    tot_all += tot;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * g + i;
+      if (dg[k] == 1 || dg[k] == 2) {
+        D.conn_list[pos] = make_int4(v0[g] + i, u0[k], u1[k], dg[k]);
+        D.conn_map[v0[g] + i] = pos;
+        ++pos;
+      }
+    }
+  }
+  if (threadIdx.x == 0) *D.tile_cnt = make_int2(tot_all & 0xFFFF, tot_all >> 16);
 }
 
-// 2. components of each job in one workgroup: union-find in LDS over the
-// job's listed reads (roots = smallest read id, exact per-root counts, no
-// global atomics).  A listed read's local number is its tile's offset plus
-// its slot in the tile, which orders local numbers like read ids, so the
-// smaller local number is the smaller id.  A job with more listed reads (or
-// mask tiles) than LDS holds uses the tagged global forest instead.  Largest
-// jobs are dispatched first.
+// 2. components of each job in one workgroup, from its listed reads: kept
+// bits (both ends outside the branch set), union-find in LDS (roots =
+// smallest read id), labels, exact per-root counts, and, when one-read
+// components cannot be eligible (min_reads >= 2), the component table in
+// label order with each component's members grouped for the induce step.
+// A listed read's local number is its tile's offset plus its slot in the
+// tile, which orders local numbers like read ids, so the smaller local
+// number is the smaller id.  A job with more listed reads (or mask tiles)
+// than LDS holds uses the tagged global forest instead.  Largest jobs are
+// dispatched first.
 constexpr int kCcBlock = 1024;
 constexpr int kCcCap = 16384;
 constexpr int kCcPer = kCcCap / kCcBlock;
 constexpr int kCcTileCap = 1024;
+constexpr int32_t kNotEligible = -(1 << 30);
 
 __device__ __forceinline__ int lds_find(int32_t *par, int x) {
   volatile int32_t *vp = par;
@@ -201,116 +226,224 @@ __device__ __forceinline__ void lds_union(int32_t *par, int a, int b) {
   }
 }
 
+// kept bits of a listed read from its neighbours' branch bits
+__device__ __forceinline__ uint32_t kept_bits(const uint8_t *__restrict__ flags, int32_t u0,
+                                              int32_t u1) {
+  uint32_t f = 0;
+  if (u0 >= 0 && !(flags[u0] & 1)) f |= 2;
+  if (u1 >= 0 && !(flags[u1] & 1)) f |= 4;
+  return f;
+}
+
+__device__ __forceinline__ uint8_t kind_of(uint32_t c4) {
+  return (c4 >> 2) == 1 ? CG_KIND_SINGLE : ((c4 & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
+}
+
+__device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *tc,
+                          int64_t *sh64, int64_t *m_l_out);
+
 __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
-  __shared__ int32_t s_par[kCcCap];
+  __shared__ int32_t s_par[kCcCap], s_aux[kCcCap];
   __shared__ int32_t s_pref[kCcTileCap + 1];
-  __shared__ int32_t sh[kCcBlock / kWave + 1];
+  __shared__ int64_t sh64[kCcBlock / kWave + 1];
   const int j = B.job_order[blockIdx.x];
   const BJob &J = B.jobs[j];
   const int nt = J.mt_count;
-  if (nt == 0) return;
-  const int32_t *cnt = B.mt_conn + J.mt_first;
-  const int4 *__restrict__ list = J.conn_list;
-  const int32_t *__restrict__ map = J.conn_map;
   const int tid = threadIdx.x;
-  if (nt <= kCcTileCap) {
-    int32_t tot;
-    const int32_t c = tid < nt ? cnt[tid] : 0;
-    const int32_t ex = block_excl_scan<int32_t, kCcBlock>(c, sh, &tot);
-    if (tid < nt) s_pref[tid] = ex;
-    if (tid == 0) s_pref[nt] = tot;
+  const bool table = J.min_reads >= 2;
+  const int2 *tc = B.mt_cnt + J.mt_first;
+  // listed reads per tile (prefix in LDS) and branch reads of the job
+  int64_t L = 0, n_branch = 0;
+  for (int base = 0; base < nt; base += kCcBlock) {
+    const int t = base + tid;
+    const int2 c = t < nt ? tc[t] : make_int2(0, 0);
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kCcBlock>(((int64_t)c.y << 32) | c.x, sh64, &tot);
+    if (t < nt && nt <= kCcTileCap) s_pref[t] = (int32_t)(L + (ex & 0xFFFFFFFF));
+    L += tot & 0xFFFFFFFF;
+    n_branch += tot >> 32;
+  }
+  if (tid == 0 && nt <= kCcTileCap) s_pref[nt] = (int32_t)L;
+  __syncthreads();
+  int64_t m_l = 0;
+  if (L > 0 && (nt > kCcTileCap || L > kCcCap)) {
+    cc_global(B, J, nt, tc, sh64, &m_l);
+  } else if (L > 0) {
+    const int per = (int)((L + kCcBlock - 1) / kCcBlock);
+    const int l0 = tid * per;
+    int t = 0;
+    {
+      int lo = 0, hi = nt - 1;  // tile of local number l0
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= l0) lo = mid;
+        else hi = mid - 1;
+      }
+      t = lo;
+    }
+    int32_t w0[kCcPer], w1[kCcPer];
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) {
+      const int l = l0 + k;
+      w0[k] = w1[k] = -1;
+      if (k < per && l < L) {
+        while (s_pref[t + 1] <= l) ++t;
+        const int4 e = J.conn_list[t * kMaskTile + (l - s_pref[t])];
+        s_aux[l] = e.x;
+        s_par[l] = l;
+        w0[k] = e.y;
+        w1[k] = e.z;
+      }
+    }
+    // kept bits and the local numbers of the kept neighbours with smaller ids
+    uint32_t fk[kCcPer];
+    int32_t lu0[kCcPer], lu1[kCcPer];
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) {
+      const int l = l0 + k;
+      fk[k] = 0;
+      lu0[k] = lu1[k] = -1;
+      if (k < per && l < L) {
+        const int32_t id = s_aux[l];
+        fk[k] = kept_bits(J.flags, w0[k], w1[k]);
+        if ((fk[k] & 2) && w0[k] < id) {
+          const int32_t p = J.conn_map[w0[k]];
+          lu0[k] = s_pref[p / kMaskTile] + p % kMaskTile;
+        }
+        if ((fk[k] & 4) && w1[k] < id) {
+          const int32_t p = J.conn_map[w1[k]];
+          lu1[k] = s_pref[p / kMaskTile] + p % kMaskTile;
+        }
+        m_l += __popc(fk[k]);
+      }
+    }
     __syncthreads();
-    const int32_t L = tot;
-    if (L == 0) return;
-    if (L <= kCcCap) {
-      // slot of local number l: its tile (binary search over s_pref) and rank
-      int32_t id[kCcPer], l0[kCcPer], l1[kCcPer];
-      uint32_t end[kCcPer];
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) {
+      if (lu0[k] >= 0) lds_union(s_par, l0 + k, lu0[k]);
+      if (lu1[k] >= 0) lds_union(s_par, l0 + k, lu1[k]);
+    }
+    __syncthreads();
+    int32_t r[kCcPer];
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) r[k] = fk[k] ? lds_find(s_par, l0 + k) : l0 + k;
+    __syncthreads();
+    // s_par becomes the per-root counter: 4 per read + 1 per path end
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k)
+      if (k < per && l0 + k < L) s_par[l0 + k] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k)
+      if (fk[k]) atomicAdd(s_par + r[k], 4 + (__popc(fk[k]) == 1 ? 1 : 0));
+    __syncthreads();
+    int32_t c4[kCcPer];  // own roots' counts (a read without kept entries: 4)
+    int32_t ne = 0, nq = 0;
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) {
+      const int l = l0 + k;
+      c4[k] = 0;
+      if (k < per && l < L) {
+        const int32_t id = s_aux[l];
+        if (fk[k]) {
+          J.flags[id] = (uint8_t)fk[k];
+          J.label[id] = s_aux[r[k]];
+          if (r[k] == l) c4[k] = s_par[l];
+        } else {
+          c4[k] = 4;
+        }
+        if (!table) {
+          if (fk[k]) J.parts.label_comp[id] = c4[k];  // 0 for non-roots
+        } else if (fk[k] && r[k] == l && (c4[k] >> 2) >= J.min_reads) {
+          ++ne;
+          nq += c4[k] >> 2;
+        }
+      }
+    }
+    if (table) {
+      int64_t tot;
+      const int64_t ex = block_excl_scan<int64_t, kCcBlock>(((int64_t)ne << 32) | nq, sh64, &tot);
+      int32_t cb = (int32_t)(ex >> 32), mb = (int32_t)(ex & 0xFFFFFFFF);
+      // s_par: member cursor of each eligible root, kNotEligible elsewhere
 #pragma unroll
       for (int k = 0; k < kCcPer; ++k) {
-        const int l = tid + k * kCcBlock;
-        id[k] = -1;
-        l0[k] = l1[k] = -1;
-        end[k] = 0;
-        if (l < L) {
-          int lo = 0, hi = nt - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_pref[mid] <= l) lo = mid;
-            else hi = mid - 1;
-          }
-          const int4 e = list[lo * kMaskTile + (l - s_pref[lo])];
-          id[k] = e.x;
-          end[k] = (((e.w >> 1) & 1) + ((e.w >> 2) & 1)) == 1 ? 1u : 0u;
-          // each kept entry is hooked once, by its larger endpoint
-          if (e.y >= 0 && e.y < e.x) {
-            const int32_t p = map[e.y];
-            l0[k] = s_pref[p / kMaskTile] + p % kMaskTile;
-          }
-          if (e.z >= 0 && e.z < e.x) {
-            const int32_t p = map[e.z];
-            l1[k] = s_pref[p / kMaskTile] + p % kMaskTile;
-          }
-          s_par[l] = l;
+        const int l = l0 + k;
+        if (!fk[k] || r[k] != l) continue;
+        const int32_t id = s_aux[l];
+        if ((c4[k] >> 2) >= J.min_reads) {
+          const int32_t q = c4[k] >> 2;
+          J.parts.comp_label[cb] = id;
+          J.parts.comp_size[cb] = q;
+          J.parts.comp_kind[cb] = kind_of(c4[k]);
+          J.parts.label_comp[id] = cb;
+          J.s.memb[cb] = mb;
+          s_par[l] = mb;
+          ++cb;
+          mb += q;
+        } else {
+          s_par[l] = kNotEligible;
         }
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < kCcPer; ++k) {
-        const int l = tid + k * kCcBlock;
-        if (l0[k] >= 0) lds_union(s_par, l, l0[k]);
-        if (l1[k] >= 0) lds_union(s_par, l, l1[k]);
-      }
-      __syncthreads();
-      int32_t r[kCcPer];
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k) {
-        const int l = tid + k * kCcBlock;
-        r[k] = l < L ? lds_find(s_par, l) : -1;
-      }
-      __syncthreads();
-      // roots publish their ids, members take them as labels
-#pragma unroll
       for (int k = 0; k < kCcPer; ++k)
-        if (id[k] >= 0 && r[k] == tid + k * kCcBlock) s_par[r[k]] = id[k];
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k)
-        if (id[k] >= 0) J.label[id[k]] = s_par[r[k]];
-      __syncthreads();
-      // s_par becomes the per-root counter: 4 per read + 1 per path end
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k)
-        if (id[k] >= 0) s_par[tid + k * kCcBlock] = 0;
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k)
-        if (id[k] >= 0) atomicAdd(s_par + r[k], 4 + (int)end[k]);
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k) {
-        const int l = tid + k * kCcBlock;
-        if (id[k] >= 0 && r[k] == l) J.parts.label_comp[id[k]] = s_par[l];
-      }
-      return;
+        if (fk[k]) {
+          const int32_t pos = atomicAdd(s_par + r[k], 1);
+          if (pos >= 0) J.s.tmp[pos] = s_aux[l0 + k];
+        }
+      if (tid == 0) *J.parts.d_n_comp = (int32_t)(tot >> 32);
     }
   }
-  // too many reads for LDS: the job's own forest in global memory (only this
-  // workgroup touches it), the list walked tile by tile
+  if (L == 0 && table && tid == 0) *J.parts.d_n_comp = 0;
+  // BranchRemoval's counts: branch reads and kept entries
+  int64_t tm;
+  (void)block_excl_scan<int64_t, kCcBlock>(m_l, sh64, &tm);
+  if (tid == 0) {
+    J.counts[0] = (int32_t)n_branch;
+    J.counts[1] = (int32_t)tm;
+  }
+}
+
+// The same for a job beyond LDS: the job's own forest in global memory (only
+// this workgroup touches it), the list walked tile by tile in id order.
+__device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *tc,
+                          int64_t *sh64, int64_t *m_l_out) {
+  const int tid = threadIdx.x;
   const uint32_t tag = forest_tag(B);
+  const bool table = J.min_reads >= 2;
+  uint32_t *lc = (uint32_t *)J.parts.label_comp;
+  int64_t m_l = 0;
+  // kept bits; counters of the reads with kept entries start at 0
   for (int t = 0; t < nt; ++t) {
-    const int32_t c = cnt[t];
+    const int32_t c = tc[t].x;
     for (int i = tid; i < c; i += kCcBlock) {
-      const int4 e = list[t * kMaskTile + i];
-      if (e.y >= 0 && e.y < e.x) tf_union(J.forest, tag, e.x, e.y);
-      if (e.z >= 0 && e.z < e.x) tf_union(J.forest, tag, e.x, e.z);
+      const int4 e = J.conn_list[t * kMaskTile + i];
+      const uint32_t f = kept_bits(J.flags, e.y, e.z);
+      if (f) {
+        J.flags[e.x] = (uint8_t)f;
+        lc[e.x] = 0;
+      }
+      m_l += __popc(f);
+    }
+  }
+  *m_l_out = m_l;
+  __syncthreads();
+  for (int t = 0; t < nt; ++t) {
+    const int32_t c = tc[t].x;
+    for (int i = tid; i < c; i += kCcBlock) {
+      const int4 e = J.conn_list[t * kMaskTile + i];
+      const uint32_t f = J.flags[e.x];
+      if ((f & 2) && e.y < e.x) tf_union(J.forest, tag, e.x, e.y);
+      if ((f & 4) && e.z < e.x) tf_union(J.forest, tag, e.x, e.z);
     }
   }
   __syncthreads();
   for (int t = 0; t < nt; ++t) {
-    const int32_t c = cnt[t];
+    const int32_t c = tc[t].x;
     for (int i = tid; i < c; i += kCcBlock) {
-      const int4 e = list[t * kMaskTile + i];
+      const int4 e = J.conn_list[t * kMaskTile + i];
+      const uint32_t f = J.flags[e.x];
+      if (!f) continue;
       int32_t r = e.x;
       while (true) {
         const int32_t p = tf_parent(J.forest, tag, r);
@@ -318,8 +451,60 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
         r = p;
       }
       J.label[e.x] = r;
-      const uint32_t degL = ((e.w >> 1) & 1) + ((e.w >> 2) & 1);
-      atomicAdd((uint32_t *)J.parts.label_comp + r, 4u + (degL == 1 ? 1u : 0u));
+      atomicAdd(lc + r, 4u + (__popc(f) == 1 ? 1u : 0u));
+    }
+  }
+  if (!table) return;
+  __syncthreads();
+  // component table in label order: the list in id order, chunk by chunk
+  int32_t cb = 0, mb = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int32_t c = tc[t].x;
+    for (int base = 0; base < c; base += kCcBlock) {
+      const int i = base + tid;
+      int32_t id = -1;
+      uint32_t c4 = 0;
+      bool elig = false, root = false;
+      if (i < c) {
+        id = J.conn_list[t * kMaskTile + i].x;
+        if (J.flags[id] & 6) {
+          root = J.label[id] == id;
+          if (root) {
+            c4 = __hip_atomic_load(lc + id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            elig = (int32_t)(c4 >> 2) >= J.min_reads;
+          }
+        }
+      }
+      int64_t tot;
+      const int64_t ex = block_excl_scan<int64_t, kCcBlock>(
+          elig ? (((int64_t)1 << 32) | (c4 >> 2)) : 0, sh64, &tot);
+      if (elig) {
+        const int32_t k = cb + (int32_t)(ex >> 32);
+        J.parts.comp_label[k] = id;
+        J.parts.comp_size[k] = (int32_t)(c4 >> 2);
+        J.parts.comp_kind[k] = kind_of(c4);
+        J.s.memb[k] = mb + (int32_t)(ex & 0xFFFFFFFF);
+        J.s.fill[k] = 0;
+      }
+      if (i < c && (J.flags[id] & 6))
+        __hip_atomic_store((int32_t *)lc + id, elig ? cb + (int32_t)(ex >> 32) : -1,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      cb += (int32_t)(tot >> 32);
+      mb += (int32_t)(tot & 0xFFFFFFFF);
+    }
+  }
+  if (tid == 0) *J.parts.d_n_comp = cb;
+  __syncthreads();
+  // members grouped by component
+  for (int t = 0; t < nt; ++t) {
+    const int32_t c = tc[t].x;
+    for (int i = tid; i < c; i += kCcBlock) {
+      const int32_t id = J.conn_list[t * kMaskTile + i].x;
+      if (!(J.flags[id] & 6)) continue;
+      const int32_t k = __hip_atomic_load((int32_t *)lc + J.label[id], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+      if (k < 0) continue;
+      J.s.tmp[J.s.memb[k] + (int32_t)atomicAdd(J.s.fill + k, 1u)] = id;
     }
   }
 }
@@ -341,6 +526,7 @@ __global__ __launch_bounds__(T) void kb_tilecount(BatchDev B) {
   __shared__ int32_t sh[T / kWave];
   const int t = blockIdx.x;
   const BJob &J = B.jobs[B.tile_job[t]];
+  if (J.min_reads >= 2) return;  // table and members come from the components pass
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   uint32_t c = 0;
   const bool e = eligible<T>(J, v, &c);
@@ -359,6 +545,7 @@ __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
   __shared__ int32_t sh[T / kWave + 1];
   const int t = blockIdx.x;
   const BJob &J = B.jobs[B.tile_job[t]];
+  if (J.min_reads >= 2) return;  // table and members come from the components pass
   int32_t before = 0;
   for (int i = J.vt_first + (int)threadIdx.x; i < t; i += T) before += B.tile_cnt[i];
   before = wave_sum(before);
@@ -410,22 +597,6 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
                    J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
                    J.parts.comp_kind, J.s.estart);
   __syncthreads();
-  // branch vertices and kept entries of the job (BranchRemoval's counts)
-  {
-    int64_t nb = 0, ml = 0;
-    for (int64_t v = threadIdx.x; v < J.g.n; v += kLptBlock) {
-      const uint32_t f = J.flags[v];
-      nb += f & 1;
-      ml += ((f >> 1) & 1) + ((f >> 2) & 1);
-    }
-    int64_t tnb, tml;
-    (void)block_excl_scan<int64_t, kLptBlock>(nb, sh, &tnb);
-    (void)block_excl_scan<int64_t, kLptBlock>(ml, sh, &tml);
-    if (threadIdx.x == 0) {
-      J.counts[0] = (int32_t)tnb;
-      J.counts[1] = (int32_t)tml;
-    }
-  }
   int64_t carry = 0;
   for (int base = 0; base < P; base += kLptBlock) {
     const int b = base + threadIdx.x;
@@ -486,6 +657,7 @@ template <int T>
 __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   const int t = blockIdx.x;
   const BJob &J = B.jobs[B.tile_job[t]];
+  if (J.min_reads >= 2) return;  // table and members come from the components pass
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   if (v >= J.g.n) return;
   const int32_t c = J.parts.label_comp[J.label[v]];
@@ -504,7 +676,9 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
     const int j = job_of(B.comp_base, B.n_jobs, i);
     const BJob &J = B.jobs[j];
     const int c = i - B.comp_base[j];
-    induce_component(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c], J.s.tmp, J.flags,
+    const int32_t *members =
+        J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : J.parts.comp_start[c]);
+    induce_component(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c], members, J.flags,
                      J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx, J.local.loc_row_ptr,
                      J.local.loc_col, J.local.loc_eid, a, sh_scan);
   }
@@ -590,6 +764,7 @@ using namespace cg;
 struct cg_batch {
   cg_ctx *ctx;
   int32_t n_jobs, n_vtiles;
+  bool any_single;  // a job with min_reads <= 1 (one-read components eligible)
   cg_batch_params prm;
   BatchDev dev;
   char *mem;
@@ -700,7 +875,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     n_mt += hj[i].mt_count;
   }
   const size_t o_mtiles = take(sizeof(MaskTile) * (n_mt > 0 ? n_mt : 1));
-  const size_t o_mtconn = take(sizeof(int32_t) * (n_mt > 0 ? n_mt : 1));
+  const size_t o_mtcnt = take(sizeof(int2) * (n_mt > 0 ? n_mt : 1));
   std::vector<size_t> forest_off(n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
     job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
@@ -711,6 +886,8 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   b->ctx = ctx;
   b->n_jobs = n_jobs;
   b->n_vtiles = nv;
+  b->any_single = false;
+  for (int i = 0; i < n_jobs; ++i) b->any_single |= jobs[i].min_reads < 2;
   b->prm = prm;
   b->mem_bytes = at;
   b->mem = nullptr;
@@ -747,12 +924,13 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     }
     std::vector<MaskTile> mt;
     mt.reserve(n_mt);
-    int32_t *d_mtconn = (int32_t *)(b->mem + o_mtconn);
+    int2 *d_mtcnt = (int2 *)(b->mem + o_mtcnt);
     for (int i = 0; i < n_jobs; ++i)
       for (int32_t v0 = 0; v0 < jobs[i].g.n; v0 += kMaskTile)
         mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, jobs[i].flags, jobs[i].label,
                               jobs[i].parts.label_comp, hj[i].conn_list, hj[i].conn_map,
-                              d_mtconn + (int32_t)mt.size(), jobs[i].g.n, v0});
+                              d_mtcnt + (int32_t)mt.size(), jobs[i].g.n, v0,
+                              jobs[i].min_reads >= 2 ? -1 : 4});
     std::vector<int32_t> order(n_jobs);
     for (int i = 0; i < n_jobs; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -785,7 +963,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
   d.counters = (unsigned int *)(b->mem + o_counters);
-  d.mt_conn = (int32_t *)(b->mem + o_mtconn);
+  d.mt_cnt = (int2 *)(b->mem + o_mtcnt);
   d.job_order = (const int32_t *)(b->mem + o_order);
   d.mtiles = (const MaskTile *)(b->mem + o_mtiles);
   d.n_mtiles = n_mt;
@@ -806,13 +984,19 @@ int cg_batch_run(cg_batch *b, void *stream) {
   if (B.n_mtiles > 0)
     CG_LAUNCH(ctx, kb_mask_list, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
   CG_LAUNCH(ctx, kb_cc_local, dim3(b->n_jobs), dim3(kCcBlock), st, B);
-  if (T == 256) launch_vertex_phases<256>(b, st);
-  else if (T == 512) launch_vertex_phases<512>(b, st);
-  else launch_vertex_phases<1024>(b, st);
+  // jobs where one-read components are eligible take their component table
+  // and member buckets from full vertex passes
+  if (b->any_single) {
+    if (T == 256) launch_vertex_phases<256>(b, st);
+    else if (T == 512) launch_vertex_phases<512>(b, st);
+    else launch_vertex_phases<1024>(b, st);
+  }
   CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kLptBlock), st, B);
-  if (T == 256) launch_vertex_fill<256>(b, st);
-  else if (T == 512) launch_vertex_fill<512>(b, st);
-  else launch_vertex_fill<1024>(b, st);
+  if (b->any_single) {
+    if (T == 256) launch_vertex_fill<256>(b, st);
+    else if (T == 512) launch_vertex_fill<512>(b, st);
+    else launch_vertex_fill<1024>(b, st);
+  }
   CG_LAUNCH(ctx, kb_induce, dim3(PB), dim3(kIndBlock), st, B);
   CG_LAUNCH(ctx, kb_walk, dim3(PB), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);

@@ -36,11 +36,18 @@ def _mixed_graphs():
     r = np.random.default_rng(5)
     gs.append(_chain_graph(r, [1500, 40, 2], cycles=[1200, 7]))   # beyond the LDS tiles
     gs.append(_chain_graph(r, [2] * 2500 + [5] * 30))              # beyond the batch LDS sort
-    gs.append(_chain_graph(r, [3000, 2900, 2400, 3]))              # beyond the LDS components
+    gs.append(_chain_graph(r, [3000, 2900, 2400, 3]))
+    # beyond the LDS components pass: with and without one-read components
+    gs.append(_chain_graph(r, [6000, 6000, 5000, 2]))
+    gs[-1].meta["min_reads"] = 2
+    gs.append(_chain_graph(r, [7000, 5000, 1], cycles=[4000, 600]))
+    gs[-1].meta["min_reads"] = 1
     return gs
 
 
 def _params(i, g):
+    if "min_reads" in g.meta:
+        return [64, 300, 8, 1024][i % 4], g.meta["min_reads"]
     r = np.random.default_rng(100 + i)
     P = int(r.integers(1, 9)) if g.n <= 16 else [64, 300, 8, 1024][i % 4]
     return P, int(r.integers(0, 3)) if g.n <= 16 else 2
