@@ -68,6 +68,37 @@ def algo_bytes(kernel, s):
     return table.get(kernel)
 
 
+def csrc_digest():
+    """sha256 over the kernel sources, in the order the byte-counter profile uses."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2207_04350_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of a batched kernel from the committed counter
+    profile (scaled FETCH_SIZE + WRITE_SIZE), or None when the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "batched_config4_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    digest, mb = None, None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("csrc sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            cells = [c.strip() for c in line.split("|")]
+            if len(cells) >= 5 and cells[1].strip("`").startswith("cg::%s(" % kernel):
+                mb = float(cells[4])
+    if digest != csrc_digest() or mb is None:
+        return None
+    return mb * 1e6
+
+
 def workload_graphs(name):
     import synth
     if name == "batch":
@@ -281,7 +312,11 @@ def main():
                     if maskcc_ms else None,
                     "kernels": "kb_mask_list + kb_cc_local (the latter also builds the component table and groups members)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(kname(dom).replace("k_", "kb_", 1))
+                     if args.workload == "batch" else None,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
+                                     "profiles/batched_config4_hbm_bytes.md)",
                      "avg_launch_us": dom_avg_us, "bytes_per_launch": dom_bytes_per_launch,
                      "timing": "HIP events around each launch on its stream, %d eager steps"
                                % args.steps},
