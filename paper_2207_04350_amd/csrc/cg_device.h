@@ -830,117 +830,248 @@ __device__ __forceinline__ uint64_t piece_src(const PieceD &d, uint64_t t, int k
   return d.rev ? d.src + d.rlen - t - (uint64_t)k : d.src + t;
 }
 
+// 16 stored bases starting at base b (any alignment) as one word: a 64-bit
+// funnel shift of two store words (indices clamped into the store).
+// Store word index clamped into [0, nwords - 1]; a window may start before
+// the store (reverse pieces of the first reads) or end after it, and the
+// words it then reads are never used.
+__device__ __forceinline__ uint64_t clamp_word(int64_t w, uint64_t nwords) {
+  return w < 0 ? 0 : ((uint64_t)w >= nwords ? nwords - 1 : (uint64_t)w);
+}
+
+// 16 stored bases starting at base b (any alignment, b taken as signed) as
+// one word: a 64-bit funnel shift of two store words.
+__device__ __forceinline__ uint32_t window16(const CG_GLOBAL uint32_t *__restrict__ seq,
+                                             uint64_t nwords, uint64_t b) {
+  const int64_t w = (int64_t)b >> 4;
+  const uint32_t lo = seq[clamp_word(w, nwords)];
+  const uint32_t hi = seq[clamp_word(w + 1, nwords)];
+  return __builtin_amdgcn_alignbit(hi, lo, 2u * (uint32_t)(b & 15));
+}
+
+// reverse the 16 2-bit fields of a word and complement them
+__device__ __forceinline__ uint32_t revcomp16(uint32_t x) { return ~rev_fields32(x); }
+
+__device__ __forceinline__ uint32_t low_fields(int k) {
+  return k >= 16 ? 0xFFFFFFFFu : ((1u << (2 * k)) - 1u);
+}
+
+// The first k (<= 16) bases of a piece in walking orientation, in fields 0..k-1
+// (fields above k are not cleared).
+__device__ __forceinline__ uint32_t piece_head16(const CG_GLOBAL uint32_t *__restrict__ seq,
+                                                 uint64_t nwords, uint64_t src, uint32_t rlen,
+                                                 bool rev) {
+  return rev ? revcomp16(window16(seq, nwords, src + rlen - 16)) : window16(seq, nwords, src);
+}
+
+// Copy descriptor of one piece: output words [w0, w0 + nw) of the bases
+// array are the words whose first base lies in the piece.
+//   base  forward: stored base of output base 0 of the bases array, so word
+//         w starts at stored base base + 16 w; reverse: stored base at which
+//         the 64-base window of a group starting at word w begins is
+//         base - 16 w (everything modulo 2^64)
+//   info  bits 0-4: bases of the piece in its last owned word (1..16);
+//         bit 5: reverse; bit 6: the piece ends its contig
+struct CopyD {
+  uint64_t base, w0;
+  uint32_t nw, info;
+};
+// What a word straddling into the next piece needs of it.
+struct CopyE {
+  uint64_t src;
+  uint32_t rlen, info;  // info: plen | reverse << 30 | ends its contig << 31
+};
+
+__device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
+  CopyD c;
+  const uint64_t pend = d.poff + d.plen;
+  const uint64_t j0 = (d.poff + 15) >> 4, j1 = (pend + 15) >> 4;
+  c.w0 = d.cb + j0;
+  c.nw = (uint32_t)(j1 - j0);
+  const uint32_t fs = (uint32_t)(pend - 16 * (j1 - 1));
+  c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u);
+  c.base = d.rev ? d.src + d.rlen - 64 + d.poff + 16 * d.cb : d.src - d.poff - 16 * d.cb;
+  return c;
+}
+
+__device__ __forceinline__ CopyE copy_next(const PieceD &e) {
+  CopyE c;
+  c.src = e.src;
+  c.rlen = e.rlen;
+  c.info = e.plen | (e.rev ? (1u << 30) : 0u) | (e.poff + e.plen == e.L ? (1u << 31) : 0u);
+  return c;
+}
+
+constexpr int kCopyUnroll = 2;  // groups per lane per step
+
+// One step of the copy: kCopyUnroll groups per lane (groups g, g + 64, ...),
+// their pieces' descriptors and store windows.
+struct CopyStage {
+  uint32_t win[kCopyUnroll][5];
+  uint32_t hlo[kCopyUnroll], hhi[kCopyUnroll];  // store words of the next piece's head
+  CopyD d[kCopyUnroll];
+  CopyE e[kCopyUnroll];
+  uint32_t k[kCopyUnroll];
+  int t[kCopyUnroll];
+  bool ok[kCopyUnroll];
+};
+
+// Find the pieces of a step's groups and start its loads.
+__device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G, uint32_t gstart,
+                                           const CopyD &my, const CopyE &nx,
+                                           const CG_GLOBAL uint32_t *__restrict__ seq,
+                                           uint64_t nwords, int lane) {
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) S.t[u] = 0;
+  // piece of group g: the last lane t with gstart[t] <= g (gstart is
+  // non-decreasing and equals G from lane cnt on, so t < cnt when g < G).
+  // Six fixed steps, every lane shuffling in every step: a shuffle must
+  // never run with part of the wave switched off.
+#pragma unroll
+  for (int step = kWave / 2; step > 0; step >>= 1) {
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const uint32_t g = gb + lane + kWave * u;
+      const uint32_t sm = __shfl(gstart, S.t[u] + step);
+      if (sm <= g) S.t[u] += step;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const int t = S.t[u];
+    S.d[u].base = __shfl(my.base, t);
+    S.d[u].w0 = __shfl(my.w0, t);
+    S.d[u].nw = __shfl(my.nw, t);
+    S.d[u].info = __shfl(my.info, t);
+    S.e[u].src = __shfl(nx.src, t);
+    S.e[u].rlen = __shfl(nx.rlen, t);
+    S.e[u].info = __shfl(nx.info, t);
+    const uint32_t gs = __shfl(gstart, t);
+    const uint32_t g = gb + lane + kWave * u;
+    S.ok[u] = g < G;
+    S.k[u] = S.ok[u] ? 4 * (g - gs) : 0;  // first owned word of the group
+  }
+  // loads only, unconditional and clamped, so that nothing here waits for
+  // memory and the step's loads stay in flight while the previous step is
+  // finished
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const CopyD &d = S.d[u];
+    const bool rev = d.info & 32u;
+    const uint64_t w = d.w0 + S.k[u];
+    // the piece's window: 5 store words covering the group's 64 bases
+    const uint64_t sb = rev ? d.base - 16 * w : d.base + 16 * w;
+    const int64_t sw = S.ok[u] ? (int64_t)sb >> 4 : 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
+    // the next piece's first 16 bases, for the piece's last word
+    const CopyE &e = S.e[u];
+    const uint64_t hb = (e.info & (1u << 30)) ? e.src + e.rlen - 16 : e.src;
+    const int64_t hw = (int64_t)hb >> 4;
+    S.hlo[u] = seq[clamp_word(hw, nwords)];
+    S.hhi[u] = seq[clamp_word(hw + 1, nwords)];
+  }
+}
+
+// Finish a step: words from the windows, the pieces' last words, stores.
+__device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays &A, int32_t c0,
+                                          int32_t n_e, const CG_GLOBAL uint32_t *__restrict__ seq,
+                                          uint64_t nwords, CG_GLOBAL uint32_t *__restrict__ bases) {
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    if (!S.ok[u]) continue;
+    const CopyD &d = S.d[u];
+    const bool rev = d.info & 32u;
+    const uint32_t sh = 2u * (uint32_t)((rev ? d.base - 16 * (d.w0 + S.k[u])
+                                            : d.base + 16 * (d.w0 + S.k[u])) & 15);
+    const uint32_t nw = d.nw - S.k[u] < 4 ? d.nw - S.k[u] : 4;
+    uint32_t out[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      out[i] = rev ? revcomp16(__builtin_amdgcn_alignbit(S.win[u][4 - i], S.win[u][3 - i], sh))
+                   : __builtin_amdgcn_alignbit(S.win[u][i + 1], S.win[u][i], sh);
+    const int fs = (int)(d.info & 31u);
+    if (S.k[u] + nw == d.nw && fs < 16) {
+      // the piece's last word: its own fs bases, then the next piece(s) or
+      // zero padding at the contig's end
+      uint32_t x = out[nw - 1] & low_fields(fs);
+      if (!(d.info & 64u)) {
+        const CopyE &e = S.e[u];
+        const int pl = (int)(e.info & 0x3FFFFFFFu);
+        const int k2 = 16 - fs < pl ? 16 - fs : pl;
+        const bool erev = e.info & (1u << 30);
+        const uint64_t hb = erev ? e.src + e.rlen - 16 : e.src;
+        uint32_t head = __builtin_amdgcn_alignbit(S.hhi[u], S.hlo[u], 2u * (uint32_t)(hb & 15));
+        if (erev) head = revcomp16(head);
+        x |= (head & low_fields(k2)) << (2 * fs);
+        int filled = fs + k2;
+        // pieces shorter than the rest of the word: take the following ones
+        if (filled < 16 && !(e.info & (1u << 31))) {
+          for (int32_t pp = c0 + S.t[u] + 2; filled < 16 && pp < n_e; ++pp) {
+            const PieceD f = load_piece(A, pp);
+            const int k3 = 16 - filled < (int)f.plen ? 16 - filled : (int)f.plen;
+            const uint32_t y = piece_head16(seq, nwords, f.src, f.rlen, f.rev != 0);
+            x |= (y & low_fields(k3)) << (2 * filled);
+            filled += k3;
+            if (f.poff + f.plen == f.L) break;
+          }
+        }
+      }
+      out[nw - 1] = x;
+    }
+    CG_GLOBAL uint32_t *o = bases + d.w0 + S.k[u];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < (int)nw) o[i] = out[i];
+  }
+}
+
 // One wave copies the chunk of cnt (<= 64) consecutive pieces starting at
 // piece c0 of a graph with n_e pieces.  Lane l gathers piece c0+l's
 // descriptor; the chunk's four-word groups (each owned by the piece holding
-// its first base) are then spread over the lanes, 64 groups per step, so
-// lanes of one step work on different pieces.  A group that runs into the
-// next piece loads both parts before combining them; a group that spans
-// three or more pieces (only with very short pieces) takes a slower loop.
-// c0, cnt and n_e are wave-uniform; all lanes run every step.
+// the first base of its words) are then spread over the lanes, 64 groups per
+// row, so lanes of one row work on different pieces.  Every word is a
+// funnel shift of two store words, reverse-complemented in registers for a
+// reverse piece; only a piece's last word can run into the next piece(s).
+// Steps are software-pipelined: the loads of step s + 1 are issued before
+// step s is finished, so a wave always has loads in flight.
+// c0, cnt and n_e are wave-uniform; every lane runs every step.
 __device__ __forceinline__ void copy_chunk(const uint32_t *seq_, uint64_t nwords, uint32_t *bases_,
                                            const PieceArrays &A, int32_t c0, int cnt,
                                            int32_t n_e, int lane) {
   const CG_GLOBAL uint32_t *seq = (const CG_GLOBAL uint32_t *)seq_;
   CG_GLOBAL uint32_t *bases = (CG_GLOBAL uint32_t *)bases_;
-  PieceD my{}, nx{};
+  CopyD my{};
   uint32_t ng = 0;
+  PieceD pd{};
   if (lane < cnt) {
-    my = load_piece(A, c0 + lane);
-    const uint64_t j0 = (my.poff + 15) >> 4, j1 = (my.poff + my.plen + 15) >> 4;
-    ng = (uint32_t)((j1 - j0 + 3) >> 2);
+    pd = load_piece(A, c0 + lane);
+    my = copy_desc(pd);
+    ng = (my.nw + 3) >> 2;
   }
   // the next piece of every lane's piece: from the next lane, or loaded for
   // the chunk's last piece
+  CopyE nx;
   {
-    PieceD up;
-    up.src = __shfl_down(my.src, 1);
-    up.poff = __shfl_down(my.poff, 1);
-    up.L = __shfl_down(my.L, 1);
-    up.cb = __shfl_down(my.cb, 1);
-    up.rlen = __shfl_down(my.rlen, 1);
-    up.plen = __shfl_down(my.plen, 1);
-    up.rev = __shfl_down(my.rev, 1);
-    nx = up;
-    if (lane == cnt - 1 && c0 + lane + 1 < n_e) nx = load_piece(A, c0 + lane + 1);
+    const CopyE mine = copy_next(pd);
+    nx.src = __shfl_down(mine.src, 1);
+    nx.rlen = __shfl_down(mine.rlen, 1);
+    nx.info = __shfl_down(mine.info, 1);
+    if (lane == cnt - 1 && c0 + lane + 1 < n_e) nx = copy_next(load_piece(A, c0 + lane + 1));
   }
   const uint32_t gincl = wave_incl_scan(ng);
   const uint32_t gstart = gincl - ng;
   const uint32_t G = __shfl(gincl, kWave - 1);
-  for (uint32_t base = 0; base < G; base += kWave) {
-    const uint32_t g = base + lane;
-    // piece of group g: the last lane t with gstart[t] <= g (gstart is
-    // non-decreasing and equals G from lane cnt on, so t < cnt when g < G).
-    // Six fixed steps, every lane shuffling in every step: a shuffle must
-    // never run with part of the wave switched off.
-    int t = 0;
-#pragma unroll
-    for (int step = kWave / 2; step > 0; step >>= 1) {
-      const uint32_t sm = __shfl(gstart, t + step);
-      if (sm <= g) t += step;
+  constexpr uint32_t kStep = kWave * kCopyUnroll;
+  CopyStage S0, S1;
+  if (G > 0) copy_fetch(S0, 0, G, gstart, my, nx, seq, nwords, lane);
+  for (uint32_t gb = 0; gb < G; gb += 2 * kStep) {
+    if (gb + kStep < G) copy_fetch(S1, gb + kStep, G, gstart, my, nx, seq, nwords, lane);
+    copy_emit(S0, A, c0, n_e, seq, nwords, bases);
+    if (gb + kStep < G) {
+      if (gb + 2 * kStep < G) copy_fetch(S0, gb + 2 * kStep, G, gstart, my, nx, seq, nwords, lane);
+      copy_emit(S1, A, c0, n_e, seq, nwords, bases);
     }
-    PieceD d;
-    d.src = __shfl(my.src, t);
-    d.poff = __shfl(my.poff, t);
-    d.L = __shfl(my.L, t);
-    d.cb = __shfl(my.cb, t);
-    d.rlen = __shfl(my.rlen, t);
-    d.plen = __shfl(my.plen, t);
-    d.rev = __shfl(my.rev, t);
-    PieceD e;
-    e.src = __shfl(nx.src, t);
-    e.rlen = __shfl(nx.rlen, t);
-    e.plen = __shfl(nx.plen, t);
-    e.rev = __shfl(nx.rev, t);
-    const uint32_t gs = __shfl(gstart, t);
-    if (g >= G) continue;
-    const uint64_t j0 = (d.poff + 15) >> 4, j1 = (d.poff + d.plen + 15) >> 4;
-    const uint64_t w4 = j0 + 4 * (uint64_t)(g - gs);
-    const int nw = j1 - w4 < 4 ? (int)(j1 - w4) : 4;
-    const uint64_t pos = w4 << 4;
-    uint64_t end = (w4 + nw) << 4;
-    if (end > d.L) end = d.L;
-    const uint64_t pend = d.poff + d.plen;  // first base after this piece
-    // part 1 from this piece, part 2 from the next one
-    const int k1 = (int)((end < pend ? end : pend) - pos);
-    uint64_t e_end = end;
-    const uint64_t nend = pend + e.plen;
-    if (e_end > nend) e_end = nend;
-    const int k2 = end > pend ? (int)(e_end - pend) : 0;
-    uint32_t w1[5], w2[5];
-    const uint64_t b1 = piece_src(d, pos - d.poff, k1);
-    load5(seq, nwords, b1 >> 4, w1);
-    uint64_t b2 = 0;
-    if (k2 > 0) {
-      e.poff = pend;
-      b2 = piece_src(e, 0, k2);
-      load5(seq, nwords, b2 >> 4, w2);
-    }
-    u128 acc = extract_bases(w1, (int)(b1 & 15), k1, d.rev != 0);
-    int filled = k1;
-    if (k2 > 0) {
-      acc |= extract_bases(w2, (int)(b2 & 15), k2, e.rev != 0) << (2 * filled);
-      filled += k2;
-      // a third and further pieces (pieces shorter than a group)
-      uint64_t at = nend;
-      int32_t pp = c0 + t + 1;
-      while (at < end && pp + 1 < n_e) {
-        const PieceD f = load_piece(A, pp + 1);
-        ++pp;
-        uint64_t fe = at + f.plen;
-        if (fe > end) fe = end;
-        const int k3 = (int)(fe - at);
-        if (k3 <= 0) break;
-        uint32_t w3[5];
-        const uint64_t b3 = piece_src(f, 0, k3);
-        load5(seq, nwords, b3 >> 4, w3);
-        acc |= extract_bases(w3, (int)(b3 & 15), k3, f.rev != 0) << (2 * filled);
-        filled += k3;
-        at = fe;
-      }
-    }
-    CG_GLOBAL uint32_t *o = bases + d.cb + w4;
-    for (int i = 0; i < nw; ++i) o[i] = (uint32_t)(acc >> (32 * i));
   }
 }
 

@@ -737,7 +737,7 @@ __device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
                       J.s.piece_len, J.g.read_off, J.g.read_len, J.out.len, J.out.base_off);
 }
 
-__global__ void kb_copy(BatchDev B) {
+__global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
