@@ -118,7 +118,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g", "serve"])
+    ap.add_argument("--requests", type=int, default=500, help="serve: measured requests")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests on the GPU")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle's CPU baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -151,6 +153,9 @@ def main():
     import torch
 
     from paper_2207_04350_amd import cg
+
+    if args.workload == "serve":
+        return serve_bench(args)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -347,6 +352,85 @@ def main():
             "seconds": spent}
         result["parity_sample"] = {"graphs": done, "identical": ok}
         log("oracle: %d graphs in %.1fs, parity %d/%d" % (done, spent, ok, done))
+    print(json.dumps(result), flush=True)
+
+
+def serve_bench(args):
+    """Continuous-batching serving of contig-generation requests: a pool of
+    synthetic request graphs (genome 1-100 Mbp log-uniform, 15-30x, reads
+    LN(12k, 4k), 1-2% branch edges, P = 64), a seeded Poisson stream sampling
+    the pool at the rate that keeps the GPU busy about 80% of the time, and
+    p50 / p99 latency from arrival to the result in host memory."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2207_04350_amd import cg, serve
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cg.lib()
+    t0 = time.time()
+    n_pool = 48
+    pool = [serve.HostGraph(synth.simulate(**p)) for p in synth.request_params(n_pool)]
+    log("request pool: %d graphs (%.1f M reads, %.1f GB packed reads) in %.1fs" % (
+        n_pool, sum(h.n for h in pool) / 1e6, sum(h.seq_words for h in pool) * 4 / 1e9,
+        time.time() - t0))
+    srv = serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64, slots=args.slots)
+
+    def stream(n, rate, seed, offset=0):
+        r = np.random.default_rng(seed)
+        pick = r.integers(0, n_pool, size=n)
+        arr = serve.poisson_arrivals(n, rate, seed + 1) if rate else np.zeros(n)
+        return [serve.Request(offset + i, pool[k], 64, 2, float(t))
+                for i, (k, t) in enumerate(zip(pick, arr))]
+
+    # service time of each pool graph alone (also the warm-up)
+    srv1 = serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64, slots=1)
+    alone, _, _ = srv1.run([serve.Request(i, h, 64, 2, 0.0) for i, h in enumerate(pool)])
+    srv1.close()
+    svc = np.array([q.t_done - q.t_admit for q in alone])
+    rate = 0.8 / svc.mean()
+    log("alone: mean service %.2f ms -> arrival rate %.1f requests/s" % (1e3 * svc.mean(), rate))
+    n_warm = max(args.requests // 10, 10)
+    busy = 0.0
+    for attempt in range(2):
+        reqs, span, peak = srv.run(stream(n_warm + args.requests, rate, 20220709 + attempt))
+        busy = serve.busy_fraction(reqs, span)
+        log("rate %.1f/s: busy %.2f over %.2fs" % (rate, busy, span))
+        if abs(busy - 0.8) <= 0.05:
+            break
+        rate *= 0.8 / max(busy, 0.05)
+    meas = sorted(reqs, key=lambda q: q.rid)[n_warm:]
+    lat = np.array([q.t_done - q.arrival for q in meas])
+    bases = sum(int(q.result["len"].sum()) for q in meas)
+    t_span = max(q.t_done for q in meas) - min(q.arrival for q in meas)
+    bad = sum(q.result["status"] != 0 for q in meas)
+    srv.close()
+    result = {
+        "metric": "contig bases/s (serving, continuous batching)",
+        "value": bases / t_span,
+        "unit": "contig bases/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "busy_fraction": busy,
+        "rate_per_s": rate,
+        "requests": len(meas),
+        "warmup_requests": n_warm,
+        "slots": args.slots,
+        "budget_bytes": srv.budget,
+        "peak_admitted_bytes": int(peak),
+        "device_status_errors": int(bad),
+        "alone_service_ms": {"mean": float(svc.mean() * 1e3), "max": float(svc.max() * 1e3)},
+        "dtype": "int32",
+        "data": "synthetic (seeded simulated genomes and reads; exact reduced string graphs)",
+        "config": {"workload": "serving: Poisson stream over a pool of %d request graphs (genome "
+                               "1-100 Mbp log-uniform, 15-30x, reads LN(12k, 4k), 1-2%% branch "
+                               "edges, P = 64)" % n_pool,
+                   "latency": "arrival to contigs in pinned host memory (upload, all five "
+                              "steps, download included)"},
+    }
     print(json.dumps(result), flush=True)
 
 

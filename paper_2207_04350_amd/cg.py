@@ -218,6 +218,24 @@ class DeviceGraph:
         self.device = torch.device(device)
 
 
+    @classmethod
+    def from_tensors(cls, n, m, t, seq_words, device="cuda"):
+        """A resident graph from device tensors already in place (keys row_ptr,
+        col, ovl, strand, read_len, read_off, seq; unsigned arrays as
+        same-width signed tensors)."""
+        import torch
+        self = cls.__new__(cls)
+        self.n, self.m = int(n), int(m)
+        for k in ("row_ptr", "col", "ovl", "strand", "read_len", "read_off", "seq"):
+            setattr(self, k, t[k])
+        self.seq_words = int(seq_words)
+        self.struct = CgGraph(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.ovl),
+                              _ptr(self.strand), _ptr(self.read_len), _ptr(self.read_off),
+                              _ptr(self.seq), self.seq_words)
+        self.device = torch.device(device)
+        return self
+
+
 class Outputs:
     """Every output buffer of the five calls for one graph (upper-bound sized)."""
 
