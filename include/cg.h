@@ -81,6 +81,20 @@ extern "C" {
  *   seq       uint32[seq_words]: 2-bit packed bases, 16 per word, base i of the
  *             store at bits 2*(i%16) of word i/16; A=0 C=1 G=2 T=3, so the
  *             complement of a base is x^3.
+ *   pre, post optional uint32[m] each (both NULL or both set): the per-entry
+ *             values of Section 4.4, in the stored coordinates of each read.
+ *             For entry e = (u,v), pre[e] is the last base of read u before
+ *             its overlap with v and post[e] the first base of read v inside
+ *             it, both in the direction the walk takes the read (increasing
+ *             for a forward read, decreasing for a reverse-complemented one).
+ *             They carry alignment overhangs (an x-drop alignment may stop
+ *             short of a read's end).  With both NULL they follow from ovl:
+ *             pre = len(u)-ovl-1 or ovl, post = 0 or len(v)-1.  A read's
+ *             piece runs from post of the entry it is entered by to pre of
+ *             the entry it leaves by (its whole first / last part for the
+ *             walk's first / last read); a piece whose end falls before its
+ *             start is empty.  cg_validate checks pre[e] < read_len[u] and
+ *             post[e] < read_len[v].
  */
 typedef struct {
   int32_t n;
@@ -93,6 +107,8 @@ typedef struct {
   const uint64_t *read_off;
   const uint32_t *seq;
   uint64_t seq_words;
+  const uint32_t *pre;
+  const uint32_t *post;
 } cg_graph;
 
 /*

@@ -64,13 +64,27 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
+def _pre_post(g):
+    """The graph's explicit pre/post arrays (Section 4.4) as uint32 arrays, or
+    None; the caller keeps them referenced while C reads them."""
+    pre, post = getattr(g, "pre", None), getattr(g, "post", None)
+    if pre is None:
+        return None
+    return _c(pre, np.uint32), _c(post, np.uint32)
+
+
+def _pp_args(pp):
+    return (ctypes.c_void_p(0), ctypes.c_void_p(0)) if pp is None else (_p(pp[0]), _p(pp[1]))
+
+
 def validate(g):
     why = np.zeros(1, np.int32)
+    pp = _pre_post(g)
     bad = _lib().cgo_validate(_i32(g.n), _i32(g.m), _p(_c(g.row_ptr, np.int32)),
                               _p(_c(g.col, np.int32)), _p(_c(g.ovl, np.uint32)),
                               _p(_c(g.strand, np.uint8)), _p(_c(g.read_len, np.uint32)),
                               _p(_c(g.read_off, np.uint64)), ctypes.c_uint64(g.seq.shape[0]),
-                              _p(why))
+                              *_pp_args(pp), _p(why))
     return int(bad), int(why[0])
 
 
@@ -155,10 +169,11 @@ def assemble(g, parts, local, cap_words=None):
     layout_rev = np.zeros(max(n_e, 1), np.uint8)
     bases = np.zeros(max(cap_words, 1), np.uint32)
     total = np.zeros(1, np.uint64)
+    pp = _pre_post(g)
     rc = _lib().cgo_assemble(
         _i32(g.n), _p(_c(g.row_ptr, np.int32)), _p(_c(g.col, np.int32)), _p(_c(g.ovl, np.uint32)),
         _p(_c(g.strand, np.uint8)), _p(_c(g.read_len, np.uint32)), _p(_c(g.read_off, np.uint64)),
-        _p(_c(g.seq, np.uint32)), _i32(nc), _p(_c(parts["comp_label"], np.int32)),
+        _p(_c(g.seq, np.uint32)), *_pp_args(pp), _i32(nc), _p(_c(parts["comp_label"], np.int32)),
         _p(_c(parts["comp_size"], np.int32)), _p(_c(parts["comp_kind"], np.uint8)),
         _p(_c(parts["comp_bin"], np.int32)), _p(_c(parts["comp_rank"], np.int32)),
         _p(_c(parts["comp_start"], np.int32)), _p(_c(local["perm"], np.int32)),

@@ -24,7 +24,8 @@ static int64_t find_entry(const int32_t *row_ptr, const int32_t *col, int32_t u,
 
 int64_t cgo_validate(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
                      const uint32_t *ovl, const uint8_t *strand, const uint32_t *read_len,
-                     const uint64_t *read_off, uint64_t seq_words, int32_t *why)
+                     const uint64_t *read_off, uint64_t seq_words, const uint32_t *pre,
+                     const uint32_t *post, int32_t *why)
 {
     *why = 0;
     if (n < 0 || m < 0 || row_ptr[0] != 0 || row_ptr[n] != m) { *why = 1; return -2; }
@@ -50,6 +51,9 @@ int64_t cgo_validate(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t
             if ((strand[t] & 3) != want || (strand[j] & ~3u)) { *why = 7; return j; }
             uint32_t lmin = read_len[u] < read_len[v] ? read_len[u] : read_len[v];
             if (ovl[j] < 1 || ovl[j] >= lmin) { *why = 8; return j; }
+            /* Section 4.4: pre indexes read u, post indexes read v */
+            if (pre && pre[j] >= read_len[u]) { *why = 12; return j; }
+            if (post && post[j] >= read_len[v]) { *why = 13; return j; }
         }
     }
     return -1;
@@ -305,9 +309,33 @@ static uint64_t emit_piece(const uint32_t *seq, uint64_t off, int64_t i, int64_t
     return at;
 }
 
+/* The piece of the t-th read v of a walk of q reads, oriented o, as stored
+ * indices [from .. to] (increasing for o = 0, decreasing for o = 1; an
+ * empty piece when to lies before from).  Section 4.4: the piece runs from
+ * post(e_{t-1}), the first base of v inside its overlap with the
+ * predecessor, to pre(e_t), the last base of v before its overlap with the
+ * successor; alpha / beta (the read's first / last base in walking order)
+ * stand in at the walk's ends.  Without explicit values they follow from the
+ * overlap length: post = 0 or |l|-1 and pre = |l|-ovl-1 or ovl. */
+static void piece_bounds(int32_t t, int32_t q, int o, int32_t v, const int32_t *edge,
+                         const uint32_t *ovl, const uint32_t *read_len, const uint32_t *pre,
+                         const uint32_t *post, int64_t *from, int64_t *to)
+{
+    int64_t L = (int64_t)read_len[v];
+    if (t == 0) *from = o == 0 ? 0 : L - 1;                    /* alpha */
+    else if (post) *from = (int64_t)post[edge[t - 1]];
+    else *from = o == 0 ? 0 : L - 1;
+    if (t == q - 1) *to = o == 0 ? L - 1 : 0;                  /* beta */
+    else if (pre) *to = (int64_t)pre[edge[t]];
+    else {
+        int64_t ov = (int64_t)ovl[edge[t]];
+        *to = o == 0 ? L - ov - 1 : ov;
+    }
+}
+
 int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *ovl,
                      const uint8_t *strand, const uint32_t *read_len, const uint64_t *read_off,
-                     const uint32_t *seq, int32_t n_comp, const int32_t *comp_label,
+                     const uint32_t *seq, const uint32_t *pre, const uint32_t *post, int32_t n_comp, const int32_t *comp_label,
                      const int32_t *comp_size, const uint8_t *comp_kind, const int32_t *comp_bin,
                      const int32_t *comp_rank, const int32_t *comp_start, const int32_t *perm,
                      const int32_t *loc_row_ptr, const int32_t *loc_col, const int32_t *loc_eid,
@@ -395,30 +423,15 @@ int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, cons
                 int o;
                 if (t == 0) o = q > 1 ? (strand[edge[lo]] & 1) : 0;
                 else o = (strand[edge[lo + t - 1]] >> 1) & 1;
-                int64_t L = (int64_t)read_len[v];
-                /* first index: alpha for the start root, post(e_{t-1}) later:
-                 * the first base of v that overlaps its predecessor, i.e. 0 or
-                 * |l|-1 depending on the orientation */
-                int64_t from = o == 0 ? 0 : L - 1;
-                /* last index: pre(e_t) = last base of v before its overlap
-                 * with the successor (inclusive indexing), or beta for the
-                 * final read.  Reading: pre is taken in v's walking
-                 * orientation; an entry whose s bit disagrees (a same-end
-                 * join, not a valid walk) is flagged and cut the same way. */
-                int64_t to;
-                if (t < q - 1) {
-                    int32_t e = edge[lo + t];
-                    int64_t ov = (int64_t)ovl[e];
-                    if ((int)(strand[e] & 1) != o) cflags |= CGO_SAME_END_JOIN;
-                    to = o == 0 ? L - ov - 1 : ov;
-                } else {
-                    to = o == 0 ? L - 1 : 0;
-                }
+                int64_t from, to;
+                piece_bounds(t, q, o, v, edge + lo, ovl, read_len, pre, post, &from, &to);
+                if (t < q - 1 && (int)(strand[edge[lo + t]] & 1) != o) cflags |= CGO_SAME_END_JOIN;
                 if (pass == 1) {
                     layout_vid[lo + t] = v;
                     layout_rev[lo + t] = (uint8_t)o;
                 }
-                total += (uint64_t)((o == 0 ? to - from : from - to) + 1);
+                int64_t plen = (o == 0 ? to - from : from - to) + 1;
+                total += (uint64_t)(plen > 0 ? plen : 0);
             }
             if (pass == 0) {
                 rec_label[k] = comp_label[c];
@@ -438,14 +451,8 @@ int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, cons
                 for (int32_t t = 0; t < q; ++t) {
                     int32_t v = perm[walk[lo + t]];
                     int o = layout_rev[lo + t];
-                    int64_t L = (int64_t)read_len[v];
-                    int64_t from = o == 0 ? 0 : L - 1, to;
-                    if (t < q - 1) {
-                        int64_t ov = (int64_t)ovl[edge[lo + t]];
-                        to = o == 0 ? L - ov - 1 : ov;
-                    } else {
-                        to = o == 0 ? L - 1 : 0;
-                    }
+                    int64_t from, to;
+                    piece_bounds(t, q, o, v, edge + lo, ovl, read_len, pre, post, &from, &to);
                     at = emit_piece(seq, read_off[v], from, to, o, buf, at);
                 }
                 uint64_t base = rec_base_off[k] / 16;

@@ -28,12 +28,14 @@ extern "C" {
 enum { CGO_SINGLE = 0, CGO_PATH = 1, CGO_CYCLE = 2 };
 enum { CGO_CIRCULAR = 1, CGO_SAME_END_JOIN = 2, CGO_SINGLE_READ = 4 };
 
-/* Input checks (string matrix symmetric, twin strand bits, overlap bounds).
+/* Input checks (string matrix symmetric, twin strand bits, overlap bounds,
+ * and, when given, pre/post inside their reads).
  * Returns -1 when valid, else the index of the first offending entry (or
  * vertex, or -2 for a bad row_ptr frame); *why receives a reason code. */
 int64_t cgo_validate(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col,
                      const uint32_t *ovl, const uint8_t *strand, const uint32_t *read_len,
-                     const uint64_t *read_off, uint64_t seq_words, int32_t *why);
+                     const uint64_t *read_off, uint64_t seq_words, const uint32_t *pre,
+                     const uint32_t *post, int32_t *why);
 
 /* Branch removal (Section 4.2): degree = nonzeros in the row; branch <=>
  * degree >= 3; an entry survives in L iff neither endpoint is a branch.
@@ -81,13 +83,16 @@ void cgo_induce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uin
 /* Local assembly (Section 4.4): for every eligible component in (bin, label)
  * order, walk its chain from the start root and concatenate the read pieces
  * l_r[alpha:pre(e0)] + l_c1[post(e0):pre(e1)] + ... + l_r'[post(e_{q-2}):beta].
- * Contig k (in (bin, label) order) is written 2-bit packed at base offset
+ * pre / post (per entry, stored coordinates) may be NULL: then they follow
+ * from the overlap lengths.  A piece whose end lies before its start is
+ * empty.  Contig k (in (bin, label) order) is written 2-bit packed at base offset
  * rec_base_off[k] (exclusive prefix of 16*ceil(len/16)); padding bits are 0.
  * Returns 0, or -4 when the contigs need more than cap_words words (then only
  * *total_words and the records are written). */
 int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *ovl,
                      const uint8_t *strand, const uint32_t *read_len, const uint64_t *read_off,
-                     const uint32_t *seq, int32_t n_comp, const int32_t *comp_label,
+                     const uint32_t *seq, const uint32_t *pre, const uint32_t *post,
+                     int32_t n_comp, const int32_t *comp_label,
                      const int32_t *comp_size, const uint8_t *comp_kind, const int32_t *comp_bin,
                      const int32_t *comp_rank, const int32_t *comp_start, const int32_t *perm,
                      const int32_t *loc_row_ptr, const int32_t *loc_col, const int32_t *loc_eid,

@@ -27,7 +27,7 @@ _vp = ctypes.c_void_p
 class CgGraph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("row_ptr", _vp), ("col", _vp),
                 ("ovl", _vp), ("strand", _vp), ("read_len", _vp), ("read_off", _vp),
-                ("seq", _vp), ("seq_words", ctypes.c_uint64)]
+                ("seq", _vp), ("seq_words", ctypes.c_uint64), ("pre", _vp), ("post", _vp)]
 
 
 class CgParts(ctypes.Structure):
@@ -212,26 +212,33 @@ class DeviceGraph:
                              None, device)
         self.seq = _dev(g.seq.astype(np.uint32), None, device)
         self.seq_words = int(g.seq.shape[0])
+        # optional per-entry pre/post (Section 4.4), else derived from ovl
+        pre, post = getattr(g, "pre", None), getattr(g, "post", None)
+        self.pre = self.post = None
+        if pre is not None:
+            z = lambda a: a.astype(np.uint32) if g.m else np.zeros(1, np.uint32)
+            self.pre, self.post = _dev(z(pre), None, device), _dev(z(post), None, device)
         self.struct = CgGraph(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.ovl),
                               _ptr(self.strand), _ptr(self.read_len), _ptr(self.read_off),
-                              _ptr(self.seq), self.seq_words)
+                              _ptr(self.seq), self.seq_words, _ptr(self.pre), _ptr(self.post))
         self.device = torch.device(device)
 
 
     @classmethod
     def from_tensors(cls, n, m, t, seq_words, device="cuda"):
         """A resident graph from device tensors already in place (keys row_ptr,
-        col, ovl, strand, read_len, read_off, seq; unsigned arrays as
-        same-width signed tensors)."""
+        col, ovl, strand, read_len, read_off, seq and optionally pre, post;
+        unsigned arrays as same-width signed tensors)."""
         import torch
         self = cls.__new__(cls)
         self.n, self.m = int(n), int(m)
         for k in ("row_ptr", "col", "ovl", "strand", "read_len", "read_off", "seq"):
             setattr(self, k, t[k])
+        self.pre, self.post = t.get("pre"), t.get("post")
         self.seq_words = int(seq_words)
         self.struct = CgGraph(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.ovl),
                               _ptr(self.strand), _ptr(self.read_len), _ptr(self.read_off),
-                              _ptr(self.seq), self.seq_words)
+                              _ptr(self.seq), self.seq_words, _ptr(self.pre), _ptr(self.post))
         self.device = torch.device(device)
         return self
 

@@ -49,6 +49,7 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
   L.walk = take(4 * 16 * (size_t)nn);
   L.estart = take(4 * (size_t)nn);
   L.memb = take(4 * (size_t)nn);
+  L.piece_skip = take(4 * (size_t)nn);
   L.total = at;
   return L;
 }
@@ -70,6 +71,7 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   s->walk = (int32_t *)(b + L.walk);
   s->estart = (int32_t *)(b + L.estart);
   s->memb = (int32_t *)(b + L.memb);
+  s->piece_skip = (uint32_t *)(b + L.piece_skip);
   return true;
 }
 
@@ -114,6 +116,8 @@ static int check_graph(const cg_graph *g, bool need_seq) {
     return set_error(CG_EINVAL, "col/ovl/strand is NULL");
   if (need_seq && g->n > 0 && (!g->read_len || !g->read_off || !g->seq))
     return set_error(CG_EINVAL, "read_len/read_off/seq is NULL");
+  if ((g->pre == nullptr) != (g->post == nullptr))
+    return set_error(CG_EINVAL, "pre and post must both be given or both be NULL");
   return CG_OK;
 }
 

@@ -517,6 +517,7 @@ __device__ __forceinline__ void walk_component(
   int32_t *R_vid = out.layout_vid + st;
   uint8_t *R_rev = out.layout_rev + st;
   uint32_t *R_len = s.piece_len + st;
+  uint32_t *R_skip = s.piece_skip + st;
   const int rank_c = parts.comp_rank[c];
   for (int i = tid; i < q; i += kWalkBlock) {
     int rank = 0, pred = -1, succ = -1, succ_e = -1;
@@ -535,23 +536,36 @@ __device__ __forceinline__ void walk_component(
     }
     const int32_t v = perm[st + i];
     int orient;
+    int pe = -1;  // the entry pred -> i, read in pred's row
     if (i == s0) {
       orient = succ_e >= 0 ? (g.strand[succ_e] & 1) : 0;
     } else if (pred >= 0) {
-      // the entry pred -> i, read in pred's row
-      const int pe = w.nb[2 * pred] == i ? w.eid[2 * pred] : w.eid[2 * pred + 1];
+      pe = w.nb[2 * pred] == i ? w.eid[2 * pred] : w.eid[2 * pred + 1];
       orient = (g.strand[pe] >> 1) & 1;
     } else {
       orient = 0;  // unreachable for a chain: every read but the start has a predecessor
     }
-    uint32_t plen = g.read_len[v];
-    if (succ_e >= 0) {
+    // the piece: walking offsets [skip, end] of the read (Section 4.4: from
+    // post of the entering entry to pre of the leaving one, in stored
+    // coordinates; from overlap lengths: the read minus its overlap with the
+    // successor)
+    const uint32_t L = g.read_len[v];
+    uint32_t skip = 0, plen = L;
+    if (g.pre) {
+      const int64_t first = pe >= 0 ? (orient ? (int64_t)L - 1 - g.post[pe] : g.post[pe]) : 0;
+      const int64_t last = succ_e >= 0
+                               ? (orient ? (int64_t)L - 1 - g.pre[succ_e] : g.pre[succ_e])
+                               : (int64_t)L - 1;
+      skip = (uint32_t)first;
+      plen = last >= first ? (uint32_t)(last - first + 1) : 0u;
+    } else if (succ_e >= 0) {
       plen -= g.ovl[succ_e];
-      if ((int)(g.strand[succ_e] & 1) != orient) s_sej = 1;
     }
+    if (succ_e >= 0 && (int)(g.strand[succ_e] & 1) != orient) s_sej = 1;
     R_vid[rank] = v;
     R_rev[rank] = (uint8_t)orient;
     R_len[rank] = plen;
+    R_skip[rank] = skip;
     s.lay_contig[st + rank] = rank_c;
     (void)succ;
   }
@@ -581,116 +595,12 @@ __device__ __forceinline__ void walk_component(
   __syncthreads();
 }
 
-// k bases (1..16) starting at base index b of the store, LSB first; words
-// past the end of the store read as zero
-__device__ __forceinline__ uint32_t fetch_bases(const uint32_t *__restrict__ seq, uint64_t nwords,
-                                                uint64_t b, int k) {
-  const uint64_t wi = b >> 4;
-  const int sh = (int)(b & 15) * 2;
-  uint64_t x = wi < nwords ? seq[wi] : 0u;
-  if (sh + 2 * k > 32 && wi + 1 < nwords) x |= (uint64_t)seq[wi + 1] << 32;
-  x >>= sh;
-  return k == 16 ? (uint32_t)x : (uint32_t)x & ((1u << (2 * k)) - 1u);
-}
-
-// reverse the order of the k low 2-bit fields and complement them
-__device__ __forceinline__ uint32_t revcomp_fields(uint32_t x, int k) {
-  uint32_t y = __builtin_bitreverse32(x);
-  y = ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
-  y >>= 32 - 2 * k;
-  return y ^ (k == 16 ? 0xFFFFFFFFu : ((1u << (2 * k)) - 1u));
-}
-
-// Output words of one piece (Section 4.4: the piece is the part of a read, in
-// its walking orientation, that the contig keeps).  A word belongs to the
-// piece that holds its first base; if the word runs past the piece it takes
-// its remaining bases from the following pieces of the same contig, so every
-// word has exactly one writer.  Lanes lane, lane + stride, ... take the
-// piece's words in turn.
-__device__ __forceinline__ void copy_piece(
-    const uint32_t *__restrict__ seq, uint64_t seq_words, const uint32_t *__restrict__ read_len,
-    const uint64_t *__restrict__ read_off, const int32_t *__restrict__ layout_vid,
-    const uint8_t *__restrict__ layout_rev, const uint64_t *__restrict__ piece_off,
-    const uint32_t *__restrict__ piece_len, const int32_t *__restrict__ lay_contig,
-    const uint64_t *__restrict__ clen, const uint64_t *__restrict__ cbase, int32_t n_e, int32_t p,
-    uint32_t *__restrict__ bases, int lane, int stride) {
-  const int32_t k = lay_contig[p];
-  const uint64_t L = clen[k];
-  const uint64_t cb = cbase[k] >> 4;
-  const uint64_t poff = piece_off[p];
-  const uint32_t plen = piece_len[p];
-  const uint64_t j0 = (poff + 15) >> 4, j1 = (poff + plen + 15) >> 4;
-  for (uint64_t j = j0 + lane; j < j1; j += stride) {
-    uint64_t pos = j << 4;
-    int32_t pp = p;
-    uint64_t o_off = poff;
-    uint32_t o_len = plen;
-    int32_t v = layout_vid[pp];
-    int rev = layout_rev[pp];
-    uint32_t out = 0;
-    int filled = 0;
-    while (filled < 16 && pos < L) {
-      while (pos >= o_off + o_len && pp + 1 < n_e) {  // continue into the next piece
-        o_off += o_len;
-        ++pp;
-        o_len = piece_len[pp];
-        v = layout_vid[pp];
-        rev = layout_rev[pp];
-      }
-      const uint64_t t = pos - o_off;
-      const uint64_t avail = o_off + o_len > pos ? o_off + o_len - pos : 0;
-      int kk = 16 - filled;
-      if (avail < (uint64_t)kk) kk = (int)avail;
-      if (kk <= 0) break;  // only on inconsistent pieces
-      uint32_t x;
-      if (!rev) {
-        x = fetch_bases(seq, seq_words, read_off[v] + t, kk);
-      } else {
-        const uint64_t Lr = read_len[v];
-        x = revcomp_fields(fetch_bases(seq, seq_words, read_off[v] + Lr - t - kk, kk), kk);
-      }
-      out |= x << (2 * filled);
-      filled += kk;
-      pos += kk;
-    }
-    bases[cb + j] = out;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Packed base copy, 64 bases (four output words) per lane.
+// Packed base copy
 // ---------------------------------------------------------------------------
-typedef unsigned __int128 u128;
-
-// up to 64 bases (k >= 1) starting at base index b of the store, LSB first;
-// words past the end of the store read as zero
-__device__ __forceinline__ u128 fetch_bases64(const CG_GLOBAL uint32_t *__restrict__ seq,
-                                              uint64_t nwords, uint64_t b, int k) {
-  const uint64_t w0 = b >> 4;
-  const int sh = (int)(b & 15) * 2;
-  const int nw = (sh + 2 * k + 31) >> 5;  // words touched, 1..5
-  uint32_t w[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) w[i] = (i < nw && w0 + i < nwords) ? seq[w0 + i] : 0u;
-  u128 x = (u128)w[0] | ((u128)w[1] << 32) | ((u128)w[2] << 64) | ((u128)w[3] << 96);
-  x >>= sh;
-  if (sh) x |= (u128)w[4] << (128 - sh);
-  if (k < 64) x &= ((u128)1 << (2 * k)) - 1;
-  return x;
-}
-
 __device__ __forceinline__ uint32_t rev_fields32(uint32_t v) {
   const uint32_t y = __builtin_bitreverse32(v);
   return ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
-}
-
-// reverse the order of the k low 2-bit fields of x and complement them
-__device__ __forceinline__ u128 revcomp_fields64(u128 x, int k) {
-  u128 y = (u128)rev_fields32((uint32_t)(x >> 96)) | ((u128)rev_fields32((uint32_t)(x >> 64)) << 32) |
-           ((u128)rev_fields32((uint32_t)(x >> 32)) << 64) | ((u128)rev_fields32((uint32_t)x) << 96);
-  y >>= 2 * (64 - k);
-  const u128 mask = k == 64 ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
-  return y ^ mask;
 }
 
 // One piece as the copy needs it.
@@ -701,6 +611,7 @@ struct PieceD {
   uint64_t cb;    // first output word of the contig
   uint32_t rlen;  // read length
   uint32_t plen;  // piece length
+  uint32_t skip;  // first base of the piece in the read's walking orientation
   int32_t rev;    // read walked reverse-complemented
 };
 
@@ -710,6 +621,7 @@ struct PieceArrays {
   const CG_GLOBAL uint8_t *layout_rev;
   const CG_GLOBAL uint64_t *piece_off;
   const CG_GLOBAL uint32_t *piece_len;
+  const CG_GLOBAL uint32_t *piece_skip;
   const CG_GLOBAL uint64_t *read_off;
   const CG_GLOBAL uint32_t *read_len;
   const CG_GLOBAL uint64_t *clen;
@@ -721,14 +633,15 @@ __device__ __forceinline__ PieceArrays piece_arrays(const int32_t *lay_contig,
                                                     const uint8_t *layout_rev,
                                                     const uint64_t *piece_off,
                                                     const uint32_t *piece_len,
+                                                    const uint32_t *piece_skip,
                                                     const uint64_t *read_off,
                                                     const uint32_t *read_len, const uint64_t *clen,
                                                     const uint64_t *cbase) {
   return PieceArrays{(const CG_GLOBAL int32_t *)lay_contig,  (const CG_GLOBAL int32_t *)layout_vid,
                      (const CG_GLOBAL uint8_t *)layout_rev,  (const CG_GLOBAL uint64_t *)piece_off,
-                     (const CG_GLOBAL uint32_t *)piece_len,  (const CG_GLOBAL uint64_t *)read_off,
-                     (const CG_GLOBAL uint32_t *)read_len,   (const CG_GLOBAL uint64_t *)clen,
-                     (const CG_GLOBAL uint64_t *)cbase};
+                     (const CG_GLOBAL uint32_t *)piece_len,  (const CG_GLOBAL uint32_t *)piece_skip,
+                     (const CG_GLOBAL uint64_t *)read_off,   (const CG_GLOBAL uint32_t *)read_len,
+                     (const CG_GLOBAL uint64_t *)clen,       (const CG_GLOBAL uint64_t *)cbase};
 }
 
 __device__ __forceinline__ PieceD load_piece(const PieceArrays &A, int32_t p) {
@@ -738,6 +651,7 @@ __device__ __forceinline__ PieceD load_piece(const PieceArrays &A, int32_t p) {
   d.src = A.read_off[v];
   d.rlen = A.read_len[v];
   d.plen = A.piece_len[p];
+  d.skip = A.piece_skip[p];
   d.poff = A.piece_off[p];
   d.rev = A.layout_rev[p];
   d.L = A.clen[k];
@@ -751,87 +665,6 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int t) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ PieceD readlane_piece(const PieceD &d, int t) {
-  PieceD r;
-  r.src = readlane64(d.src, t);
-  r.poff = readlane64(d.poff, t);
-  r.L = readlane64(d.L, t);
-  r.cb = readlane64(d.cb, t);
-  r.rlen = __builtin_amdgcn_readlane(d.rlen, t);
-  r.plen = __builtin_amdgcn_readlane(d.plen, t);
-  r.rev = __builtin_amdgcn_readlane(d.rev, t);
-  return r;
-}
-
-// The output words owned by piece p (those whose first base lies in it),
-// four consecutive words per lane.  A word that runs past the piece takes
-// its remaining bases from the next pieces of the contig: `nxt` (when
-// has_nxt), then pieces loaded from A.
-__device__ __forceinline__ void copy_piece_words(const CG_GLOBAL uint32_t *__restrict__ seq,
-                                                 uint64_t nwords, CG_GLOBAL uint32_t *__restrict__ bases,
-                                                 const PieceD &cur,
-                                                 const PieceD &nxt, bool has_nxt,
-                                                 const PieceArrays &A, int32_t p, int lane) {
-  const uint64_t j0 = (cur.poff + 15) >> 4, j1 = (cur.poff + cur.plen + 15) >> 4;
-  for (uint64_t w4 = j0 + 4 * (uint64_t)lane; w4 < j1; w4 += 4 * kWave) {
-    const int nw = j1 - w4 < 4 ? (int)(j1 - w4) : 4;
-    uint64_t pos = w4 << 4;
-    uint64_t end = (w4 + nw) << 4;
-    if (end > cur.L) end = cur.L;
-    PieceD d = cur;
-    int32_t pp = p;
-    u128 acc = 0;
-    int filled = 0;
-    while (pos < end) {
-      if (pos >= d.poff + d.plen) {  // continue into the next piece
-        const uint64_t at = d.poff + d.plen;
-        d = (pp == p && has_nxt) ? nxt : load_piece(A, pp + 1);
-        d.poff = at;
-        ++pp;
-      }
-      const uint64_t t = pos - d.poff;
-      uint64_t kk = end - pos;
-      if (d.poff + d.plen - pos < kk) kk = d.poff + d.plen - pos;
-      if (kk == 0) break;  // only on inconsistent pieces
-      const int k = (int)kk;
-      const u128 x = d.rev ? revcomp_fields64(fetch_bases64(seq, nwords, d.src + d.rlen - t - k, k), k)
-                           : fetch_bases64(seq, nwords, d.src + t, k);
-      acc |= x << (2 * filled);
-      filled += k;
-      pos += kk;
-    }
-    CG_GLOBAL uint32_t *o = bases + cur.cb + w4;
-    for (int i = 0; i < nw; ++i) o[i] = (uint32_t)(acc >> (32 * i));
-  }
-}
-
-// Five consecutive store words starting at word w (indices clamped into the
-// store, so the loads are unconditional and issue back to back).
-__device__ __forceinline__ void load5(const CG_GLOBAL uint32_t *__restrict__ seq, uint64_t nwords,
-                                      uint64_t w, uint32_t *o) {
-  const uint64_t last = nwords - 1;
-#pragma unroll
-  for (int i = 0; i < 5; ++i) o[i] = seq[w + i < last ? w + i : last];
-}
-
-// k (1..64) bases from five loaded words whose first base sits at field sh
-// of word 0; reverse-complemented when rev.
-__device__ __forceinline__ u128 extract_bases(const uint32_t *w, int sh, int k, bool rev) {
-  u128 x = (u128)w[0] | ((u128)w[1] << 32) | ((u128)w[2] << 64) | ((u128)w[3] << 96);
-  x >>= 2 * sh;
-  if (sh) x |= (u128)w[4] << (128 - 2 * sh);
-  if (k < 64) x &= ((u128)1 << (2 * k)) - 1;
-  return rev ? revcomp_fields64(x, k) : x;
-}
-
-// First stored base of the k bases that start t bases into a piece, in the
-// piece's walking orientation (a reversed piece is read backwards).
-__device__ __forceinline__ uint64_t piece_src(const PieceD &d, uint64_t t, int k) {
-  return d.rev ? d.src + d.rlen - t - (uint64_t)k : d.src + t;
-}
-
-// 16 stored bases starting at base b (any alignment) as one word: a 64-bit
-// funnel shift of two store words (indices clamped into the store).
 // Store word index clamped into [0, nwords - 1]; a window may start before
 // the store (reverse pieces of the first reads) or end after it, and the
 // words it then reads are never used.
@@ -856,12 +689,19 @@ __device__ __forceinline__ uint32_t low_fields(int k) {
   return k >= 16 ? 0xFFFFFFFFu : ((1u << (2 * k)) - 1u);
 }
 
+// Stored base where the 16-base window holding a piece's first 16 bases (in
+// walking orientation) starts: forward at the piece's first base, reverse 15
+// bases below it (the window is then read backwards).
+__device__ __forceinline__ uint64_t head_src(uint64_t src, uint32_t rlen, uint32_t skip, bool rev) {
+  return rev ? src + rlen - 16 - skip : src + skip;
+}
+
 // The first k (<= 16) bases of a piece in walking orientation, in fields 0..k-1
 // (fields above k are not cleared).
 __device__ __forceinline__ uint32_t piece_head16(const CG_GLOBAL uint32_t *__restrict__ seq,
-                                                 uint64_t nwords, uint64_t src, uint32_t rlen,
-                                                 bool rev) {
-  return rev ? revcomp16(window16(seq, nwords, src + rlen - 16)) : window16(seq, nwords, src);
+                                                 uint64_t nwords, const PieceD &f) {
+  const uint32_t x = window16(seq, nwords, head_src(f.src, f.rlen, f.skip, f.rev != 0));
+  return f.rev ? revcomp16(x) : x;
 }
 
 // Copy descriptor of one piece: output words [w0, w0 + nw) of the bases
@@ -878,8 +718,8 @@ struct CopyD {
 };
 // What a word straddling into the next piece needs of it.
 struct CopyE {
-  uint64_t src;
-  uint32_t rlen, info;  // info: plen | reverse << 30 | ends its contig << 31
+  uint64_t hsrc;   // head_src of the piece
+  uint32_t info;   // plen | reverse << 30 | ends its contig << 31
 };
 
 __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
@@ -890,14 +730,14 @@ __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
   c.nw = (uint32_t)(j1 - j0);
   const uint32_t fs = (uint32_t)(pend - 16 * (j1 - 1));
   c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u);
-  c.base = d.rev ? d.src + d.rlen - 64 + d.poff + 16 * d.cb : d.src - d.poff - 16 * d.cb;
+  c.base = d.rev ? d.src + d.rlen - 64 - d.skip + d.poff + 16 * d.cb
+                 : d.src + d.skip - d.poff - 16 * d.cb;
   return c;
 }
 
 __device__ __forceinline__ CopyE copy_next(const PieceD &e) {
   CopyE c;
-  c.src = e.src;
-  c.rlen = e.rlen;
+  c.hsrc = head_src(e.src, e.rlen, e.skip, e.rev != 0);
   c.info = e.plen | (e.rev ? (1u << 30) : 0u) | (e.poff + e.plen == e.L ? (1u << 31) : 0u);
   return c;
 }
@@ -943,8 +783,7 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     S.d[u].w0 = __shfl(my.w0, t);
     S.d[u].nw = __shfl(my.nw, t);
     S.d[u].info = __shfl(my.info, t);
-    S.e[u].src = __shfl(nx.src, t);
-    S.e[u].rlen = __shfl(nx.rlen, t);
+    S.e[u].hsrc = __shfl(nx.hsrc, t);
     S.e[u].info = __shfl(nx.info, t);
     const uint32_t gs = __shfl(gstart, t);
     const uint32_t g = gb + lane + kWave * u;
@@ -965,9 +804,7 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
 #pragma unroll
     for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
     // the next piece's first 16 bases, for the piece's last word
-    const CopyE &e = S.e[u];
-    const uint64_t hb = (e.info & (1u << 30)) ? e.src + e.rlen - 16 : e.src;
-    const int64_t hw = (int64_t)hb >> 4;
+    const int64_t hw = (int64_t)S.e[u].hsrc >> 4;
     S.hlo[u] = seq[clamp_word(hw, nwords)];
     S.hhi[u] = seq[clamp_word(hw + 1, nwords)];
   }
@@ -1000,8 +837,8 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
         const int pl = (int)(e.info & 0x3FFFFFFFu);
         const int k2 = 16 - fs < pl ? 16 - fs : pl;
         const bool erev = e.info & (1u << 30);
-        const uint64_t hb = erev ? e.src + e.rlen - 16 : e.src;
-        uint32_t head = __builtin_amdgcn_alignbit(S.hhi[u], S.hlo[u], 2u * (uint32_t)(hb & 15));
+        uint32_t head =
+            __builtin_amdgcn_alignbit(S.hhi[u], S.hlo[u], 2u * (uint32_t)(e.hsrc & 15));
         if (erev) head = revcomp16(head);
         x |= (head & low_fields(k2)) << (2 * fs);
         int filled = fs + k2;
@@ -1010,7 +847,7 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
           for (int32_t pp = c0 + S.t[u] + 2; filled < 16 && pp < n_e; ++pp) {
             const PieceD f = load_piece(A, pp);
             const int k3 = 16 - filled < (int)f.plen ? 16 - filled : (int)f.plen;
-            const uint32_t y = piece_head16(seq, nwords, f.src, f.rlen, f.rev != 0);
+            const uint32_t y = piece_head16(seq, nwords, f);
             x |= (y & low_fields(k3)) << (2 * filled);
             filled += k3;
             if (f.poff + f.plen == f.L) break;
@@ -1054,8 +891,7 @@ __device__ __forceinline__ void copy_chunk(const uint32_t *seq_, uint64_t nwords
   CopyE nx;
   {
     const CopyE mine = copy_next(pd);
-    nx.src = __shfl_down(mine.src, 1);
-    nx.rlen = __shfl_down(mine.rlen, 1);
+    nx.hsrc = __shfl_down(mine.hsrc, 1);
     nx.info = __shfl_down(mine.info, 1);
     if (lane == cnt - 1 && c0 + lane + 1 < n_e) nx = copy_next(load_piece(A, c0 + lane + 1));
   }

@@ -80,6 +80,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
                                                          const uint8_t *__restrict__ layout_rev,
                                                          const uint64_t *__restrict__ piece_off,
                                                          const uint32_t *__restrict__ piece_len,
+                                                         const uint32_t *__restrict__ piece_skip,
                                                          const int32_t *__restrict__ lay_contig,
                                                          const uint64_t *__restrict__ clen,
                                                          const uint64_t *__restrict__ cbase,
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
   if (*d_total_words > cap_words) return;
   const int32_t n_e = bin_vptr[P];
   const PieceArrays A = piece_arrays(lay_contig, layout_vid, layout_rev, piece_off, piece_len,
-                                     read_off, read_len, clen, cbase);
+                                     piece_skip, read_off, read_len, clen, cbase);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
@@ -123,7 +124,8 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
   CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
                      g.read_len,
                      g.read_off, local.bin_vptr, P, out.layout_vid, out.layout_rev, s.piece_off,
-                     s.piece_len, s.lay_contig, out.len, out.base_off, out.d_total_words,
+                     s.piece_len, s.piece_skip, s.lay_contig, out.len, out.base_off,
+                     out.d_total_words,
                      out.cap_words, out.bases);
   return hip_check(hipGetLastError(), "k_asm");
 }

@@ -734,7 +734,8 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
 // 9. packed copy: waves take chunks of 64 consecutive pieces of the batch
 __device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
   return piece_arrays(J.s.lay_contig, J.out.layout_vid, J.out.layout_rev, J.s.piece_off,
-                      J.s.piece_len, J.g.read_off, J.g.read_len, J.out.len, J.out.base_off);
+                      J.s.piece_len, J.s.piece_skip, J.g.read_off, J.g.read_len, J.out.len,
+                      J.out.base_off);
 }
 
 __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
@@ -777,7 +778,7 @@ static int check_job(const cg_job &J, int i) {
   const cg_graph &g = J.g;
   if (g.n < 0 || g.n >= (1 << 30) || g.m < 0 || !g.row_ptr ||
       (g.m > 0 && (!g.col || !g.ovl || !g.strand)) ||
-      (g.n > 0 && (!g.read_len || !g.read_off || !g.seq)))
+      (g.n > 0 && (!g.read_len || !g.read_off || !g.seq)) || ((g.pre == nullptr) != (g.post == nullptr)))
     return set_error(CG_EINVAL, "job %d: bad graph", i);
   if (J.P < 1 || J.P > 65536) return set_error(CG_EINVAL, "job %d: P=%d outside [1, 65536]", i, J.P);
   const cg_parts &p = J.parts;

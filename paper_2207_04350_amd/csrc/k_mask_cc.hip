@@ -189,6 +189,8 @@ __global__ __launch_bounds__(kValBlock) void k_val_check(cg_graph g, Fixed *fx) 
           uint32_t lu = g.read_len[v], lv = g.read_len[u];
           uint32_t lmin = lu < lv ? lu : lv;
           if (g.ovl[j] < 1 || g.ovl[j] >= lmin) why = 8;
+          else if (g.pre && g.pre[j] >= lu) why = 12;    // pre indexes the row's read
+          else if (g.pre && g.post[j] >= lv) why = 13;   // post the column's read
         }
       }
     }

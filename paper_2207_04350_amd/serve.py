@@ -27,10 +27,11 @@ from . import cg
 # Footprint
 # ---------------------------------------------------------------------------
 
-def graph_bytes(n, m, seq_words):
+def graph_bytes(n, m, seq_words, pre_post=False):
     """Device bytes of a resident graph (as DeviceGraph allocates it)."""
     k, mm = max(n, 1), max(m, 1)
-    return 4 * (n + 1) + mm * (4 + 4 + 1) + k * (4 + 8) + 4 * max(int(seq_words), 1)
+    return (4 * (n + 1) + mm * (4 + 4 + 1 + (8 if pre_post else 0)) + k * (4 + 8)
+            + 4 * max(int(seq_words), 1))
 
 
 def output_bytes(n, P, cap_words):
@@ -48,7 +49,8 @@ def output_bytes(n, P, cap_words):
 def request_footprint(g, P):
     """HBM a request holds while it is admitted (its slot's scratch is not
     counted: slots own theirs for the life of the server)."""
-    return graph_bytes(g.n, g.m, g.seq.shape[0]) + output_bytes(g.n, P, g.seq.shape[0] + g.n)
+    return (graph_bytes(g.n, g.m, g.seq.shape[0], getattr(g, "pre", None) is not None)
+            + output_bytes(g.n, P, g.seq.shape[0] + g.n))
 
 
 # ---------------------------------------------------------------------------
@@ -112,6 +114,9 @@ class HostGraph:
             read_len=pin(u(g.read_len, np.uint32, np.int32) if g.n else np.zeros(1, np.int32)),
             read_off=pin(u(g.read_off, np.uint64, np.int64) if g.n else np.zeros(1, np.int64)),
             seq=pin(u(g.seq, np.uint32, np.int32)))
+        if getattr(g, "pre", None) is not None:
+            z = lambda a: u(a, np.uint32, np.int32) if g.m else np.zeros(1, np.int32)
+            self.t["pre"], self.t["post"] = pin(z(g.pre)), pin(z(g.post))
 
 
 class Request:

@@ -72,6 +72,8 @@ class StringGraph:
     seq: np.ndarray
     truth: dict = field(default_factory=dict)
     meta: dict = field(default_factory=dict)
+    pre: np.ndarray = None     # optional alignment coordinates per entry (uint32[m])
+    post: np.ndarray = None
 
     @property
     def seq_words(self) -> int:
@@ -378,6 +380,48 @@ def request_params(n_req, seed=SEED_BASE + 5):
                         err=0.0, extra_rate=float(r.uniform(0.01, 0.02)), repeats=None, P=64,
                         name="req-%d" % i, seed=int(seed * 1000 + i)))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Alignment coordinates per entry (what an aligner reports for each overlap)
+# ----------------------------------------------------------------------------
+
+def with_alignment_ends(g: StringGraph, rng=None, max_clip: int = 0) -> StringGraph:
+    """A copy of g with explicit per-entry alignment coordinates.
+
+    For entry (u, v) the walk goes along u then v; pre is the stored index of
+    the last base of u before the aligned region and post the stored index of
+    the first aligned base of v, each counted in the direction the walk takes
+    its read (strand bits s, d).  An x-drop alignment may start late: each
+    undirected overlap gets clips (x, y) with x + y < ovl, x applied at the
+    start of the overlap as walked u -> v and y as walked v -> u (the twin
+    entry), so both walks describe the same shortened alignment.  With
+    max_clip = 0 the aligned region is the whole overlap."""
+    import copy
+    rng = rng if rng is not None else np.random.default_rng(0)
+    h = copy.copy(g)
+    pre = np.zeros(g.m, np.uint32)
+    post = np.zeros(g.m, np.uint32)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    clip = {}
+    for e in range(g.m):
+        u, v = int(src[e]), int(g.col[e])
+        key = (min(u, v), max(u, v))
+        ov = int(g.ovl[e])
+        if key not in clip:
+            lim = min(max_clip, (ov - 1) // 2)
+            clip[key] = (int(rng.integers(0, lim + 1)), int(rng.integers(0, lim + 1)))
+        x = clip[key][0] if u < v else clip[key][1]
+        s, d = int(g.strand[e]) & 1, (int(g.strand[e]) >> 1) & 1
+        lu, lv = int(g.read_len[u]), int(g.read_len[v])
+        # in walking coordinates the overlap starts at lu - ov in u and at 0 in v
+        w_pre = lu - ov + x - 1
+        w_post = x
+        pre[e] = w_pre if s == 0 else lu - 1 - w_pre
+        post[e] = w_post if d == 0 else lv - 1 - w_post
+    h.pre, h.post = pre, post
+    h.meta = dict(g.meta, alignment_clip=max_clip)
+    return h
 
 
 # ----------------------------------------------------------------------------

@@ -37,6 +37,11 @@ def _mixed_graphs():
     gs.append(_chain_graph(r, [1500, 40, 2], cycles=[1200, 7]))   # beyond the LDS tiles
     gs.append(_chain_graph(r, [2] * 2500 + [5] * 30))              # beyond the batch LDS sort
     gs.append(_chain_graph(r, [3000, 2900, 2400, 3]))
+    # explicit alignment coordinates: x-drop clips, and arbitrary values
+    from tests.test_oracle_overhangs import _random_pre_post
+    gs.append(synth.with_alignment_ends(synth.config_graph(1), np.random.default_rng(8), 3))
+    ra = np.random.default_rng(18)
+    gs += [_random_pre_post(synth.adversarial(ra), ra) for _ in range(6)]
     # beyond the LDS components pass: with and without one-read components
     gs.append(_chain_graph(r, [6000, 6000, 5000, 2]))
     gs[-1].meta["min_reads"] = 2

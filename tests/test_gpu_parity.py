@@ -177,29 +177,36 @@ def test_capacity_overflow(cg):
 
 def test_validate_matches_oracle(cg):
     import torch
-    from tests.test_oracle_pins import NEGATIVE
+    from tests.test_oracle_pins import NEGATIVE, break_graph
     reads = [np.zeros(10, np.uint8) for _ in range(4)]
     ctx = cg.Context.for_graph(8, 8, 1)
     for case in [None] + sorted(NEGATIVE):
         g = synth.graph_from_edges(reads, [(0, 1, 3, 0, 0), (1, 2, 3, 1, 0)])
-        if case == "asymmetric":
-            g.col = g.col.copy(); g.col[0] = 3
-        elif case == "bad_twin_bits":
-            g.strand = g.strand.copy(); g.strand[0] ^= 1
-        elif case == "ovl_too_long":
-            g.ovl = g.ovl.copy(); g.ovl[:] = 10
-        elif case == "self_loop":
-            g.col = g.col.copy(); g.col[0] = 0
-        elif case == "duplicate":
-            g.col = g.col.copy(); g.col[2] = g.col[1]
-        elif case == "twin_ovl":
-            g.ovl = g.ovl.copy(); g.ovl[0] = 4
-        elif case == "misaligned_read":
-            g.read_off = g.read_off.copy(); g.read_off[1] += 1
+        if case is not None:
+            g = break_graph(g, case)
         _say("validate case", case)
         dg = cg.DeviceGraph(g, "cuda")
         bad = torch.empty(2, dtype=torch.int64, device="cuda")
         cg.validate(ctx, dg, bad)
         got = tuple(int(x) for x in bad.cpu().numpy())
         assert got == oracle.validate(g), case
+    ctx.close()
+
+
+def test_alignment_ends(cg):
+    """Explicit per-entry (pre, post) (Section 4.4): consistent x-drop clips
+    on reads with errors, and arbitrary in-range values (empty pieces,
+    same-end joins) on the adversarial corpus."""
+    from tests.test_oracle_overhangs import _random_pre_post
+    g = synth.with_alignment_ends(synth.config_graph(1), np.random.default_rng(4), max_clip=3)
+    check(cg, g, 8, 2, name="config1-clipped")
+    check(cg, g, 3, 1, name="config1-clipped-singles")
+    rng = np.random.default_rng(12)
+    ctx = cg.Context.for_graph(64, 256, 16)
+    for i in range(150):
+        h = _random_pre_post(synth.adversarial(rng), rng)
+        P, mr = int(rng.integers(1, 9)), int(rng.integers(0, 3))
+        got, _ = run_gpu(cg, h, P, mr, ctx)
+        bad = mismatches(got, oracle.run(h, P=P, min_reads=mr))
+        assert bad == [], (i, bad)
     ctx.close()

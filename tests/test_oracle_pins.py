@@ -309,15 +309,12 @@ def test_config1_invariants():
 
 NEGATIVE = {
     "asymmetric": 5, "bad_twin_bits": 7, "ovl_too_long": 8, "self_loop": 3, "duplicate": 4,
-    "twin_ovl": 6, "misaligned_read": 10,
+    "twin_ovl": 6, "misaligned_read": 10, "pre_outside_read": 12, "post_outside_read": 13,
 }
 
 
-@pytest.mark.parametrize("case", sorted(NEGATIVE))
-def test_validate_rejects(case):
-    reads = [np.zeros(10, np.uint8) for _ in range(4)]
-    g = synth.graph_from_edges(reads, [(0, 1, 3, 0, 0), (1, 2, 3, 1, 0)])
-    assert oracle.validate(g) == (-1, 0)
+def break_graph(g, case):
+    """The negative case `case` planted into a valid 4-read graph."""
     if case == "asymmetric":
         g.col = g.col.copy()
         g.col[0] = 3          # 0->3 has no twin
@@ -339,5 +336,20 @@ def test_validate_rejects(case):
     elif case == "misaligned_read":
         g.read_off = g.read_off.copy()
         g.read_off[1] += 1
+    elif case == "pre_outside_read":
+        g = synth.with_alignment_ends(g)
+        g.pre[0] = g.read_len[0]   # entry 0 is (0, 1): pre indexes read 0
+    elif case == "post_outside_read":
+        g = synth.with_alignment_ends(g)
+        g.post[0] = g.read_len[1]  # post indexes read 1
+    return g
+
+
+@pytest.mark.parametrize("case", sorted(NEGATIVE))
+def test_validate_rejects(case):
+    reads = [np.zeros(10, np.uint8) for _ in range(4)]
+    g = synth.graph_from_edges(reads, [(0, 1, 3, 0, 0), (1, 2, 3, 1, 0)])
+    assert oracle.validate(g) == (-1, 0)
+    g = break_graph(g, case)
     bad, why = oracle.validate(g)
     assert bad != -1 and why == NEGATIVE[case]
