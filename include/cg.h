@@ -62,6 +62,7 @@ extern "C" {
 #define CG_STATUS_BASES_OVERFLOW 1u /* cg_assemble: contigs need more than cap_words */
 #define CG_STATUS_SCAN_STALLED   2u /* a scan stopped waiting for a block that never
                                        published (results of that call are invalid) */
+#define CG_STATUS_WEIGHT_RANGE   4u /* cg_partition: a bases weight of 2^32 or more */
 
 /*
  * The string graph S (Section 2: a bidirected graph, stored as a symmetric
@@ -261,11 +262,20 @@ int cg_components(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, int32_t 
 
 /* Contig sizes and GreedyPartitioning(v, P) -> p (Sections 4.2 and 4.3):
  * component sizes and kinds, eligible components (min_reads <= 1 is taken
- * as 1), then LPT: sizes in decreasing order (ties: ascending label), each
+ * as 1), then LPT: weights in decreasing order (ties: ascending label), each
  * to the least loaded of the P bins (ties: lowest bin index).  Fills `out`
- * (cg_parts above).  1 <= P <= 65536. */
+ * (cg_parts above; bin_load holds the sum of the bin's weights).
+ * 1 <= P <= 65536.
+ *   weight  CG_WEIGHT_READS: a component weighs its read count, the size the
+ *           paper partitions by (Section 4.3); CG_WEIGHT_BASES: the total
+ *           length of its reads, the work of assembling it.  Bases weights
+ *           must stay below 2^32 per component; a larger one raises
+ *           CG_STATUS_WEIGHT_RANGE and leaves the partition invalid. */
+#define CG_WEIGHT_READS 0
+#define CG_WEIGHT_BASES 1
 int cg_partition(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
-                 int32_t P, int32_t min_reads, const cg_parts *out, void *stream);
+                 int32_t P, int32_t min_reads, int32_t weight, const cg_parts *out,
+                 void *stream);
 
 /* InducedSubgraph(L, p) (Section 4.3): the bins' induced subgraphs in one
  * local numbering; fills `out` (cg_local above). */
@@ -292,6 +302,7 @@ typedef struct {
   cg_graph g;
   int32_t P;          /* bins, 1..65536 */
   int32_t min_reads;  /* as in cg_partition */
+  int32_t weight;     /* as in cg_partition: CG_WEIGHT_READS or CG_WEIGHT_BASES */
   uint8_t *flags;     /* [n]  as in cg_mask_branches */
   int32_t *d_counts;  /* [2]  as in cg_mask_branches */
   int32_t *label;     /* [n]  as in cg_components */

@@ -117,13 +117,31 @@ def table(n, row_ptr, flags, label, min_reads=2):
     return (comp_label[:n_comp], comp_size[:n_comp], comp_kind[:n_comp], label_comp[:n])
 
 
-def lpt(comp_size, comp_label, P):
-    nc = len(comp_size)
+def lpt(weights, comp_label, P):
+    nc = len(weights)
+    w = np.ascontiguousarray(weights, dtype=np.uint64)
     comp_bin = np.zeros(max(nc, 1), np.int32)
     bin_load = np.zeros(max(P, 1), np.uint64)
-    _lib().cgo_lpt(_i32(nc), _p(_c(comp_size, np.int32)), _p(_c(comp_label, np.int32)),
-                   _i32(P), _p(comp_bin), _p(bin_load))
+    _lib().cgo_lpt(_i32(nc), _p(w), _p(_c(comp_label, np.int32)), _i32(P), _p(comp_bin),
+                   _p(bin_load))
     return comp_bin[:nc], bin_load[:P]
+
+
+def component_weights(g, label, label_comp, comp_size, weight="reads"):
+    """LPT weight of each eligible component: its read count (Section 4.3),
+    or with weight="bases" the total length of its reads.  Bases weights of
+    2^32 or more are outside the library's range and raise ValueError."""
+    if weight == "reads":
+        return np.asarray(comp_size, np.uint64)
+    if weight != "bases":
+        raise ValueError("weight must be 'reads' or 'bases'")
+    owner = np.asarray(label_comp)[np.asarray(label)] if g.n else np.zeros(0, np.int64)
+    keep = owner >= 0
+    w = np.zeros(len(comp_size), np.uint64)
+    np.add.at(w, owner[keep], g.read_len[keep].astype(np.uint64))
+    if len(w) and int(w.max()) >= 1 << 32:
+        raise ValueError("a component's bases weight reaches 2^32")
+    return w
 
 
 def order(comp_label, comp_bin, comp_size):
@@ -148,7 +166,7 @@ def induce(g, flags, label, parts, P):
                       _p(_c(flags, np.uint8)), _p(_c(label, np.int32)),
                       _i32(len(parts["comp_label"])), _p(_c(parts["label_comp"], np.int32)),
                       _p(_c(parts["comp_bin"], np.int32)), _p(_c(parts["comp_start"], np.int32)),
-                      _i32(P), _p(_c(parts["bin_load"], np.uint64)), _p(perm), _p(bin_vptr),
+                      _i32(P), _p(_c(parts["comp_size"], np.int32)), _p(perm), _p(bin_vptr),
                       _p(loc_row_ptr), _p(loc_col), _p(loc_eid), _p(sizes))
     n_e, m_e = int(sizes[0]), int(sizes[1])
     return dict(perm=perm[:n_e], bin_vptr=bin_vptr, loc_row_ptr=loc_row_ptr[:n_e + 1],
@@ -191,10 +209,12 @@ def assemble(g, parts, local, cap_words=None):
     return out
 
 
-def run(g, P, min_reads=2, timings=None):
+def run(g, P, min_reads=2, timings=None, weight="reads"):
     """All five steps of Algorithm 2 on one graph; returns a dict of outputs.
 
-    If ``timings`` is a dict, per-step wall times (seconds) are stored in it."""
+    weight: "reads" (the paper's component size) or "bases" (total read
+    length) for GreedyPartitioning.  If ``timings`` is a dict, per-step wall
+    times (seconds) are stored in it."""
     t = time.perf_counter
     t0 = t()
     flags, counts = mask(g.n, g.row_ptr, g.col)
@@ -202,7 +222,8 @@ def run(g, P, min_reads=2, timings=None):
     label = components(g.n, g.row_ptr, g.col, flags)
     t2 = t()
     comp_label, comp_size, comp_kind, label_comp = table(g.n, g.row_ptr, flags, label, min_reads)
-    comp_bin, bin_load = lpt(comp_size, comp_label, P)
+    weights = component_weights(g, label, label_comp, comp_size, weight)
+    comp_bin, bin_load = lpt(weights, comp_label, P)
     comp_rank, comp_start = order(comp_label, comp_bin, comp_size)
     t3 = t()
     parts = dict(comp_label=comp_label, comp_size=comp_size, comp_kind=comp_kind,

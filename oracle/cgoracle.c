@@ -178,22 +178,23 @@ int32_t cgo_table(int32_t n, const int32_t *row_ptr, const uint8_t *flags, const
 /* O-4  GreedyPartitioning(v, P) -> p   (LPT)                                 */
 /* ------------------------------------------------------------------------ */
 
-static const int32_t *g_sort_size, *g_sort_label;
+static const uint64_t *g_sort_weight;
+static const int32_t *g_sort_label;
 
 static int cmp_size_desc(const void *a, const void *b)
 {
     int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
-    if (g_sort_size[x] != g_sort_size[y]) return g_sort_size[x] > g_sort_size[y] ? -1 : 1;
+    if (g_sort_weight[x] != g_sort_weight[y]) return g_sort_weight[x] > g_sort_weight[y] ? -1 : 1;
     if (g_sort_label[x] != g_sort_label[y]) return g_sort_label[x] < g_sort_label[y] ? -1 : 1;
     return 0;
 }
 
-void cgo_lpt(int32_t n_comp, const int32_t *comp_size, const int32_t *comp_label, int32_t P,
+void cgo_lpt(int32_t n_comp, const uint64_t *weight, const int32_t *comp_label, int32_t P,
              int32_t *comp_bin, uint64_t *bin_load)
 {
     int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_comp > 0 ? n_comp : 1));
     for (int32_t i = 0; i < n_comp; ++i) order[i] = i;
-    g_sort_size = comp_size;
+    g_sort_weight = weight;
     g_sort_label = comp_label;
     qsort(order, (size_t)n_comp, sizeof(int32_t), cmp_size_desc);
     for (int32_t j = 0; j < P; ++j) bin_load[j] = 0;
@@ -203,7 +204,7 @@ void cgo_lpt(int32_t n_comp, const int32_t *comp_size, const int32_t *comp_label
         for (int32_t j = 1; j < P; ++j)
             if (bin_load[j] < bin_load[best]) best = j;
         comp_bin[c] = best;
-        bin_load[best] += (uint64_t)comp_size[c];
+        bin_load[best] += weight[c];
     }
     free(order);
 }
@@ -242,11 +243,9 @@ void cgo_order(int32_t n_comp, const int32_t *comp_label, const int32_t *comp_bi
 void cgo_induce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint8_t *flags,
                 const int32_t *label, int32_t n_comp, const int32_t *label_comp,
                 const int32_t *comp_bin, const int32_t *comp_start, int32_t P,
-                const uint64_t *bin_load, int32_t *perm, int32_t *bin_vptr,
+                const int32_t *comp_size, int32_t *perm, int32_t *bin_vptr,
                 int32_t *loc_row_ptr, int32_t *loc_col, int32_t *loc_eid, int32_t *sizes)
 {
-    (void)comp_bin;
-    (void)n_comp;
     /* V_i = {v : owner(v) = i}; vertices numbered by (bin, label, id): the
      * component blocks come in (bin, label) order (comp_start), and inside a
      * block the vertices keep ascending id order. */
@@ -262,8 +261,10 @@ void cgo_induce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uin
         local[v] = pos;
         ++n_e;
     }
-    bin_vptr[0] = 0;
-    for (int32_t b = 0; b < P; ++b) bin_vptr[b + 1] = bin_vptr[b] + (int32_t)bin_load[b];
+    /* bin boundaries: the reads of each bin, counted from the components */
+    for (int32_t b = 0; b <= P; ++b) bin_vptr[b] = 0;
+    for (int32_t c = 0; c < n_comp; ++c) bin_vptr[comp_bin[c] + 1] += comp_size[c];
+    for (int32_t b = 0; b < P; ++b) bin_vptr[b + 1] += bin_vptr[b];
     /* E_i = {(u, v) in L : u, v in V_i}: each kept entry of a local vertex, in
      * the row order of S, with its column renumbered and its entry index kept */
     int32_t m_e = 0;

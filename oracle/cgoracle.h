@@ -58,10 +58,11 @@ int32_t cgo_table(int32_t n, const int32_t *row_ptr, const uint8_t *flags, const
                   int32_t min_reads, int32_t *comp_label, int32_t *comp_size, uint8_t *comp_kind,
                   int32_t *label_comp);
 
-/* Greedy multiway number partitioning, LPT (Section 4.3): sizes sorted in
- * decreasing order (ties by ascending label), each to the least loaded of P
- * bins (ties by lowest bin index). */
-void cgo_lpt(int32_t n_comp, const int32_t *comp_size, const int32_t *comp_label, int32_t P,
+/* Greedy multiway number partitioning, LPT (Section 4.3): component weights
+ * (the read counts, or any other weights) sorted in decreasing order (ties
+ * by ascending label), each to the least loaded of P bins (ties by lowest
+ * bin index); bin_load[b] = sum of the weights in bin b. */
+void cgo_lpt(int32_t n_comp, const uint64_t *weight, const int32_t *comp_label, int32_t P,
              int32_t *comp_bin, uint64_t *bin_load);
 
 /* Order of the components by (bin, label): comp_rank[c] is c's position in
@@ -73,11 +74,12 @@ void cgo_order(int32_t n_comp, const int32_t *comp_label, const int32_t *comp_bi
 /* Induced subgraph (Section 4.3): eligible vertices renumbered by
  * (bin, label, id); local CSR of their kept entries in original row order,
  * columns mapped to local numbers, original entry index kept.
+ * bin_vptr[b] = reads of the bins before b (counted from comp_size).
  * sizes[0] = n_e (local vertices), sizes[1] = m_e (local entries). */
 void cgo_induce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint8_t *flags,
                 const int32_t *label, int32_t n_comp, const int32_t *label_comp,
                 const int32_t *comp_bin, const int32_t *comp_start, int32_t P,
-                const uint64_t *bin_load, int32_t *perm, int32_t *bin_vptr,
+                const int32_t *comp_size, int32_t *perm, int32_t *bin_vptr,
                 int32_t *loc_row_ptr, int32_t *loc_col, int32_t *loc_eid, int32_t *sizes);
 
 /* Local assembly (Section 4.4): for every eligible component in (bin, label)

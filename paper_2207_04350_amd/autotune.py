@@ -23,15 +23,16 @@ _CACHE = os.environ.get("CG_TUNE_CACHE",
 
 
 def _key(jobs):
-    n = sum(dg.n for dg, _, _, _ in jobs)
-    m = sum(dg.m for dg, _, _, _ in jobs)
+    n = sum(job[0].n for job in jobs)
+    m = sum(job[0].m for job in jobs)
     return "%d:%d:%d" % (len(jobs), n, m)
 
 
 def _snapshot(jobs):
     """Device copies of every output that defines the result."""
     snap = []
-    for dg, out, _, _ in jobs:
+    for job in jobs:
+        dg, out = job[0], job[1]
         nc = int(out.n_comp.item())
         ne = int(out.sizes[0].item())
         me = int(out.sizes[1].item())

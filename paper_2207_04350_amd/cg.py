@@ -50,7 +50,7 @@ class CgContigs(ctypes.Structure):
 
 class CgJob(ctypes.Structure):
     _fields_ = [("g", CgGraph), ("P", ctypes.c_int32), ("min_reads", ctypes.c_int32),
-                ("flags", _vp), ("d_counts", _vp), ("label", _vp), ("parts", CgParts),
+                ("weight", ctypes.c_int32), ("flags", _vp), ("d_counts", _vp), ("label", _vp), ("parts", CgParts),
                 ("local", CgLocal), ("contigs", CgContigs)]
 
 
@@ -84,7 +84,7 @@ def lib():
         L.cg_mask_branches.argtypes = [_vp, P(CgGraph), _vp, _vp, _vp]
         L.cg_components.argtypes = [_vp, P(CgGraph), _vp, _vp, _vp]
         L.cg_partition.argtypes = [_vp, P(CgGraph), _vp, _vp, ctypes.c_int32, ctypes.c_int32,
-                                   P(CgParts), _vp]
+                                   ctypes.c_int32, P(CgParts), _vp]
         L.cg_induce.argtypes = [_vp, P(CgGraph), _vp, _vp, P(CgParts), ctypes.c_int32,
                                 P(CgLocal), _vp]
         L.cg_assemble.argtypes = [_vp, P(CgGraph), P(CgParts), P(CgLocal), ctypes.c_int32,
@@ -300,9 +300,18 @@ def components(ctx, dg, flags, label, stream=None):
                                _stream(stream)))
 
 
-def partition(ctx, dg, flags, label, P, min_reads, parts, stream=None):
+WEIGHT_READS, WEIGHT_BASES = 0, 1
+
+
+def _weight(w):
+    return {"reads": WEIGHT_READS, "bases": WEIGHT_BASES}.get(w, w)
+
+
+def partition(ctx, dg, flags, label, P, min_reads, parts, stream=None, weight="reads"):
+    """GreedyPartitioning; weight "reads" (Section 4.3) or "bases"."""
     _check(lib().cg_partition(ctx.handle, ctypes.byref(dg.struct), _ptr(flags), _ptr(label),
-                              int(P), int(min_reads), ctypes.byref(parts), _stream(stream)))
+                              int(P), int(min_reads), int(_weight(weight)), ctypes.byref(parts),
+                              _stream(stream)))
 
 
 def induce(ctx, dg, flags, label, parts, P, local, stream=None):
@@ -316,11 +325,11 @@ def assemble(ctx, dg, parts, local, P, contigs, stream=None):
                              _stream(stream)))
 
 
-def run_path(ctx, dg, out, P, min_reads=2, stream=None):
+def run_path(ctx, dg, out, P, min_reads=2, stream=None, weight="reads"):
     """Enqueue all five steps of Algorithm 2 for one resident graph."""
     mask_branches(ctx, dg, out.flags, out.counts, stream)
     components(ctx, dg, out.flags, out.label, stream)
-    partition(ctx, dg, out.flags, out.label, P, min_reads, out.parts, stream)
+    partition(ctx, dg, out.flags, out.label, P, min_reads, out.parts, stream, weight)
     induce(ctx, dg, out.flags, out.label, out.parts, P, out.local, stream)
     assemble(ctx, dg, out.parts, out.local, P, out.contigs, stream)
 
@@ -357,16 +366,19 @@ def to_host(out, n):
 
 class Batch:
     """A cg_batch over resident graphs: `jobs` is a list of (DeviceGraph,
-    Outputs, P, min_reads).  Keeps the tensors alive while it exists."""
+    Outputs, P, min_reads[, weight]).  Keeps the tensors alive while it
+    exists."""
 
     def __init__(self, ctx, jobs, vertex_tile=0, copy_block=0, persist_blocks=0):
         self.ctx = ctx
         self._keep = jobs
         arr = (CgJob * len(jobs))()
-        for i, (dg, out, P, mr) in enumerate(jobs):
+        for i, job in enumerate(jobs):
+            dg, out, P, mr = job[:4]
             arr[i].g = dg.struct
             arr[i].P = int(P)
             arr[i].min_reads = int(mr)
+            arr[i].weight = int(_weight(job[4] if len(job) > 4 else "reads"))
             arr[i].flags = _ptr(out.flags)
             arr[i].d_counts = _ptr(out.counts)
             arr[i].label = _ptr(out.label)

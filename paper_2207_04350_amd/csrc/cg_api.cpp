@@ -50,6 +50,8 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
   L.estart = take(4 * (size_t)nn);
   L.memb = take(4 * (size_t)nn);
   L.piece_skip = take(4 * (size_t)nn);
+  L.comp_w = take(8 * (size_t)nn);
+  L.bin_reads = take(8 * (size_t)(P > 0 ? P : 1));
   L.total = at;
   return L;
 }
@@ -72,6 +74,8 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   s->estart = (int32_t *)(b + L.estart);
   s->memb = (int32_t *)(b + L.memb);
   s->piece_skip = (uint32_t *)(b + L.piece_skip);
+  s->comp_w = (uint64_t *)(b + L.comp_w);
+  s->bin_reads = (uint64_t *)(b + L.bin_reads);
   return true;
 }
 
@@ -290,13 +294,19 @@ static int check_parts(const cg_parts *p) {
 }
 
 int cg_partition(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
-                 int32_t P, int32_t min_reads, const cg_parts *out, void *stream) {
+                 int32_t P, int32_t min_reads, int32_t weight, const cg_parts *out,
+                 void *stream) {
   int rc = check_graph(g, false);
   if (rc || (rc = check_P(P)) || (rc = check_parts(out))) return rc;
   if (g->n > 0 && (!flags || !label)) return set_error(CG_EINVAL, "NULL argument");
+  if (weight != CG_WEIGHT_READS && weight != CG_WEIGHT_BASES)
+    return set_error(CG_EINVAL, "weight=%d is neither CG_WEIGHT_READS nor CG_WEIGHT_BASES", weight);
+  if (weight == CG_WEIGHT_BASES && g->n > 0 && !g->read_len)
+    return set_error(CG_EINVAL, "bases weights need read_len");
   Scratch s;
   if ((rc = check_ctx(ctx, g, P, &s))) return rc;
-  return launch_partition(ctx, *g, s, flags, label, P, min_reads, *out, (hipStream_t)stream);
+  return launch_partition(ctx, *g, s, flags, label, P, min_reads, weight, *out,
+                          (hipStream_t)stream);
 }
 
 int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,

@@ -158,13 +158,17 @@ constexpr int kBinBits = 16;
 
 // With comp_kind and comp_estart given, it also writes each component's
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
-// a single read, in (bin, label) order) and returns their total.
+// a single read, in (bin, label) order) and returns their total.  bin_reads
+// (global memory, read back with atomic loads) gets the reads of each bin.
 __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict__ comp_size,
+                                        const uint64_t *__restrict__ weight,
                                         uint64_t *keys, int32_t *bin_of, uint64_t *binA,
                                         uint64_t *binB, int32_t *__restrict__ comp_bin,
                                         int32_t *__restrict__ comp_rank,
                                         int32_t *__restrict__ comp_start,
                                         uint64_t *__restrict__ bin_load,
+                                        uint64_t *__restrict__ bin_reads,
+                                        unsigned int *status,
                                         const uint8_t *__restrict__ comp_kind = nullptr,
                                         int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
@@ -172,10 +176,19 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   const int tid = threadIdx.x;
   const int N2 = next_pow2(nc > 0 ? nc : 1);
 
-  // 1. sort by (size desc, label asc); components are indexed in label order
-  for (int i = tid; i < N2; i += blockDim.x)
-    keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)comp_size[i]) << 32) | (uint32_t)i
-                     : ~0ull;
+  // 1. sort by (weight desc, label asc); components are indexed in label
+  // order.  The weight is the read count, or the given weights (below 2^32).
+  for (int i = tid; i < N2; i += blockDim.x) {
+    uint64_t w = 0;
+    if (i < nc) {
+      w = weight ? weight[i] : (uint64_t)comp_size[i];
+      if (w > 0xFFFFFFFFull) {
+        atomicOr(status, CG_STATUS_WEIGHT_RANGE);
+        w = 0xFFFFFFFFull;
+      }
+    }
+    keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)w) << 32) | (uint32_t)i : ~0ull;
+  }
   for (int b = tid; b < P; b += blockDim.x) binA[b] = (uint64_t)b;  // load 0, sorted
   __syncthreads();
   bitonic_sort(keys, N2);
@@ -241,10 +254,13 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     bin_load[k & ((1u << kBinBits) - 1)] = k >> kBinBits;
   }
 
-  // 3. (bin, label) order and read offsets
+  // 3. (bin, label) order, read offsets and the reads of each bin
   for (int i = tid; i < N2; i += blockDim.x)
     keys[i] = i < nc ? ((uint64_t)(uint32_t)bin_of[i] << 32) | (uint32_t)i : ~0ull;
+  for (int b = tid; b < P; b += blockDim.x) bin_reads[b] = 0;
   __syncthreads();
+  for (int i = tid; i < nc; i += blockDim.x)
+    atomicAdd((unsigned long long *)bin_reads + bin_of[i], (unsigned long long)comp_size[i]);
   bitonic_sort(keys, N2);
   for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
   int carry = 0, ecarry = 0;

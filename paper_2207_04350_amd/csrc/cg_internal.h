@@ -44,6 +44,8 @@ struct Scratch {
   int32_t *walk;       // [16n] assemble: chain arrays of components too big for LDS
   int32_t *estart;     // [n] batched induce: first local CSR entry of each component
   int32_t *memb;       // [n] batched components: first member slot of each component
+  uint64_t *comp_w;    // [n] partition: bases weight of each component
+  uint64_t *bin_reads; // [P] partition: reads of each bin
 };
 
 }  // namespace cg
@@ -72,7 +74,7 @@ namespace cg {
 // Scratch carving shared by cg_footprint and the calls.
 struct Layout {
   size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
-      estart, memb, piece_skip, total;
+      estart, memb, piece_skip, comp_w, bin_reads, total;
 };
 Layout layout(int64_t n, int64_t m, int64_t P);
 bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);
@@ -266,8 +268,8 @@ int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_count
 int launch_components(cg_ctx *ctx, const cg_graph &g, const uint8_t *flags, int32_t *label,
                       hipStream_t st);
 int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
-                     const int32_t *label, int32_t P, int32_t min_reads, const cg_parts &out,
-                     hipStream_t st);
+                     const int32_t *label, int32_t P, int32_t min_reads, int32_t weight,
+                     const cg_parts &out, hipStream_t st);
 int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
                   const int32_t *label, const cg_parts &parts, int32_t P, const cg_local &out,
                   hipStream_t st);

@@ -25,7 +25,7 @@ namespace cg {
 
 struct BJob {
   cg_graph g;
-  int32_t P, min_reads;
+  int32_t P, min_reads, weight;
   uint8_t *flags;
   int32_t *counts;
   int32_t *label;
@@ -377,6 +377,7 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
           J.parts.comp_kind[cb] = kind_of(c4[k]);
           J.parts.label_comp[id] = cb;
           J.s.memb[cb] = mb;
+          J.s.comp_w[cb] = 0;
           s_par[l] = mb;
           ++cb;
           mb += q;
@@ -485,6 +486,7 @@ __device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *
         J.parts.comp_kind[k] = kind_of(c4);
         J.s.memb[k] = mb + (int32_t)(ex & 0xFFFFFFFF);
         J.s.fill[k] = 0;
+        J.s.comp_w[k] = 0;
       }
       if (i < c && (J.flags[id] & 6))
         __hip_atomic_store((int32_t *)lc + id, elig ? cb + (int32_t)(ex >> 32) : -1,
@@ -566,11 +568,25 @@ __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
       J.parts.comp_size[ex] = (int32_t)q;
       J.parts.comp_kind[ex] = q == 1 ? CG_KIND_SINGLE : ((c & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
       J.parts.label_comp[v] = ex;
+      J.s.comp_w[ex] = 0;
     } else {
       J.parts.label_comp[v] = -1;
     }
   }
   if (t == J.vt_first + J.vt_count - 1 && threadIdx.x == 0) *J.parts.d_n_comp = base + tot;
+}
+
+// 3b. bases weight of each eligible component (jobs partitioned by bases):
+// the lengths of its reads, added at the component's entry
+template <int T>
+__global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
+  const int t = blockIdx.x;
+  const BJob &J = B.jobs[B.tile_job[t]];
+  if (J.weight != CG_WEIGHT_BASES) return;
+  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
+  if (v >= J.g.n) return;
+  const int32_t c = J.parts.label_comp[J.label[v]];
+  if (c >= 0) atomicAdd((unsigned long long *)J.s.comp_w + c, (unsigned long long)J.g.read_len[v]);
 }
 
 // 4. LPT per job (one workgroup each), bin offsets, bucket cursors; the last
@@ -587,20 +603,24 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   const BJob &J = B.jobs[j];
   const int P = J.P;
   const int nc = *J.parts.d_n_comp;
+  const uint64_t *wts = J.weight == CG_WEIGHT_BASES ? J.s.comp_w : nullptr;
   int m_e;
   if (nc <= kBatchSortCap && P <= kBatchBinCap)
-    m_e = lpt_body(nc, P, J.parts.comp_size, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
-                   J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.parts.comp_kind,
-                   J.s.estart);
+    m_e = lpt_body(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
+                   J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.s.bin_reads,
+                   &B.fixed->status, J.parts.comp_kind, J.s.estart);
   else
-    m_e = lpt_body(nc, P, J.parts.comp_size, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
+    m_e = lpt_body(nc, P, J.parts.comp_size, wts, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
                    J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
-                   J.parts.comp_kind, J.s.estart);
+                   J.s.bin_reads, &B.fixed->status, J.parts.comp_kind, J.s.estart);
   __syncthreads();
+  // bin boundaries: prefix of the reads of each bin
   int64_t carry = 0;
   for (int base = 0; base < P; base += kLptBlock) {
     const int b = base + threadIdx.x;
-    const int64_t x = b < P ? (int64_t)J.parts.bin_load[b] : 0;
+    const int64_t x = b < P ? (int64_t)__hip_atomic_load(J.s.bin_reads + b, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                            : 0;
     int64_t tot;
     const int64_t ex = block_excl_scan<int64_t, kLptBlock>(x, sh, &tot);
     if (b < P) J.local.bin_vptr[b] = (int32_t)(carry + ex);
@@ -766,6 +786,7 @@ struct cg_batch {
   cg_ctx *ctx;
   int32_t n_jobs, n_vtiles;
   bool any_single;  // a job with min_reads <= 1 (one-read components eligible)
+  bool any_bases;   // a job partitioned by bases weights
   cg_batch_params prm;
   BatchDev dev;
   char *mem;
@@ -781,6 +802,8 @@ static int check_job(const cg_job &J, int i) {
       (g.n > 0 && (!g.read_len || !g.read_off || !g.seq)) || ((g.pre == nullptr) != (g.post == nullptr)))
     return set_error(CG_EINVAL, "job %d: bad graph", i);
   if (J.P < 1 || J.P > 65536) return set_error(CG_EINVAL, "job %d: P=%d outside [1, 65536]", i, J.P);
+  if (J.weight != CG_WEIGHT_READS && J.weight != CG_WEIGHT_BASES)
+    return set_error(CG_EINVAL, "job %d: weight=%d", i, J.weight);
   const cg_parts &p = J.parts;
   const cg_local &l = J.local;
   const cg_contigs &c = J.contigs;
@@ -888,7 +911,11 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   b->n_jobs = n_jobs;
   b->n_vtiles = nv;
   b->any_single = false;
-  for (int i = 0; i < n_jobs; ++i) b->any_single |= jobs[i].min_reads < 2;
+  b->any_bases = false;
+  for (int i = 0; i < n_jobs; ++i) {
+    b->any_single |= jobs[i].min_reads < 2;
+    b->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
+  }
   b->prm = prm;
   b->mem_bytes = at;
   b->mem = nullptr;
@@ -906,6 +933,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
       h.g = J.g;
       h.P = J.P;
       h.min_reads = J.min_reads;
+      h.weight = J.weight;
       h.flags = J.flags;
       h.counts = J.d_counts;
       h.label = J.label;
@@ -991,6 +1019,11 @@ int cg_batch_run(cg_batch *b, void *stream) {
     if (T == 256) launch_vertex_phases<256>(b, st);
     else if (T == 512) launch_vertex_phases<512>(b, st);
     else launch_vertex_phases<1024>(b, st);
+  }
+  if (b->any_bases) {
+    if (T == 256) CG_LAUNCH(ctx, kb_weight<256>, dim3(b->n_vtiles), dim3(256), st, B);
+    else if (T == 512) CG_LAUNCH(ctx, kb_weight<512>, dim3(b->n_vtiles), dim3(512), st, B);
+    else CG_LAUNCH(ctx, kb_weight<1024>, dim3(b->n_vtiles), dim3(1024), st, B);
   }
   CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kLptBlock), st, B);
   if (b->any_single) {

@@ -3,7 +3,7 @@
 // bins share one local numbering ordered by (bin, label, id): a component's
 // reads form the block [comp_start, comp_start + q).
 //
-//  k_ind_zero   bucket cursors; bin_vptr (scan of bin_load); n_e
+//  k_ind_zero   bucket cursors; bin_vptr (scan of the reads of each bin); n_e
 //  k_ind_fill   each eligible read claims a slot in its component's block
 //  k_ind_local  one workgroup per component: sort the block by read id
 //               (LDS bitonic up to 1024 reads, rank counting above)
@@ -15,7 +15,9 @@ namespace cg {
 
 
 __global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_t *__restrict__ d_n_comp,
-                                                         const uint64_t *__restrict__ bin_load,
+                                                         const int32_t *__restrict__ comp_bin,
+                                                         const int32_t *__restrict__ comp_size,
+                                                         uint64_t *bin_reads,
                                                          uint32_t *__restrict__ fill,
                                                          int32_t *__restrict__ bin_vptr,
                                                          int32_t *__restrict__ d_sizes) {
@@ -24,11 +26,19 @@ __global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_
        c += (int64_t)gridDim.x * blockDim.x)
     fill[c] = 0;
   if (blockIdx.x == 0) {
+    // the reads of each bin, then their prefix: bin_vptr
     __shared__ int64_t sh[kScanBlock / kWave + 1];
+    for (int b = threadIdx.x; b < P; b += kScanBlock) bin_reads[b] = 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += kScanBlock)
+      atomicAdd((unsigned long long *)bin_reads + comp_bin[c], (unsigned long long)comp_size[c]);
+    __syncthreads();
     int64_t carry = 0;
     for (int base = 0; base < P; base += kScanBlock) {
       const int b = base + threadIdx.x;
-      const int64_t x = b < P ? (int64_t)bin_load[b] : 0;
+      const int64_t x = b < P ? (int64_t)__hip_atomic_load(bin_reads + b, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)
+                              : 0;
       int64_t tot;
       const int64_t ex = block_excl_scan<int64_t, kScanBlock>(x, sh, &tot);
       if (b < P) bin_vptr[b] = (int32_t)(carry + ex);
@@ -107,7 +117,8 @@ int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_
   const int32_t n = g.n;
   const int zgrid = n > 0 ? (int)((n + kScanBlock - 1) / kScanBlock) : 1;
   CG_LAUNCH(ctx, k_ind_zero, dim3(zgrid < 256 ? zgrid : 256), dim3(kScanBlock), st, P,
-                     parts.d_n_comp, parts.bin_load, s.fill, out.bin_vptr, out.d_sizes);
+                     parts.d_n_comp, parts.comp_bin, parts.comp_size, s.bin_reads, s.fill,
+                     out.bin_vptr, out.d_sizes);
   if (n > 0) {
     const int grid = (int)((n + kIndBlock - 1) / kIndBlock);
     CG_LAUNCH(ctx, k_ind_fill, dim3(grid), dim3(kIndBlock), st, n, label, parts.label_comp,

@@ -5,7 +5,8 @@
 //                              one = c & 3 (2 for a path, 0 for a cycle)
 //  k_part_compact              eligible components in ascending label order
 //                              (single-pass look-back scan), label -> index map
-//  k_part_lpt                  one workgroup: sort by (size desc, label asc),
+//  k_part_wzero / k_part_weight bases weights (lengths of a component's reads)
+//  k_part_lpt                  one workgroup: sort by (weight desc, label asc),
 //                              exact LPT, sort by (bin, label), read offsets
 #include "cg_device.h"
 
@@ -56,8 +57,26 @@ __global__ __launch_bounds__(kScanBlock) void k_part_compact(
 // ---------------------------------------------------------------------------
 // Single-workgroup sort + LPT.
 // ---------------------------------------------------------------------------
+// bases weight of each eligible component: the lengths of its reads
+__global__ __launch_bounds__(kPartBlock) void k_part_wzero(int32_t n, uint64_t *__restrict__ w) {
+  const int64_t v = (int64_t)blockIdx.x * kPartBlock + threadIdx.x;
+  if (v < n) w[v] = 0;
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_part_weight(int32_t n, const int32_t *__restrict__ label,
+                                                            const int32_t *__restrict__ label_comp,
+                                                            const uint32_t *__restrict__ read_len,
+                                                            uint64_t *w) {
+  const int64_t v = (int64_t)blockIdx.x * kPartBlock + threadIdx.x;
+  if (v >= n) return;
+  const int32_t c = label_comp[label[v]];
+  if (c >= 0) atomicAdd((unsigned long long *)w + c, (unsigned long long)read_len[v]);
+}
+
 __global__ __launch_bounds__(kLptBlock) void k_part_lpt(int32_t P, const int32_t *__restrict__ d_n_comp,
                                                         const int32_t *__restrict__ comp_size,
+                                                        const uint64_t *__restrict__ weight,
+                                                        uint64_t *bin_reads, unsigned int *status,
                                                         int32_t *__restrict__ comp_bin,
                                                         int32_t *__restrict__ comp_rank,
                                                         int32_t *__restrict__ comp_start,
@@ -69,16 +88,16 @@ __global__ __launch_bounds__(kLptBlock) void k_part_lpt(int32_t P, const int32_t
   __shared__ uint64_t s_binA[kBinCapLds], s_binB[kBinCapLds];
   const int nc = *d_n_comp;
   if (nc <= kSortCapLds && P <= kBinCapLds)
-    lpt_body(nc, P, comp_size, s_keys, s_bin, s_binA, s_binB, comp_bin, comp_rank, comp_start,
-             bin_load);
+    lpt_body(nc, P, comp_size, weight, s_keys, s_bin, s_binA, s_binB, comp_bin, comp_rank,
+             comp_start, bin_load, bin_reads, status);
   else
-    lpt_body(nc, P, comp_size, g_keys, g_bin, g_bins, g_bins + P, comp_bin, comp_rank, comp_start,
-             bin_load);
+    lpt_body(nc, P, comp_size, weight, g_keys, g_bin, g_bins, g_bins + P, comp_bin, comp_rank,
+             comp_start, bin_load, bin_reads, status);
 }
 
 int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
-                     const int32_t *label, int32_t P, int32_t min_reads, const cg_parts &out,
-                     hipStream_t st) {
+                     const int32_t *label, int32_t P, int32_t min_reads, int32_t weight,
+                     const cg_parts &out, hipStream_t st) {
   const int32_t n = g.n;
   if (min_reads < 1) min_reads = 1;
   const int grid = n > 0 ? (int)((n + kPartBlock - 1) / kPartBlock) : 1;
@@ -91,9 +110,16 @@ int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uin
   CG_LAUNCH(ctx, k_part_compact, dim3(nb), dim3(kScanBlock), st, n, flags, out.label_comp,
                      min_reads, out.comp_label, out.comp_size, out.comp_kind, out.d_n_comp,
                      scan_ctx(ctx, s), nb);
+  const bool bases = weight == CG_WEIGHT_BASES;
+  if (bases && n > 0) {
+    CG_LAUNCH(ctx, k_part_wzero, dim3(grid), dim3(kPartBlock), st, n, s.comp_w);
+    CG_LAUNCH(ctx, k_part_weight, dim3(grid), dim3(kPartBlock), st, n, label, out.label_comp,
+                       g.read_len, s.comp_w);
+  }
   CG_LAUNCH(ctx, k_part_lpt, dim3(1), dim3(kLptBlock), st, P, out.d_n_comp, out.comp_size,
-                     out.comp_bin, out.comp_rank, out.comp_start, out.bin_load, s.keys, s.aux,
-                     s.bins);
+                     bases ? (const uint64_t *)s.comp_w : nullptr, s.bin_reads,
+                     &ctx->fixed->status, out.comp_bin, out.comp_rank, out.comp_start,
+                     out.bin_load, s.keys, s.aux, s.bins);
   return hip_check(hipGetLastError(), "k_part");
 }
 

@@ -51,11 +51,13 @@ def _mixed_graphs():
 
 
 def _params(i, g):
+    """(P, min_reads, weight) of job i: every third job partitions by bases."""
+    w = "bases" if i % 3 == 1 else "reads"
     if "min_reads" in g.meta:
-        return [64, 300, 8, 1024][i % 4], g.meta["min_reads"]
+        return [64, 300, 8, 1024][i % 4], g.meta["min_reads"], w
     r = np.random.default_rng(100 + i)
     P = int(r.integers(1, 9)) if g.n <= 16 else [64, 300, 8, 1024][i % 4]
-    return P, int(r.integers(0, 3)) if g.n <= 16 else 2
+    return P, int(r.integers(0, 3)) if g.n <= 16 else 2, w
 
 
 def _make(cg, graphs, params, **shape):
@@ -65,8 +67,8 @@ def _make(cg, graphs, params, **shape):
                                                              params[i][0]))
     ctx = cg.Context.for_graph(graphs[big].n, graphs[big].m, params[big][0])
     dgs = [cg.DeviceGraph(g, dev) for g in graphs]
-    outs = [cg.Outputs(g.n, P, g.seq_words, dev) for g, (P, _) in zip(graphs, params)]
-    b = cg.Batch(ctx, [(dg, o, P, mr) for dg, o, (P, mr) in zip(dgs, outs, params)], **shape)
+    outs = [cg.Outputs(g.n, p[0], g.seq_words, dev) for g, p in zip(graphs, params)]
+    b = cg.Batch(ctx, [(dg, o) + tuple(p) for dg, o, p in zip(dgs, outs, params)], **shape)
     return ctx, dgs, outs, b
 
 
@@ -107,7 +109,7 @@ def test_batch_mixed_all_shapes(cg):
     import torch
     graphs = _mixed_graphs()
     params = [_params(i, g) for i, g in enumerate(graphs)]
-    wants = [oracle.run(g, P=P, min_reads=mr) for g, (P, mr) in zip(graphs, params)]
+    wants = [oracle.run(g, P=P, min_reads=mr, weight=w) for g, (P, mr, w) in zip(graphs, params)]
     for shape in (dict(), dict(vertex_tile=512, copy_block=128, persist_blocks=64),
                   dict(vertex_tile=1024, copy_block=1024, persist_blocks=7),
                   dict(vertex_tile=256, copy_block=64, persist_blocks=2048)):
@@ -130,7 +132,7 @@ def test_batch_graph_replay(cg):
     import torch
     graphs = _mixed_graphs()[30:]
     params = [_params(i, g) for i, g in enumerate(graphs)]
-    wants = [oracle.run(g, P=P, min_reads=mr) for g, (P, mr) in zip(graphs, params)]
+    wants = [oracle.run(g, P=P, min_reads=mr, weight=w) for g, (P, mr, w) in zip(graphs, params)]
     ctx, dgs, outs, b = _make(cg, graphs, params)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
@@ -156,12 +158,12 @@ def test_batch_512_graphs(cg):
     """The batched workload in full: 512 graphs in one batch."""
     import torch
     graphs = synth.batch_graphs(512)
-    params = [(g.meta["P"], 2) for g in graphs]
+    params = [(g.meta["P"], 2, "bases" if i % 2 else "reads") for i, g in enumerate(graphs)]
     ctx, dgs, outs, b = _make(cg, graphs, params)
     b.run()
     torch.cuda.synchronize()
     for i, g in enumerate(graphs):
-        want = oracle.run(g, P=params[i][0], min_reads=2)
+        want = oracle.run(g, P=params[i][0], min_reads=2, weight=params[i][2])
         got = cg.to_host(outs[i], g.n)
         bad = mismatches(got, want)
         if bad == ["contigs.bases"]:

@@ -26,23 +26,24 @@ def cg():
     return _cg
 
 
-def run_gpu(cg, g, P, min_reads=2, ctx=None, cap_words=None):
+def run_gpu(cg, g, P, min_reads=2, ctx=None, cap_words=None, weight="reads"):
     own = ctx is None
     if own:
         ctx = cg.Context.for_graph(g.n, g.m, P)
     dg = cg.DeviceGraph(g, "cuda")
     out = cg.Outputs(g.n, P, g.seq_words if cap_words is None else cap_words, "cuda")
-    cg.run_path(ctx, dg, out, P, min_reads)
+    cg.run_path(ctx, dg, out, P, min_reads, weight=weight)
     got = cg.to_host(out, g.n)
     if own:
         ctx.close()
     return got, out
 
 
-def check(cg, g, P, min_reads=2, ctx=None, name=""):
-    _say("parity case", name, "n=%d m=%d P=%d min_reads=%d" % (g.n, g.m, P, min_reads))
-    got, _ = run_gpu(cg, g, P, min_reads, ctx)
-    want = oracle.run(g, P=P, min_reads=min_reads)
+def check(cg, g, P, min_reads=2, ctx=None, name="", weight="reads"):
+    _say("parity case", name, "n=%d m=%d P=%d min_reads=%d weight=%s" % (g.n, g.m, P, min_reads,
+                                                                          weight))
+    got, _ = run_gpu(cg, g, P, min_reads, ctx, weight=weight)
+    want = oracle.run(g, P=P, min_reads=min_reads, weight=weight)
     bad = mismatches(got, want)
     assert bad == [], (name, bad)
     return got
@@ -208,5 +209,21 @@ def test_alignment_ends(cg):
         P, mr = int(rng.integers(1, 9)), int(rng.integers(0, 3))
         got, _ = run_gpu(cg, h, P, mr, ctx)
         bad = mismatches(got, oracle.run(h, P=P, min_reads=mr))
+        assert bad == [], (i, bad)
+    ctx.close()
+
+
+def test_bases_weighted_partition(cg):
+    """GreedyPartitioning by bases (the total read length of a component)."""
+    check(cg, synth.config_graph(1), 8, 2, name="config1-bases", weight="bases")
+    check(cg, synth.config_graph(2), 64, 2, name="config2-bases", weight="bases")
+    check(cg, synth.config_graph(2), 3000, 2, name="config2-bases-3000-bins", weight="bases")
+    rng = np.random.default_rng(21)
+    ctx = cg.Context.for_graph(64, 256, 16)
+    for i in range(150):
+        g = synth.adversarial(rng)
+        P, mr = int(rng.integers(1, 9)), int(rng.integers(0, 3))
+        got, _ = run_gpu(cg, g, P, mr, ctx, weight="bases")
+        bad = mismatches(got, oracle.run(g, P=P, min_reads=mr, weight="bases"))
         assert bad == [], (i, bad)
     ctx.close()

@@ -45,7 +45,15 @@ def test_null_arguments_rejected_on_host():
     g.n, g.m = 10, 0
     assert lib.cg_mask_branches(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
     assert b"NULL" in lib.cg_last_error() or lib.cg_last_error()
-    assert lib.cg_partition(None, ctypes.byref(g), None, None, 0, 2, None, None) == cg.CG_EINVAL
-    assert lib.cg_partition(None, ctypes.byref(g), None, None, 70000, 2, None, None) == cg.CG_EINVAL
+    assert lib.cg_partition(None, ctypes.byref(g), None, None, 0, 2, 0, None, None) == cg.CG_EINVAL
+    assert lib.cg_partition(None, ctypes.byref(g), None, None, 70000, 2, 0, None, None) == cg.CG_EINVAL
+    # an unknown weight, and pre without post, are argument errors
+    assert lib.cg_partition(None, ctypes.byref(g), None, None, 4, 2, 7, None, None) == cg.CG_EINVAL
+    pre = (ctypes.c_uint32 * 1)()
+    g.row_ptr = ctypes.cast(pre, ctypes.c_void_p)   # checked on the host only, never read
+    g.pre = ctypes.cast(pre, ctypes.c_void_p)
+    assert lib.cg_mask_branches(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
+    assert b"pre and post" in lib.cg_last_error()
+    g.pre = g.row_ptr = None
     g.n = 1 << 30
     assert lib.cg_components(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
