@@ -152,6 +152,15 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int len, uint6
   return lo;
 }
 
+// x of lane l + 1 in lane l, by a DPP wave shift (wave_shl:1); lane 63,
+// which has no source, keeps its own x
+__device__ __forceinline__ uint64_t wave_next_u64(uint64_t x) {
+  const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+  const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
+  const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
+  return ((uint64_t)nhi << 32) | nlo;
+}
+
 // Bin keys are (load << 16) | bin: ascending key order is ascending
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
@@ -211,14 +220,18 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         const int cnt = T - base < kWave ? T - base : kWave;
         const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
         for (int t = 0; t < cnt; ++t) {
-          const uint64_t it = __shfl(item, t);
-          const uint32_t c = (uint32_t)it;
-          const uint64_t q = 0xFFFFFFFFu - (uint32_t)(it >> 32);
-          const uint64_t k0 = __shfl(key, 0);
+          // t is uniform: broadcasts are lane reads into scalar registers
+          const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)item, t);
+          const uint64_t q =
+              0xFFFFFFFFu - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(item >> 32), t);
+          const uint64_t k0 =
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), 0) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, 0);
           if (l == 0) bin_of[c] = (int32_t)(k0 & ((1u << kBinBits) - 1));
           const uint64_t nk = k0 + (q << kBinBits);
           const int p = __popcll(__ballot(key < nk)) - 1;  // lanes 1.. below nk
-          const uint64_t nxt = __shfl_down(key, 1);
+          // the key of lane l + 1 (a wave-wide DPP shift; lane 63 keeps its own)
+          const uint64_t nxt = wave_next_u64(key);
           key = l < p ? nxt : (l == p ? nk : key);
         }
       }
@@ -297,18 +310,23 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
 constexpr int kIndBlock = 256;
 constexpr int kIndLocalCap = 1024;
 
+// one-wave form for the small components of the batched path
+constexpr int kIndSmallBlock = 64;
+constexpr int kIndSmallCap = 256;
+
+template <int BLOCK, int CAP>
 __device__ __forceinline__ void sort_component_block(int q, int st,
                                                      const int32_t *__restrict__ members,
                                                      int32_t *__restrict__ perm,
                                                      int32_t *__restrict__ lidx, int32_t *a) {
-  if (q <= kIndLocalCap) {
+  if (q <= CAP) {
     int N2 = 1;
     while (N2 < q) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += kIndBlock) a[i] = i < q ? members[i] : 0x7FFFFFFF;
+    for (int i = threadIdx.x; i < N2; i += BLOCK) a[i] = i < q ? members[i] : 0x7FFFFFFF;
     __syncthreads();
     for (int k = 2; k <= N2; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < N2; i += kIndBlock) {
+        for (int i = threadIdx.x; i < N2; i += BLOCK) {
           const int ixj = i ^ j;
           if (ixj > i) {
             const int32_t x = a[i], y = a[ixj];
@@ -321,7 +339,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
         __syncthreads();
       }
     }
-    for (int i = threadIdx.x; i < q; i += kIndBlock) {
+    for (int i = threadIdx.x; i < q; i += BLOCK) {
       const int32_t v = a[i];
       perm[st + i] = v;
       lidx[v] = st + i;
@@ -329,7 +347,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
   } else {
     // large component: the rank of a read is the number of smaller ids in
     // its block (ids are distinct)
-    for (int i = threadIdx.x; i < q; i += kIndBlock) {
+    for (int i = threadIdx.x; i < q; i += BLOCK) {
       const int32_t x = members[i];
       int r = 0;
       for (int t = 0; t < q; ++t) r += members[t] < x;
@@ -346,6 +364,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
 // entry index kept)
 // starting at entry estart.  Neighbours of a kept entry lie in the same
 // component, so their local numbers come from the sorted block itself.
+template <int BLOCK, int CAP>
 __device__ __forceinline__ void induce_component(
     int q, int st, int estart, const int32_t *__restrict__ members,
     const uint8_t *__restrict__ flags,
@@ -353,10 +372,10 @@ __device__ __forceinline__ void induce_component(
     int32_t *__restrict__ perm, int32_t *__restrict__ lidx, int32_t *__restrict__ loc_row_ptr,
     int32_t *__restrict__ loc_col, int32_t *__restrict__ loc_eid, int32_t *a,
     int32_t *sh_scan) {
-  sort_component_block(q, st, members, perm, lidx, a);  // ends with a barrier
-  const bool in_lds = q <= kIndLocalCap;
+  sort_component_block<BLOCK, CAP>(q, st, members, perm, lidx, a);  // ends with a barrier
+  const bool in_lds = q <= CAP;
   int carry = 0;
-  for (int base = 0; base < q; base += kIndBlock) {
+  for (int base = 0; base < q; base += BLOCK) {
     const int i = base + threadIdx.x;
     int32_t v = -1;
     uint32_t f = 0;
@@ -366,7 +385,7 @@ __device__ __forceinline__ void induce_component(
     }
     const int32_t deg = (int32_t)(((f >> 1) & 1) + ((f >> 2) & 1));
     int32_t tot;
-    const int32_t ex = block_excl_scan<int32_t, kIndBlock>(deg, sh_scan, &tot);
+    const int32_t ex = block_excl_scan<int32_t, BLOCK>(deg, sh_scan, &tot);
     if (i < q) {
       int32_t r = estart + carry + ex;
       loc_row_ptr[st + i] = r;
@@ -401,7 +420,9 @@ __device__ __forceinline__ void induce_component(
 // ---------------------------------------------------------------------------
 constexpr int kWalkBlock = 256;
 constexpr int kWalkCap = 1024;               // reads per component handled in LDS
-constexpr int kRaysPerThread = 2 * kWalkCap / kWalkBlock;
+// small components: one wave each, so many more are walked at once
+constexpr int kWalkSmallBlock = 64;
+constexpr int kWalkSmallCap = 128;
 
 struct WalkArrays {
   int32_t *nb;     // [2q] local neighbour of slot k of read i (-1: none / cut)
@@ -411,7 +432,7 @@ struct WalkArrays {
   int32_t *endv;   // [2q] ray end
 };
 
-template <bool kLds>
+template <int BLOCK, int CAP, bool kLds>
 __device__ __forceinline__ void walk_component(
     int c, int q, int st, WalkArrays w, const cg_graph &g, const cg_parts &parts,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ loc_row_ptr,
@@ -427,7 +448,7 @@ __device__ __forceinline__ void walk_component(
     s_carry = 0;
   }
   // 1. local rows of the component's block
-  for (int i = tid; i < q; i += kWalkBlock) {
+  for (int i = tid; i < q; i += BLOCK) {
     const int a = loc_row_ptr[st + i], b = loc_row_ptr[st + i + 1];
     const int deg = b - a;
     w.nb[2 * i] = deg >= 1 ? loc_col[a] - st : -1;
@@ -439,7 +460,7 @@ __device__ __forceinline__ void walk_component(
   // 2. start: the first read of local degree 1 (the smaller-id root, since
   // the block is in id order); a cycle starts at its first read and loses
   // the edge to the larger-numbered neighbour of it
-  for (int i = tid; i < q; i += kWalkBlock)
+  for (int i = tid; i < q; i += BLOCK)
     if ((w.nb[2 * i] >= 0) != (w.nb[2 * i + 1] >= 0)) atomicMin(&s_start, i);
   __syncthreads();
   if (tid == 0) {
@@ -459,7 +480,7 @@ __device__ __forceinline__ void walk_component(
   // 3. rays (i, k): leave read i through slot k.  A ray jumps along the
   // chain; after ceil(log2 q) doublings it knows the chain end it reaches and
   // how many steps away that end is.
-  for (int r = tid; r < 2 * q; r += kWalkBlock) {
+  for (int r = tid; r < 2 * q; r += BLOCK) {
     const int y = w.nb[r];
     if (y < 0) {
       w.nxt[r] = -1;
@@ -477,10 +498,10 @@ __device__ __forceinline__ void walk_component(
   __syncthreads();
   for (int span = 1; span < q; span <<= 1) {
     if (kLds) {
-      int rn[kRaysPerThread], rd[kRaysPerThread], re[kRaysPerThread];
+      int rn[(2 * CAP / BLOCK)], rd[(2 * CAP / BLOCK)], re[(2 * CAP / BLOCK)];
 #pragma unroll
-      for (int u = 0; u < kRaysPerThread; ++u) {
-        const int r = tid + u * kWalkBlock;
+      for (int u = 0; u < (2 * CAP / BLOCK); ++u) {
+        const int r = tid + u * BLOCK;
         rn[u] = -2;
         if (r < 2 * q) {
           const int x = w.nxt[r];
@@ -493,8 +514,8 @@ __device__ __forceinline__ void walk_component(
       }
       __syncthreads();
 #pragma unroll
-      for (int u = 0; u < kRaysPerThread; ++u) {
-        const int r = tid + u * kWalkBlock;
+      for (int u = 0; u < (2 * CAP / BLOCK); ++u) {
+        const int r = tid + u * BLOCK;
         if (rn[u] != -2) {
           w.nxt[r] = rn[u];
           w.dist[r] = rd[u];
@@ -506,7 +527,7 @@ __device__ __forceinline__ void walk_component(
       // large component (global arrays): ray r's successor x is only
       // rewritten by its own owner, so read all then write all in two passes
       // with the new values parked in the endv/dist of the high half
-      for (int r = tid; r < 2 * q; r += kWalkBlock) {
+      for (int r = tid; r < 2 * q; r += BLOCK) {
         const int x = w.nxt[r];
         if (x >= 0) {
           // encode the update next to the ray: (new nxt, new dist, new end)
@@ -518,7 +539,7 @@ __device__ __forceinline__ void walk_component(
         }
       }
       __syncthreads();
-      for (int r = tid; r < 2 * q; r += kWalkBlock) {
+      for (int r = tid; r < 2 * q; r += BLOCK) {
         const int x = w.nxt[2 * q + r];
         if (x != -2) {
           w.nxt[r] = x;
@@ -535,7 +556,7 @@ __device__ __forceinline__ void walk_component(
   uint32_t *R_len = s.piece_len + st;
   uint32_t *R_skip = s.piece_skip + st;
   const int rank_c = parts.comp_rank[c];
-  for (int i = tid; i < q; i += kWalkBlock) {
+  for (int i = tid; i < q; i += BLOCK) {
     int rank = 0, pred = -1, succ = -1, succ_e = -1;
     if (i == s0) {
       if (w.nb[2 * i] >= 0) { succ = w.nb[2 * i]; succ_e = w.eid[2 * i]; }
@@ -587,11 +608,11 @@ __device__ __forceinline__ void walk_component(
   }
   __syncthreads();
   // 5. piece offsets in walk order
-  for (int base = 0; base < q; base += kWalkBlock) {
+  for (int base = 0; base < q; base += BLOCK) {
     const int i = base + tid;
     const uint32_t x = i < q ? R_len[i] : 0u;
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<uint32_t, kWalkBlock>(x, sh_scan, &tot);
+    const uint32_t ex = block_excl_scan<uint32_t, BLOCK>(x, sh_scan, &tot);
     if (i < q) s.piece_off[st + i] = s_carry + ex;
     __syncthreads();
     if (tid == 0) s_carry += tot;

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
     const int st = parts.comp_start[c];
     if (q <= kWalkCap) {
       WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
-      walk_component<true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
+      walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
                            local.loc_eid, out, s, nullptr, sh_scan);
     } else {
       // per-component slices of global scratch: the blocks of different
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
                    gbuf + 4 * (int64_t)n + 4 * (int64_t)st,
                    gbuf + 8 * (int64_t)n + 4 * (int64_t)st,
                    gbuf + 12 * (int64_t)n + 4 * (int64_t)st};
-      walk_component<false>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
+      walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
                             local.loc_eid, out, s, nullptr, sh_scan);
     }
   }

@@ -66,6 +66,8 @@ struct BatchDev {
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
+  int32_t *comp_job;                // [sum n] job of each batch-wide component
+  int32_t *chunk_job;               // [sum n / 64 + n_jobs] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
   int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
@@ -668,8 +670,31 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
     B.chunk_base[B.n_jobs] = (int32_t)hc;
     B.counters[2] = 0;
     B.counters[3] += 1u;  // the next run's forest tag
-    __threadfence();
   }
+  __syncthreads();
+  // the job of every batch-wide component and copy chunk, so that the
+  // persistent passes find it with one load
+  // (each wave loads the bounds of 64 jobs at once, then its lanes fill the
+  // entries of one job after the other)
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int j0 = (threadIdx.x / kWave) * kWave; j0 < B.n_jobs; j0 += kLptBlock) {
+    const int jl = j0 + lane;
+    int32_t c0 = 0, c1 = 0, h0 = 0, h1 = 0;
+    if (jl < B.n_jobs) {
+      c0 = B.comp_base[jl];
+      c1 = B.comp_base[jl + 1];
+      h0 = B.chunk_base[jl];
+      h1 = B.chunk_base[jl + 1];
+    }
+    const int cnt = B.n_jobs - j0 < kWave ? B.n_jobs - j0 : kWave;
+    for (int t = 0; t < cnt; ++t) {
+      const int32_t a0 = __shfl(c0, t), a1 = __shfl(c1, t);
+      const int32_t b0 = __shfl(h0, t), b1 = __shfl(h1, t);
+      for (int32_t i = a0 + lane; i < a1; i += kWave) B.comp_job[i] = j0 + t;
+      for (int32_t i = b0 + lane; i < b1; i += kWave) B.chunk_job[i] = j0 + t;
+    }
+  }
+  __threadfence();
 }
 
 // 5. each eligible read claims a slot in its component's block
@@ -686,47 +711,137 @@ __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   J.s.tmp[J.parts.comp_start[c] + slot] = (int32_t)v;
 }
 
+// The batch-wide components a block of a persistent pass owns are
+// i = blockIdx.x + k * gridDim.x.  gather_components looks at 64 of them at a
+// time (round r: k in [64r, 64r + 64)), each lane of the first wave loading
+// one candidate's read count, and packs those with lo < q <= hi into list in
+// increasing i.  Returns how many it packed; all threads see the list.
+__device__ __forceinline__ int gather_components(const BatchDev &B, int32_t total, int r, int lo,
+                                                 int hi, int32_t *list, int *s_cnt) {
+  __syncthreads();  // the previous round's list is no longer read
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x + ((int64_t)r * kWave + lane) * gridDim.x;
+    bool hit = false;
+    if (i < total) {
+      const int j = B.comp_job[i];
+      const int q = B.jobs[j].parts.comp_size[i - B.comp_base[j]];
+      hit = q > lo && q <= hi;
+    }
+    const uint64_t m = __ballot(hit);
+    if (hit) list[__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+    if (lane == 0) *s_cnt = __popcll(m);
+  }
+  __syncthreads();
+  return *s_cnt;
+}
+
+__device__ __forceinline__ int gather_rounds(int32_t total) {
+  const int64_t per = (int64_t)kWave * gridDim.x;
+  return (int)(((int64_t)total - blockIdx.x + per - 1) / per);
+}
+
 // 6. induced subgraph of each component: sorted local numbers and local CSR
 // rows (persistent over all components of the batch)
-__global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
-  __shared__ int32_t a[kIndLocalCap];
-  __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
+template <int BLOCK, int CAP>
+__device__ __forceinline__ void induce_listed(const BatchDev &B, int32_t i, int32_t *a,
+                                              int32_t *sh_scan) {
+  const int j = B.comp_job[i];
+  const BJob &J = B.jobs[j];
+  const int c = i - B.comp_base[j];
+  const int32_t *members = J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : J.parts.comp_start[c]);
+  induce_component<BLOCK, CAP>(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c],
+                               members, J.flags, J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx,
+                               J.local.loc_row_ptr, J.local.loc_col, J.local.loc_eid, a, sh_scan);
+}
+
+// 6a. components of at most kIndSmallCap reads: one wave each
+__global__ __launch_bounds__(kIndSmallBlock) void kb_induce_small(BatchDev B) {
+  __shared__ int32_t a[kIndSmallCap];
+  __shared__ int32_t sh_scan[kIndSmallBlock / kWave + 1];
+  __shared__ int32_t list[kWave];
+  __shared__ int cnt;
   const int32_t total = B.comp_base[B.n_jobs];
-  for (int32_t i = blockIdx.x; i < total; i += gridDim.x) {
-    const int j = job_of(B.comp_base, B.n_jobs, i);
-    const BJob &J = B.jobs[j];
-    const int c = i - B.comp_base[j];
-    const int32_t *members =
-        J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : J.parts.comp_start[c]);
-    induce_component(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c], members, J.flags,
-                     J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx, J.local.loc_row_ptr,
-                     J.local.loc_col, J.local.loc_eid, a, sh_scan);
+  const int rounds = gather_rounds(total);
+  for (int r = 0; r < rounds; ++r) {
+    const int k = gather_components(B, total, r, 0, kIndSmallCap, list, &cnt);
+    for (int t = 0; t < k; ++t)
+      induce_listed<kIndSmallBlock, kIndSmallCap>(B, list[t], a, sh_scan);
   }
 }
 
-// 7. walk every component (persistent, all components)
+// 6b. the larger components
+__global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
+  __shared__ int32_t a[kIndLocalCap];
+  __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
+  __shared__ int32_t list[kWave];
+  __shared__ int cnt;
+  const int32_t total = B.comp_base[B.n_jobs];
+  const int rounds = gather_rounds(total);
+  for (int r = 0; r < rounds; ++r) {
+    const int k = gather_components(B, total, r, kIndSmallCap, 0x7FFFFFFF, list, &cnt);
+    for (int t = 0; t < k; ++t) induce_listed<kIndBlock, kIndLocalCap>(B, list[t], a, sh_scan);
+  }
+}
+
+// 7. walk every component (persistent grids over all components)
+// 7a. components of at most kWalkSmallCap reads: one wave each
+__global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
+  __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
+      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap];
+  __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
+  __shared__ int32_t list[kWave];
+  __shared__ int cnt;
+  const int32_t total = B.comp_base[B.n_jobs];
+  const int rounds = gather_rounds(total);
+  for (int r = 0; r < rounds; ++r) {
+    const int k = gather_components(B, total, r, 0, kWalkSmallCap, list, &cnt);
+    for (int t = 0; t < k; ++t) {
+      const int32_t i = list[t];
+      const int j = B.comp_job[i];
+      const BJob &J = B.jobs[j];
+      const int c = i - B.comp_base[j];
+      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
+      walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
+          c, J.parts.comp_size[c], J.parts.comp_start[c], w, J.g, J.parts, J.local.perm,
+          J.local.loc_row_ptr, J.local.loc_col, J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+    }
+  }
+}
+
+// 7b. the larger components
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
+  __shared__ int32_t list[kWave];
+  __shared__ int cnt;
   const int32_t total = B.comp_base[B.n_jobs];
-  for (int32_t i = blockIdx.x; i < total; i += gridDim.x) {
-    const int j = job_of(B.comp_base, B.n_jobs, i);
-    const BJob &J = B.jobs[j];
-    const int c = i - B.comp_base[j];
-    const int q = J.parts.comp_size[c];
-    const int st = J.parts.comp_start[c];
-    if (q <= kWalkCap) {
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
-      walk_component<true>(c, q, st, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr,
-                           J.local.loc_col, J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-    } else {
-      const int64_t n = J.g.n;
-      int32_t *gb = J.s.walk;
-      WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st, gb + 4 * n + 4 * (int64_t)st,
-                   gb + 8 * n + 4 * (int64_t)st, gb + 12 * n + 4 * (int64_t)st};
-      walk_component<false>(c, q, st, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr,
-                            J.local.loc_col, J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+  const int rounds = gather_rounds(total);
+  for (int r = 0; r < rounds; ++r) {
+    const int k = gather_components(B, total, r, kWalkSmallCap, 0x7FFFFFFF, list, &cnt);
+    for (int t = 0; t < k; ++t) {
+      const int32_t i = list[t];
+      const int j = B.comp_job[i];
+      const BJob &J = B.jobs[j];
+      const int c = i - B.comp_base[j];
+      const int q = J.parts.comp_size[c];
+      const int st = J.parts.comp_start[c];
+      if (q <= kWalkCap) {
+        WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
+        walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, J.g, J.parts, J.local.perm,
+                                                   J.local.loc_row_ptr, J.local.loc_col,
+                                                   J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+      } else {
+        const int64_t n = J.g.n;
+        int32_t *gb = J.s.walk;
+        WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st,
+                     gb + 4 * n + 4 * (int64_t)st, gb + 8 * n + 4 * (int64_t)st,
+                     gb + 12 * n + 4 * (int64_t)st};
+        walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, J.g, J.parts, J.local.perm,
+                                                    J.local.loc_row_ptr, J.local.loc_col,
+                                                    J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+      }
     }
   }
 }
@@ -765,7 +880,7 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
   const int32_t total = B.chunk_base[B.n_jobs];
   for (int32_t ch = gw; ch < total; ch += nwv) {
     // a chunk never spans two jobs, so the job is the same for the whole wave
-    const int j = job_of(B.chunk_base, B.n_jobs, ch);
+    const int j = B.chunk_job[ch];
     const BJob &J = B.jobs[j];
     if (*J.out.d_total_words > J.out.cap_words) continue;
     const int32_t n_e = B.piece_base[j + 1] - B.piece_base[j];
@@ -890,6 +1005,13 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const size_t o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
+  int64_t sum_n = 0, sum_chunks = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    sum_n += jobs[i].g.n;
+    sum_chunks += (jobs[i].g.n + kWave - 1) / kWave;
+  }
+  const size_t o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
+  const size_t o_hjob = take(sizeof(int32_t) * (size_t)(sum_chunks > 0 ? sum_chunks : 1));
   const size_t o_counters = take(sizeof(unsigned int) * 8);
   const size_t o_order = take(sizeof(int32_t) * n_jobs);
   int32_t n_mt = 0;
@@ -991,6 +1113,8 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.comp_base = (int32_t *)(b->mem + o_cbase);
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
+  d.comp_job = (int32_t *)(b->mem + o_cjob);
+  d.chunk_job = (int32_t *)(b->mem + o_hjob);
   d.counters = (unsigned int *)(b->mem + o_counters);
   d.mt_cnt = (int2 *)(b->mem + o_mtcnt);
   d.job_order = (const int32_t *)(b->mem + o_order);
@@ -1031,7 +1155,9 @@ int cg_batch_run(cg_batch *b, void *stream) {
     else if (T == 512) launch_vertex_fill<512>(b, st);
     else launch_vertex_fill<1024>(b, st);
   }
+  CG_LAUNCH(ctx, kb_induce_small, dim3(4 * PB), dim3(kIndSmallBlock), st, B);
   CG_LAUNCH(ctx, kb_induce, dim3(PB), dim3(kIndBlock), st, B);
+  CG_LAUNCH(ctx, kb_walk_small, dim3(4 * PB), dim3(kWalkSmallBlock), st, B);
   CG_LAUNCH(ctx, kb_walk, dim3(PB), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);
   CG_LAUNCH(ctx, kb_copy, dim3(PB), dim3(b->prm.copy_block), st, B);

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kIndBlock) void k_ind_local(const int32_t *__restri
   __shared__ int32_t a[kIndLocalCap];
   const int nc = *d_n_comp;
   for (int c = blockIdx.x; c < nc; c += gridDim.x)
-    sort_component_block(comp_size[c], comp_start[c], tmp + comp_start[c], perm, lidx, a);
+    sort_component_block<kIndBlock, kIndLocalCap>(comp_size[c], comp_start[c], tmp + comp_start[c], perm, lidx, a);
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_ind_rows(
