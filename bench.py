@@ -113,21 +113,98 @@ def workload_graphs(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": model}
+
+
+def _pool_worker(idx, Ps, barrier, q):
+    import oracle
+    import synth
+    # this worker's graphs of the batched workload, regenerated from their seeds
+    gs = synth.batch_graphs(512, only=idx)
+    barrier.wait()
+    t0 = time.perf_counter()
+    bases, busy = 0, 0.0
+    for g, P in zip(gs, Ps):
+        tm = {}
+        bases += int(oracle.run(g, P=P, min_reads=2, timings=tm)["contigs"]["len"].sum())
+        busy += tm["total"]
+    q.put((bases, time.perf_counter() - t0, len(gs), busy))
+
+
+def cpu_pool_baseline(graphs, Ps, workers):
+    """The single-threaded oracle in `workers` processes, one graph at a time
+    per process (graph-level parallelism only); graphs go to workers by LPT on
+    their read counts.  Wall time runs from a barrier all workers reach after
+    building their inputs to the last worker's end."""
+    import multiprocessing as mp
+    mpc = mp.get_context("spawn")
+    load = [0] * workers
+    part = [[] for _ in range(workers)]
+    # graph k of the list is graph ids[k] of the batched workload's generator
+    ids = [int(g.meta["name"].rsplit("-", 1)[1]) for g in graphs]
+    for i in sorted(range(len(graphs)), key=lambda i: (-graphs[i].n, i)):
+        w = min(range(workers), key=lambda w: (load[w], w))
+        part[w].append(i)
+        load[w] += graphs[i].n
+    barrier, q = mpc.Barrier(workers + 1), mpc.Queue()
+    procs = [mpc.Process(target=_pool_worker,
+                         args=([ids[i] for i in part[w]], [Ps[i] for i in part[w]], barrier, q))
+             for w in range(workers) if part[w]]
+    barrier = barrier if len(procs) == workers else None
+    if barrier is None:
+        raise RuntimeError("fewer graphs than workers")
+    for pr in procs:
+        pr.start()
+    barrier.wait(timeout=600)
+    t0 = time.perf_counter()
+    res = [q.get(timeout=600) for _ in procs]
+    wall = time.perf_counter() - t0
+    for pr in procs:
+        pr.join()
+    bases = sum(r[0] for r in res)
+    busiest = max(r[3] for r in res)
+    # timed like the single-threaded baseline: the C oracle's own clock, here
+    # that of the busiest worker; the wall time adds the Python marshalling
+    return {"value": bases / busiest, "unit": "contig bases/s", "cores": workers,
+            "kind": "oracle",
+            "sample": "all %d graphs (%d contig bases), %d processes of the single-threaded C "
+                      "oracle, one graph at a time each" % (len(graphs), bases, workers),
+            "seconds": busiest, "wall_s": wall,
+            "timing": "C oracle phase clocks of the busiest worker (wall_s: barrier to last "
+                      "result, Python marshalling included)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g", "serve"])
-    ap.add_argument("--requests", type=int, default=500, help="serve: measured requests")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: measured requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests on the GPU")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle's CPU baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-workers", type=int,
+                    default=min(16, len(os.sched_getaffinity(0))),
+                    help="processes of the oracle pool baseline (batched workload)")
     ap.add_argument("--shape", default="",
                     help="vertex_tile,copy_block,persist_blocks of the batched form (skips tuning)")
     ap.add_argument("--skip-plain", action="store_true",
                     help="profile runs: leave out the plain per-graph form")
+    ap.add_argument("--reps", type=int, default=20,
+                    help="repetitions behind the median per-kernel timings (warm and cold)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device a few times (the reference kernel "
                          "that scales HBM byte counters), then exit")
@@ -192,6 +269,31 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
 
+    # a buffer larger than the 256 MB Infinity Cache: writing it before a rep
+    # leaves none of the path's data in cache ("cold")
+    flush = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+
+    def kernel_reps(step, stream_, reps, cold):
+        """Median over reps of each kernel's per-step time, and of the step's
+        time between events; cold reps flush the cache first."""
+        per, whole = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for r in range(reps):
+            if cold:
+                flush.fill_(r)
+            ctx.profile(64)
+            e0.record(stream_)
+            step()
+            e1.record(stream_)
+            prof = ctx.profile_read()
+            ctx.profile(0)
+            torch.cuda.synchronize()
+            whole.append(e0.elapsed_time(e1))
+            per.append({k: v[1] for k, v in prof.items() if k[0] != "_"})
+        keys = sorted(set().union(*per))
+        return ({k: float(np.median([p.get(k, 0.0) for p in per])) for k in keys},
+                float(np.median(whole)))
+
     def kernel_profile(step, steps, launches_per_step):
         ctx.profile(launches_per_step * steps + 64)
         for _ in range(steps):
@@ -230,6 +332,14 @@ def main():
     log("batched: %.3f ms/step wall, %.3f ms/step between events" % (b_wall, b_gpu))
     with torch.cuda.stream(side):
         batch_kern = kernel_profile(lambda: batch.run(side), args.steps, 16)
+        # medians of per-kernel times, warm and cold (the primary mask+CC
+        # number is cold: the cache would otherwise hold its whole working set)
+        for _ in range(3):
+            batch.run(side)
+        warm_k, warm_step = kernel_reps(lambda: batch.run(side), side, args.reps, False)
+        cold_k, cold_step = kernel_reps(lambda: batch.run(side), side, args.reps, True)
+    log("batched, median of %d: warm %.3f ms/step, cold %.3f ms/step (eager launches with "
+        "per-kernel events)" % (args.reps, warm_step, cold_step))
     assert ctx.status(side) == 0, "device status raised"
 
     # ---- workload sizes (from one step's device-side counts) ---------------
@@ -252,14 +362,17 @@ def main():
         return {
             # the batched form hooks in the mask pass
             "mask": pick(lambda k: k in ("k_mask", "kb_mask_list")),
-            "components": pick(lambda k: k.startswith("k_cc") or k == "kb_cc_local"),
+            "components": pick(lambda k: k.startswith("k_cc") or k.startswith("kb_cc")),
             "partition": pick(lambda k: k.startswith("k_part") or k.startswith("kb_compact")
                               or k.startswith("kb_tilecount") or k == "kb_lpt"),
             "induce": pick(lambda k: k.startswith("k_ind") or k.startswith("kb_fill")
-                           or k == "kb_induce"),
-            "assemble": pick(lambda k: k.startswith("k_asm") or k in ("kb_walk", "kb_offsets",
-                                                                       "kb_copy")),
+                           or k.startswith("kb_induce")),
+            "assemble": pick(lambda k: k.startswith("k_asm") or k.startswith("kb_walk")
+                             or k in ("kb_offsets", "kb_copy")),
         }
+
+    def medians(km):
+        return phases({k: (1, v) for k, v in km.items()})
 
     for name, kern in (("plain", plain_kern), ("batched", batch_kern)):
         for k, (c, ms) in sorted(kern.items(), key=lambda kv: -kv[1][1]):
@@ -267,16 +380,24 @@ def main():
                 % (name, k, c, ms, 1e3 * ms / c))
 
     b_ph = phases(batch_kern)
+    warm_ph, cold_ph = medians(warm_k), medians(cold_k)
     maskcc_ms = b_ph["mask"] + b_ph["components"]
     # fused minimum of mask + components: row_ptr, the columns of degree <= 2
     # rows, flags written, labels written (each array once)
     maskcc_bytes = 4 * (st["N"] + 1) + 4 * st["m_nb"] + st["N"] + 4 * st["N"]
+
+    def maskcc(ph):
+        ms = ph["mask"] + ph["components"]
+        return {"ms": ms, "edges_per_s": st["m"] / (ms * 1e-3),
+                "hbm_frac": maskcc_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
     kname = lambda k: k.replace("kb_", "k_").replace("<T>", "")
     dom = max(batch_kern, key=lambda k: batch_kern[k][1])
     dom_launches, dom_ms = batch_kern[dom]
     dom_avg_us = 1e3 * dom_ms / dom_launches
     dom_map = {"kb_copy": ["k_asm_copy"], "kb_walk": ["k_asm_walk"], "kb_lpt": ["k_part_lpt"],
-               "kb_induce": ["k_ind_local", "k_ind_rows"], "kb_mask_list": ["k_mask"],
+               "kb_walk_small": ["k_asm_walk"],
+               "kb_induce": ["k_ind_local", "k_ind_rows"],
+               "kb_induce_small": ["k_ind_local", "k_ind_rows"], "kb_mask_list": ["k_mask"],
                "kb_cc_local": ["k_cc_hook", "k_cc_compress"],
                "kb_fill<T>": ["k_ind_fill"],
                "kb_offsets": ["k_asm_offsets"]}
@@ -297,7 +418,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (seeded simulated genomes and reads; exact reduced string graphs)",
-        "config": {"workload": desc, "form": "batched: one HIP graph of 10 launches for all graphs",
+        "config": {"workload": desc,
+                   "form": "batched: one HIP graph of %d launches for all graphs"
+                           % int(round(sum(v[0] for v in batch_kern.values()))),
                    "graphs": len(graphs), "reads": st["N"], "directed_entries": st["m"],
                    "contig_reads": st["n_e"], "contigs": st["n_comp"],
                    "contig_bases": st["contig_bases"],
@@ -306,7 +429,18 @@ def main():
                                     "persist_blocks": shape[2]}},
         "batched": {"ms_per_step": b_wall, "gpu_ms_per_step": b_gpu,
                     "contig_bases_per_s": st["contig_bases"] / (b_wall * 1e-3),
-                    "phase_kernel_ms": b_ph},
+                    "phase_kernel_ms": b_ph,
+                    "median_of": args.reps,
+                    "warm": {"ms_per_step": warm_step, "phase_kernel_ms": warm_ph,
+                             "kernel_ms": warm_k,
+                             "contig_bases_per_s_assemble":
+                                 st["contig_bases"] / (warm_ph["assemble"] * 1e-3)},
+                    "cold": {"ms_per_step": cold_step, "phase_kernel_ms": cold_ph,
+                             "kernel_ms": cold_k,
+                             "contig_bases_per_s": st["contig_bases"] / (cold_step * 1e-3),
+                             "contig_bases_per_s_assemble":
+                                 st["contig_bases"] / (cold_ph["assemble"] * 1e-3),
+                             "flush": "1 GiB written before each rep"}},
         "plain": {"ms_per_step": plain_wall, "gpu_ms_per_step": plain_gpu,
                   "contig_bases_per_s": st["contig_bases"] / (plain_wall * 1e-3),
                   "phase_kernel_ms": phases(plain_kern)},
@@ -315,7 +449,9 @@ def main():
         "mask_cc": {"ms_per_step": maskcc_ms, "algorithmic_bytes": maskcc_bytes,
                     "hbm_frac": maskcc_bytes / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
                     if maskcc_ms else None,
-                    "kernels": "kb_mask_list + kb_cc_local (the latter also builds the component table and groups members)"},
+                    "cold_median": maskcc(cold_ph), "warm_median": maskcc(warm_ph),
+                    "kernels": "kb_mask_list + kb_cc_prep + kb_cc_local (the last also builds the component "
+                               "table and groups members)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic(kname(dom).replace("k_", "kb_", 1))
@@ -352,6 +488,11 @@ def main():
             "seconds": spent}
         result["parity_sample"] = {"graphs": done, "identical": ok}
         log("oracle: %d graphs in %.1fs, parity %d/%d" % (done, spent, ok, done))
+        result["host"] = host_info()
+        if args.workload == "batch" and args.cpu_workers > 1:
+            pool = cpu_pool_baseline(graphs, Ps, args.cpu_workers)
+            result["cpu_baseline_pool"] = pool
+            log("oracle pool: %d processes, %.2fs wall" % (args.cpu_workers, pool["seconds"]))
     print(json.dumps(result), flush=True)
 
 
@@ -393,7 +534,7 @@ def serve_bench(args):
     log("alone: mean service %.2f ms -> arrival rate %.1f requests/s" % (1e3 * svc.mean(), rate))
     n_warm = max(args.requests // 10, 10)
     busy = 0.0
-    for attempt in range(2):
+    for attempt in range(3):
         reqs, span, peak = srv.run(stream(n_warm + args.requests, rate, 20220709 + attempt))
         busy = serve.busy_fraction(reqs, span)
         log("rate %.1f/s: busy %.2f over %.2fs" % (rate, busy, span))

@@ -640,6 +640,8 @@ __device__ __forceinline__ uint32_t rev_fields32(uint32_t v) {
   return ((y >> 1) & 0x55555555u) | ((y & 0x55555555u) << 1);
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // One piece as the copy needs it.
 struct PieceD {
   uint64_t src;   // base offset of the piece's read in the store
@@ -827,23 +829,38 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     S.ok[u] = g < G;
     S.k[u] = S.ok[u] ? 4 * (g - gs) : 0;  // first owned word of the group
   }
-  // loads only, unconditional and clamped, so that nothing here waits for
-  // memory and the step's loads stay in flight while the previous step is
-  // finished
+  // loads only, so that nothing here waits for memory and the step's loads
+  // stay in flight while the previous step is finished
 #pragma unroll
   for (int u = 0; u < kCopyUnroll; ++u) {
     const CopyD &d = S.d[u];
     const bool rev = d.info & 32u;
     const uint64_t w = d.w0 + S.k[u];
-    // the piece's window: 5 store words covering the group's 64 bases
+    // the piece's window: 5 store words covering the group's 64 bases, as
+    // one 16-byte load (dword aligned) and a dword; clamped word by word at
+    // the ends of the store, where the words outside it are never used
     const uint64_t sb = rev ? d.base - 16 * w : d.base + 16 * w;
     const int64_t sw = S.ok[u] ? (int64_t)sb >> 4 : 0;
+    if (sw >= 0 && sw + 5 <= (int64_t)nwords) {
+      u32x4 a;
+      __builtin_memcpy(&a, seq + sw, 16);
+      S.win[u][0] = a.x;
+      S.win[u][1] = a.y;
+      S.win[u][2] = a.z;
+      S.win[u][3] = a.w;
+      S.win[u][4] = seq[sw + 4];
+    } else {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
-    // the next piece's first 16 bases, for the piece's last word
-    const int64_t hw = (int64_t)S.e[u].hsrc >> 4;
-    S.hlo[u] = seq[clamp_word(hw, nwords)];
-    S.hhi[u] = seq[clamp_word(hw + 1, nwords)];
+      for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
+    }
+    // the next piece's first 16 bases, for the group holding the piece's
+    // last word
+    S.hlo[u] = S.hhi[u] = 0;
+    if (S.ok[u] && S.k[u] + 4 >= d.nw) {
+      const int64_t hw = (int64_t)S.e[u].hsrc >> 4;
+      S.hlo[u] = seq[clamp_word(hw, nwords)];
+      S.hhi[u] = seq[clamp_word(hw + 1, nwords)];
+    }
   }
 }
 
@@ -894,9 +911,14 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
       out[nw - 1] = x;
     }
     CG_GLOBAL uint32_t *o = bases + d.w0 + S.k[u];
+    if (nw == 4) {
+      const u32x4 v = {out[0], out[1], out[2], out[3]};
+      __builtin_memcpy(o, &v, 16);  // one 16-byte store, dword aligned
+    } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i < (int)nw) o[i] = out[i];
+      for (int i = 0; i < 4; ++i)
+        if (i < (int)nw) o[i] = out[i];
+    }
   }
 }
 

@@ -34,12 +34,33 @@ struct BJob {
   cg_contigs out;
   Scratch s;
   uint64_t *forest;            // [n] tagged union-find forest (batch-owned, never reused)
-  int4 *conn_list;             // [n] reads of degree 1-2: (id, columns or -1, degree), each
-                               // mask tile's reads packed in id order at the start of its slice
+  int4 *conn_list;             // [n] reads of degree 1-2, each mask tile's reads packed in id
+                               // order at the start of its slice: (id, columns or -1, degree)
+                               // from the mask pass, then (id, s0, s1, kept bits) from the
+                               // neighbour pass, s_k the list slot of neighbour k when its
+                               // entry is kept and its id is smaller, else -1
   int32_t *conn_map;           // [n] slot of a listed read in conn_list
   int32_t vt_first, vt_count;  // the job's vertex tiles (covering 0..n)
   int32_t mt_first, mt_count;  // the job's mask tiles
 };
+
+// A job's descriptor by value.  The job table is read-only while a launch
+// runs, so it is read through the constant address space: with a uniform job
+// index the fields arrive by scalar loads, and no LDS store can alias them.
+#define CG_CONST __attribute__((address_space(4)))
+static_assert(sizeof(BJob) % 8 == 0, "job descriptors are copied in 8-byte words");
+__device__ __forceinline__ BJob job_at(const BJob *jobs, int j) {
+  BJob out;
+  const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(jobs + j);
+  uint64_t *q = reinterpret_cast<uint64_t *>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(BJob) / 8); ++k) q[k] = p[k];
+  return out;
+}
+// the same for the batch-wide tables that an earlier launch wrote
+__device__ __forceinline__ int32_t ld_const(const int32_t *a, int64_t i) {
+  return ((const CG_CONST int32_t *)a)[i];
+}
 
 // One tile of the mask pass: kMaskTile consecutive reads of one job.
 struct MaskTile {
@@ -54,7 +75,9 @@ struct MaskTile {
   int32_t n, v0;
   int32_t lc_init;  // first value of label_comp: -1, or 4 (one-read count) when
                     // one-read components can be eligible
+  int32_t pad_;
 };
+static_assert(sizeof(MaskTile) % 8 == 0, "tile descriptors are copied in 8-byte words");
 constexpr int kMaskThreads = 256;
 constexpr int kMaskGroups = 2;  // groups of 4 consecutive reads per thread
 constexpr int kMaskTile = 4 * kMaskThreads * kMaskGroups;
@@ -188,6 +211,58 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__r
   if (threadIdx.x == 0) *D.tile_cnt = make_int2(tot_all & 0xFFFF, tot_all >> 16);
 }
 
+// 1b. the neighbour lookups of every listed read, spread over the whole chip
+// (done inside the components pass they would fall on one CU per job): kept
+// bits from the neighbours' branch bits, and the list slots of the kept
+// neighbours with smaller ids, written back into the read's list entry
+constexpr int kPrepChunks = kMaskTile / kMaskThreads;
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kMaskThreads) void kb_cc_prep(const MaskTile *__restrict__ tiles) {
+  // the tile descriptor through the constant address space (scalar loads),
+  // its arrays as global memory
+  MaskTile D;
+  {
+    const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(tiles + blockIdx.x);
+    uint64_t *q = reinterpret_cast<uint64_t *>(&D);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(MaskTile) / 8); ++k) q[k] = p[k];
+  }
+  const int32_t c = ((const CG_GLOBAL int2 *)D.tile_cnt)->x;
+  if (c == 0) return;
+  CG_GLOBAL i32x4 *list = (CG_GLOBAL i32x4 *)D.conn_list + D.v0;
+  const CG_GLOBAL uint8_t *flags = (const CG_GLOBAL uint8_t *)D.flags;
+  const CG_GLOBAL int32_t *map = (const CG_GLOBAL int32_t *)D.conn_map;
+  // all loads of the thread's entries in flight before any is used; slots at
+  // or past c read slot 0 and are then treated as empty (a listed read's
+  // job has at least one read, so index 0 is in bounds)
+  i32x4 e[kPrepChunks];
+#pragma unroll
+  for (int k = 0; k < kPrepChunks; ++k) {
+    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
+    e[k] = list[i < c ? i : 0];
+  }
+  uint32_t b0[kPrepChunks], b1[kPrepChunks];
+  int32_t m0[kPrepChunks], m1[kPrepChunks];
+#pragma unroll
+  for (int k = 0; k < kPrepChunks; ++k) {
+    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
+    if (i >= c) e[k] = i32x4{-1, -1, -1, 0};
+    const int32_t u0 = e[k].y >= 0 ? e[k].y : 0, u1 = e[k].z >= 0 ? e[k].z : 0;
+    b0[k] = flags[u0];
+    b1[k] = flags[u1];
+    m0[k] = map[u0];
+    m1[k] = map[u1];
+  }
+#pragma unroll
+  for (int k = 0; k < kPrepChunks; ++k) {
+    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
+    if (i >= c) continue;
+    const bool k0 = e[k].y >= 0 && !(b0[k] & 1), k1 = e[k].z >= 0 && !(b1[k] & 1);
+    list[i] = i32x4{e[k].x, k0 && e[k].y < e[k].x ? m0[k] : -1, k1 && e[k].z < e[k].x ? m1[k] : -1,
+                    (k0 ? 2 : 0) | (k1 ? 4 : 0)};
+  }
+}
+
 // 2. components of each job in one workgroup, from its listed reads: kept
 // bits (both ends outside the branch set), union-find in LDS (roots =
 // smallest read id), labels, exact per-root counts, and, when one-read
@@ -228,15 +303,6 @@ __device__ __forceinline__ void lds_union(int32_t *par, int a, int b) {
   }
 }
 
-// kept bits of a listed read from its neighbours' branch bits
-__device__ __forceinline__ uint32_t kept_bits(const uint8_t *__restrict__ flags, int32_t u0,
-                                              int32_t u1) {
-  uint32_t f = 0;
-  if (u0 >= 0 && !(flags[u0] & 1)) f |= 2;
-  if (u1 >= 0 && !(flags[u1] & 1)) f |= 4;
-  return f;
-}
-
 __device__ __forceinline__ uint8_t kind_of(uint32_t c4) {
   return (c4 >> 2) == 1 ? CG_KIND_SINGLE : ((c4 & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
 }
@@ -248,8 +314,8 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
   __shared__ int32_t s_par[kCcCap], s_aux[kCcCap];
   __shared__ int32_t s_pref[kCcTileCap + 1];
   __shared__ int64_t sh64[kCcBlock / kWave + 1];
-  const int j = B.job_order[blockIdx.x];
-  const BJob &J = B.jobs[j];
+  const int j = ld_const(B.job_order, blockIdx.x);
+  const BJob J = job_at(B.jobs, j);
   const int nt = J.mt_count;
   const int tid = threadIdx.x;
   const bool table = J.min_reads >= 2;
@@ -269,11 +335,17 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
   __syncthreads();
   int64_t m_l = 0;
   if (L > 0 && (nt > kCcTileCap || L > kCcCap)) {
-    cc_global(B, J, nt, tc, sh64, &m_l);
+    cc_global(B, B.jobs[j], nt, tc, sh64, &m_l);
   } else if (L > 0) {
+    // All of this thread's loads are issued before any is used, and every
+    // global store waits for the tail: a barrier behind scattered stores
+    // waits for them to land.
     const int per = (int)((L + kCcBlock - 1) / kCcBlock);
     const int l0 = tid * per;
-    int t = 0;
+    // 1. this thread's listed reads l0 .. l0 + per - 1: their slots in the
+    // tiles' lists, their entries, then their neighbours' branch bits and
+    // list slots
+    int32_t slot[kCcPer];
     {
       int lo = 0, hi = nt - 1;  // tile of local number l0
       while (lo < hi) {
@@ -281,23 +353,20 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
         if (s_pref[mid] <= l0) lo = mid;
         else hi = mid - 1;
       }
-      t = lo;
-    }
-    int32_t w0[kCcPer], w1[kCcPer];
+      int t = lo;
 #pragma unroll
-    for (int k = 0; k < kCcPer; ++k) {
-      const int l = l0 + k;
-      w0[k] = w1[k] = -1;
-      if (k < per && l < L) {
-        while (s_pref[t + 1] <= l) ++t;
-        const int4 e = J.conn_list[t * kMaskTile + (l - s_pref[t])];
-        s_aux[l] = e.x;
-        s_par[l] = l;
-        w0[k] = e.y;
-        w1[k] = e.z;
+      for (int k = 0; k < kCcPer; ++k) {
+        const int l = l0 + k;
+        slot[k] = -1;
+        if (k < per && l < L) {
+          while (s_pref[t + 1] <= l) ++t;
+          slot[k] = t * kMaskTile + (l - s_pref[t]);
+        }
       }
     }
-    // kept bits and the local numbers of the kept neighbours with smaller ids
+    int4 e[kCcPer];
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) e[k] = J.conn_list[slot[k] >= 0 ? slot[k] : 0];
     uint32_t fk[kCcPer];
     int32_t lu0[kCcPer], lu1[kCcPer];
 #pragma unroll
@@ -305,21 +374,17 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
       const int l = l0 + k;
       fk[k] = 0;
       lu0[k] = lu1[k] = -1;
-      if (k < per && l < L) {
-        const int32_t id = s_aux[l];
-        fk[k] = kept_bits(J.flags, w0[k], w1[k]);
-        if ((fk[k] & 2) && w0[k] < id) {
-          const int32_t p = J.conn_map[w0[k]];
-          lu0[k] = s_pref[p / kMaskTile] + p % kMaskTile;
-        }
-        if ((fk[k] & 4) && w1[k] < id) {
-          const int32_t p = J.conn_map[w1[k]];
-          lu1[k] = s_pref[p / kMaskTile] + p % kMaskTile;
-        }
+      if (slot[k] >= 0) {
+        fk[k] = (uint32_t)e[k].w;
+        s_aux[l] = e[k].x;
+        s_par[l] = l;
+        if (e[k].y >= 0) lu0[k] = s_pref[e[k].y / kMaskTile] + e[k].y % kMaskTile;
+        if (e[k].z >= 0) lu1[k] = s_pref[e[k].z / kMaskTile] + e[k].z % kMaskTile;
         m_l += __popc(fk[k]);
       }
     }
     __syncthreads();
+    // 2. union-find over local numbers (the larger root under the smaller)
 #pragma unroll
     for (int k = 0; k < kCcPer; ++k) {
       if (lu0[k] >= 0) lds_union(s_par, l0 + k, lu0[k]);
@@ -330,10 +395,10 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
 #pragma unroll
     for (int k = 0; k < kCcPer; ++k) r[k] = fk[k] ? lds_find(s_par, l0 + k) : l0 + k;
     __syncthreads();
-    // s_par becomes the per-root counter: 4 per read + 1 per path end
+    // 3. s_par becomes the per-root counter: 4 per read + 1 per path end
 #pragma unroll
     for (int k = 0; k < kCcPer; ++k)
-      if (k < per && l0 + k < L) s_par[l0 + k] = 0;
+      if (slot[k] >= 0) s_par[l0 + k] = 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kCcPer; ++k)
@@ -345,27 +410,22 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
     for (int k = 0; k < kCcPer; ++k) {
       const int l = l0 + k;
       c4[k] = 0;
-      if (k < per && l < L) {
-        const int32_t id = s_aux[l];
-        if (fk[k]) {
-          J.flags[id] = (uint8_t)fk[k];
-          J.label[id] = s_aux[r[k]];
-          if (r[k] == l) c4[k] = s_par[l];
-        } else {
-          c4[k] = 4;
-        }
-        if (!table) {
-          if (fk[k]) J.parts.label_comp[id] = c4[k];  // 0 for non-roots
-        } else if (fk[k] && r[k] == l && (c4[k] >> 2) >= J.min_reads) {
+      if (slot[k] >= 0) {
+        if (!fk[k]) c4[k] = 4;
+        else if (r[k] == l) c4[k] = s_par[l];
+        if (table && fk[k] && r[k] == l && (c4[k] >> 2) >= J.min_reads) {
           ++ne;
           nq += c4[k] >> 2;
         }
       }
     }
+    // 4. one scan: eligible roots, their reads and the kept entries (21 bits each)
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kCcBlock>(
+        ((int64_t)ne << 42) | ((int64_t)nq << 21) | m_l, sh64, &tot);
+    const int64_t kMask21 = (1 << 21) - 1;
     if (table) {
-      int64_t tot;
-      const int64_t ex = block_excl_scan<int64_t, kCcBlock>(((int64_t)ne << 32) | nq, sh64, &tot);
-      int32_t cb = (int32_t)(ex >> 32), mb = (int32_t)(ex & 0xFFFFFFFF);
+      int32_t cb = (int32_t)(ex >> 42), mb = (int32_t)((ex >> 21) & kMask21);
       // s_par: member cursor of each eligible root, kNotEligible elsewhere
 #pragma unroll
       for (int k = 0; k < kCcPer; ++k) {
@@ -388,14 +448,27 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
         }
       }
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k)
-        if (fk[k]) {
-          const int32_t pos = atomicAdd(s_par + r[k], 1);
-          if (pos >= 0) J.s.tmp[pos] = s_aux[l0 + k];
-        }
-      if (tid == 0) *J.parts.d_n_comp = (int32_t)(tot >> 32);
     }
+    // 5. the tail: members, flags, labels, counts
+#pragma unroll
+    for (int k = 0; k < kCcPer; ++k) {
+      if (!fk[k]) continue;
+      const int32_t id = s_aux[l0 + k];
+      J.flags[id] = (uint8_t)fk[k];
+      J.label[id] = s_aux[r[k]];
+      if (table) {
+        const int32_t at = atomicAdd(s_par + r[k], 1);
+        if (at >= 0) J.s.tmp[at] = id;
+      } else {
+        J.parts.label_comp[id] = c4[k];  // 0 for non-roots
+      }
+    }
+    if (tid == 0) {
+      if (table) *J.parts.d_n_comp = (int32_t)(tot >> 42);
+      J.counts[0] = (int32_t)n_branch;
+      J.counts[1] = (int32_t)(tot & kMask21);
+    }
+    return;
   }
   if (L == 0 && table && tid == 0) *J.parts.d_n_comp = 0;
   // BranchRemoval's counts: branch reads and kept entries
@@ -421,7 +494,7 @@ __device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *
     const int32_t c = tc[t].x;
     for (int i = tid; i < c; i += kCcBlock) {
       const int4 e = J.conn_list[t * kMaskTile + i];
-      const uint32_t f = kept_bits(J.flags, e.y, e.z);
+      const uint32_t f = (uint32_t)e.w;
       if (f) {
         J.flags[e.x] = (uint8_t)f;
         lc[e.x] = 0;
@@ -435,9 +508,8 @@ __device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *
     const int32_t c = tc[t].x;
     for (int i = tid; i < c; i += kCcBlock) {
       const int4 e = J.conn_list[t * kMaskTile + i];
-      const uint32_t f = J.flags[e.x];
-      if ((f & 2) && e.y < e.x) tf_union(J.forest, tag, e.x, e.y);
-      if ((f & 4) && e.z < e.x) tf_union(J.forest, tag, e.x, e.z);
+      if (e.y >= 0) tf_union(J.forest, tag, e.x, J.conn_list[e.y].x);
+      if (e.z >= 0) tf_union(J.forest, tag, e.x, J.conn_list[e.z].x);
     }
   }
   __syncthreads();
@@ -529,7 +601,7 @@ template <int T>
 __global__ __launch_bounds__(T) void kb_tilecount(BatchDev B) {
   __shared__ int32_t sh[T / kWave];
   const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
+  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
   if (J.min_reads >= 2) return;  // table and members come from the components pass
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   uint32_t c = 0;
@@ -548,7 +620,7 @@ template <int T>
 __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
   __shared__ int32_t sh[T / kWave + 1];
   const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
+  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
   if (J.min_reads >= 2) return;  // table and members come from the components pass
   int32_t before = 0;
   for (int i = J.vt_first + (int)threadIdx.x; i < t; i += T) before += B.tile_cnt[i];
@@ -583,7 +655,7 @@ __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
 template <int T>
 __global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
   const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
+  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
   if (J.weight != CG_WEIGHT_BASES) return;
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   if (v >= J.g.n) return;
@@ -602,7 +674,7 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   __shared__ uint64_t s_binA[kBatchBinCap], s_binB[kBatchBinCap];
   __shared__ int64_t sh[kLptBlock / kWave + 1];
   const int j = blockIdx.x;
-  const BJob &J = B.jobs[j];
+  const BJob J = job_at(B.jobs, j);
   const int P = J.P;
   const int nc = *J.parts.d_n_comp;
   const uint64_t *wts = J.weight == CG_WEIGHT_BASES ? J.s.comp_w : nullptr;
@@ -701,7 +773,7 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
 template <int T>
 __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   const int t = blockIdx.x;
-  const BJob &J = B.jobs[B.tile_job[t]];
+  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
   if (J.min_reads >= 2) return;  // table and members come from the components pass
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   if (v >= J.g.n) return;
@@ -724,8 +796,8 @@ __device__ __forceinline__ int gather_components(const BatchDev &B, int32_t tota
     const int64_t i = (int64_t)blockIdx.x + ((int64_t)r * kWave + lane) * gridDim.x;
     bool hit = false;
     if (i < total) {
-      const int j = B.comp_job[i];
-      const int q = B.jobs[j].parts.comp_size[i - B.comp_base[j]];
+      const int j = ld_const(B.comp_job, i);
+      const int q = B.jobs[j].parts.comp_size[i - ld_const(B.comp_base, j)];
       hit = q > lo && q <= hi;
     }
     const uint64_t m = __ballot(hit);
@@ -746,9 +818,9 @@ __device__ __forceinline__ int gather_rounds(int32_t total) {
 template <int BLOCK, int CAP>
 __device__ __forceinline__ void induce_listed(const BatchDev &B, int32_t i, int32_t *a,
                                               int32_t *sh_scan) {
-  const int j = B.comp_job[i];
-  const BJob &J = B.jobs[j];
-  const int c = i - B.comp_base[j];
+  const int j = ld_const(B.comp_job, i);
+  const BJob J = job_at(B.jobs, j);
+  const int c = i - ld_const(B.comp_base, j);
   const int32_t *members = J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : J.parts.comp_start[c]);
   induce_component<BLOCK, CAP>(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c],
                                members, J.flags, J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx,
@@ -761,12 +833,13 @@ __global__ __launch_bounds__(kIndSmallBlock) void kb_induce_small(BatchDev B) {
   __shared__ int32_t sh_scan[kIndSmallBlock / kWave + 1];
   __shared__ int32_t list[kWave];
   __shared__ int cnt;
-  const int32_t total = B.comp_base[B.n_jobs];
+  const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
     const int k = gather_components(B, total, r, 0, kIndSmallCap, list, &cnt);
     for (int t = 0; t < k; ++t)
-      induce_listed<kIndSmallBlock, kIndSmallCap>(B, list[t], a, sh_scan);
+      induce_listed<kIndSmallBlock, kIndSmallCap>(B, __builtin_amdgcn_readfirstlane(list[t]), a,
+                                                  sh_scan);
   }
 }
 
@@ -776,11 +849,12 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
   __shared__ int32_t list[kWave];
   __shared__ int cnt;
-  const int32_t total = B.comp_base[B.n_jobs];
+  const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
     const int k = gather_components(B, total, r, kIndSmallCap, 0x7FFFFFFF, list, &cnt);
-    for (int t = 0; t < k; ++t) induce_listed<kIndBlock, kIndLocalCap>(B, list[t], a, sh_scan);
+    for (int t = 0; t < k; ++t)
+      induce_listed<kIndBlock, kIndLocalCap>(B, __builtin_amdgcn_readfirstlane(list[t]), a, sh_scan);
   }
 }
 
@@ -792,15 +866,15 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   __shared__ int32_t list[kWave];
   __shared__ int cnt;
-  const int32_t total = B.comp_base[B.n_jobs];
+  const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
     const int k = gather_components(B, total, r, 0, kWalkSmallCap, list, &cnt);
     for (int t = 0; t < k; ++t) {
-      const int32_t i = list[t];
-      const int j = B.comp_job[i];
-      const BJob &J = B.jobs[j];
-      const int c = i - B.comp_base[j];
+      const int32_t i = __builtin_amdgcn_readfirstlane(list[t]);  // uniform: scalar job loads
+      const int j = ld_const(B.comp_job, i);
+      const BJob J = job_at(B.jobs, j);
+      const int c = i - ld_const(B.comp_base, j);
       WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
       walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
           c, J.parts.comp_size[c], J.parts.comp_start[c], w, J.g, J.parts, J.local.perm,
@@ -816,15 +890,15 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   __shared__ int32_t list[kWave];
   __shared__ int cnt;
-  const int32_t total = B.comp_base[B.n_jobs];
+  const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
     const int k = gather_components(B, total, r, kWalkSmallCap, 0x7FFFFFFF, list, &cnt);
     for (int t = 0; t < k; ++t) {
-      const int32_t i = list[t];
-      const int j = B.comp_job[i];
-      const BJob &J = B.jobs[j];
-      const int c = i - B.comp_base[j];
+      const int32_t i = __builtin_amdgcn_readfirstlane(list[t]);  // uniform: scalar job loads
+      const int j = ld_const(B.comp_job, i);
+      const BJob J = job_at(B.jobs, j);
+      const int c = i - ld_const(B.comp_base, j);
       const int q = J.parts.comp_size[c];
       const int st = J.parts.comp_start[c];
       if (q <= kWalkCap) {
@@ -849,7 +923,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
 // 8. contig word offsets per job
 __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
-  const BJob &J = B.jobs[blockIdx.x];
+  const BJob J = job_at(B.jobs, blockIdx.x);
   const int nc = *J.parts.d_n_comp;
   unsigned long long carry = 0;
   for (int base = 0; base < nc; base += kScanBlock) {
@@ -877,14 +951,14 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
-  const int32_t total = B.chunk_base[B.n_jobs];
+  const int32_t total = ld_const(B.chunk_base, B.n_jobs);
   for (int32_t ch = gw; ch < total; ch += nwv) {
     // a chunk never spans two jobs, so the job is the same for the whole wave
-    const int j = B.chunk_job[ch];
-    const BJob &J = B.jobs[j];
+    const int j = ld_const(B.chunk_job, ch);
+    const BJob J = job_at(B.jobs, j);
     if (*J.out.d_total_words > J.out.cap_words) continue;
-    const int32_t n_e = B.piece_base[j + 1] - B.piece_base[j];
-    const int32_t c0 = (ch - B.chunk_base[j]) * kWave;
+    const int32_t n_e = ld_const(B.piece_base, j + 1) - ld_const(B.piece_base, j);
+    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * kWave;
     const int cnt = n_e - c0 < kWave ? n_e - c0 : kWave;
     copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), c0, cnt, n_e, lane_id());
   }
@@ -1134,8 +1208,10 @@ int cg_batch_run(cg_batch *b, void *stream) {
   const BatchDev &B = b->dev;
   const int T = b->prm.vertex_tile;
   const int PB = b->prm.persist_blocks;
-  if (B.n_mtiles > 0)
+  if (B.n_mtiles > 0) {
     CG_LAUNCH(ctx, kb_mask_list, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
+    CG_LAUNCH(ctx, kb_cc_prep, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
+  }
   CG_LAUNCH(ctx, kb_cc_local, dim3(b->n_jobs), dim3(kCcBlock), st, B);
   // jobs where one-read components are eligible take their component table
   // and member buckets from full vertex passes
