@@ -169,6 +169,7 @@ constexpr int kBinBits = 16;
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
 // a single read, in (bin, label) order) and returns their total.  bin_reads
 // (global memory, read back with atomic loads) gets the reads of each bin.
+template <int BLOCK>
 __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict__ comp_size,
                                         const uint64_t *__restrict__ weight,
                                         uint64_t *keys, int32_t *bin_of, uint64_t *binA,
@@ -181,7 +182,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         const uint8_t *__restrict__ comp_kind = nullptr,
                                         int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
-  __shared__ int32_t sh_scan[kLptBlock / kWave + 1];
+  __shared__ int32_t sh_scan[BLOCK / kWave + 1];
   const int tid = threadIdx.x;
   const int N2 = next_pow2(nc > 0 ? nc : 1);
 
@@ -217,23 +218,24 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
       const int l = tid;
       uint64_t key = l < W ? binA[l] : ~0ull;
       for (int base = 0; base < T; base += kWave) {
-        const int cnt = T - base < kWave ? T - base : kWave;
+        const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
         const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
+        int32_t mine = 0;  // bin of item l, kept in lane l until the batch ends
         for (int t = 0; t < cnt; ++t) {
           // t is uniform: broadcasts are lane reads into scalar registers
-          const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)item, t);
           const uint64_t q =
               0xFFFFFFFFu - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(item >> 32), t);
           const uint64_t k0 =
               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), 0) << 32) |
               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, 0);
-          if (l == 0) bin_of[c] = (int32_t)(k0 & ((1u << kBinBits) - 1));
+          mine = l == t ? (int32_t)(k0 & ((1u << kBinBits) - 1)) : mine;
           const uint64_t nk = k0 + (q << kBinBits);
           const int p = __popcll(__ballot(key < nk)) - 1;  // lanes 1.. below nk
           // the key of lane l + 1 (a wave-wide DPP shift; lane 63 keeps its own)
           const uint64_t nxt = wave_next_u64(key);
           key = l < p ? nxt : (l == p ? nk : key);
         }
+        if (l < cnt) bin_of[(uint32_t)item] = mine;
       }
       if (l < W) win[l] = key;
     }
@@ -277,12 +279,12 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   bitonic_sort(keys, N2);
   for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
   int carry = 0, ecarry = 0;
-  for (int base = 0; base < nc; base += kLptBlock) {
+  for (int base = 0; base < nc; base += BLOCK) {
     const int i = base + tid;
     const uint32_t c = i < nc ? (uint32_t)keys[i] : 0u;
     const int32_t sz = i < nc ? comp_size[c] : 0;
     int32_t tot;
-    const int32_t ex = block_excl_scan<int32_t, kLptBlock>(sz, sh_scan, &tot);
+    const int32_t ex = block_excl_scan<int32_t, BLOCK>(sz, sh_scan, &tot);
     if (i < nc) {
       comp_start[c] = carry + ex;
       comp_rank[c] = i;
@@ -295,7 +297,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         e2 = kd == CG_KIND_PATH ? 2 * (sz - 1) : (kd == CG_KIND_CYCLE ? 2 * sz : 0);
       }
       int32_t etot;
-      const int32_t eex = block_excl_scan<int32_t, kLptBlock>(e2, sh_scan, &etot);
+      const int32_t eex = block_excl_scan<int32_t, BLOCK>(e2, sh_scan, &etot);
       if (i < nc) comp_estart[c] = ecarry + eex;
       ecarry += etot;
     }
@@ -377,11 +379,12 @@ __device__ __forceinline__ void induce_component(
   int carry = 0;
   for (int base = 0; base < q; base += BLOCK) {
     const int i = base + threadIdx.x;
-    int32_t v = -1;
+    int32_t v = -1, b = 0;
     uint32_t f = 0;
     if (i < q) {
       v = in_lds ? a[i] : perm[st + i];
       f = flags[v];
+      b = row_ptr[v];  // with the flags, before the scan
     }
     const int32_t deg = (int32_t)(((f >> 1) & 1) + ((f >> 2) & 1));
     int32_t tot;
@@ -389,7 +392,6 @@ __device__ __forceinline__ void induce_component(
     if (i < q) {
       int32_t r = estart + carry + ex;
       loc_row_ptr[st + i] = r;
-      const int32_t b = row_ptr[v];
       for (int j = 0; j < 2; ++j) {
         if (!(f & (2u << j))) continue;
         const int32_t u = col[b + j];
@@ -430,6 +432,12 @@ struct WalkArrays {
   int32_t *nxt;    // [2q] ray successor
   int32_t *dist;   // [2q] ray length
   int32_t *endv;   // [2q] ray end
+  // the LDS form also keeps what the pieces need, loaded before the doubling:
+  int32_t *vid;    // [q] read id of local read i
+  uint32_t *rlen;  // [q] its length
+  uint8_t *es;     // [2q] strand bits of the entry of slot k
+  uint32_t *eo;    // [2q] its pre (explicit coordinates) or overlap length
+  uint32_t *ep;    // [2q] its post (explicit coordinates)
 };
 
 template <int BLOCK, int CAP, bool kLds>
@@ -448,13 +456,89 @@ __device__ __forceinline__ void walk_component(
     s_carry = 0;
   }
   // 1. local rows of the component's block
-  for (int i = tid; i < q; i += BLOCK) {
-    const int a = loc_row_ptr[st + i], b = loc_row_ptr[st + i + 1];
-    const int deg = b - a;
-    w.nb[2 * i] = deg >= 1 ? loc_col[a] - st : -1;
-    w.nb[2 * i + 1] = deg >= 2 ? loc_col[a + 1] - st : -1;
-    w.eid[2 * i] = deg >= 1 ? loc_eid[a] : -1;
-    w.eid[2 * i + 1] = deg >= 2 ? loc_eid[a + 1] : -1;
+  if constexpr (kLds) {
+    // and, in three rounds of loads issued together, the read ids and
+    // lengths and the entries' strand bits and overlaps (or coordinates)
+    constexpr int R = CAP / BLOCK;
+    const CG_GLOBAL int32_t *lrp = (const CG_GLOBAL int32_t *)loc_row_ptr;
+    const CG_GLOBAL int32_t *lcol = (const CG_GLOBAL int32_t *)loc_col;
+    const CG_GLOBAL int32_t *leid = (const CG_GLOBAL int32_t *)loc_eid;
+    const CG_GLOBAL int32_t *gperm = (const CG_GLOBAL int32_t *)perm;
+    const CG_GLOBAL uint32_t *glen = (const CG_GLOBAL uint32_t *)g.read_len;
+    const CG_GLOBAL uint8_t *gstr = (const CG_GLOBAL uint8_t *)g.strand;
+    const CG_GLOBAL uint32_t *gov =
+        (const CG_GLOBAL uint32_t *)(g.pre ? g.pre : g.ovl);
+    const CG_GLOBAL uint32_t *gpost = (const CG_GLOBAL uint32_t *)g.post;
+    int ra[R], rd[R], rv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = tid + u * BLOCK;
+      ra[u] = rd[u] = rv[u] = 0;
+      if (i < q) {
+        ra[u] = lrp[st + i];
+        rd[u] = lrp[st + i + 1];
+        rv[u] = gperm[st + i];
+      }
+    }
+    int c0[R], c1[R], e0[R], e1[R];
+    uint32_t rl[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = tid + u * BLOCK;
+      const int deg = i < q ? rd[u] - ra[u] : 0;
+      c0[u] = c1[u] = e0[u] = e1[u] = -1;
+      rl[u] = 0;
+      if (i < q) rl[u] = glen[rv[u]];
+      if (deg >= 1) {
+        c0[u] = lcol[ra[u]];
+        e0[u] = leid[ra[u]];
+      }
+      if (deg >= 2) {
+        c1[u] = lcol[ra[u] + 1];
+        e1[u] = leid[ra[u] + 1];
+      }
+    }
+    uint32_t s0[R], s1[R], o0[R], o1[R], p0[R], p1[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      s0[u] = s1[u] = o0[u] = o1[u] = p0[u] = p1[u] = 0;
+      if (e0[u] >= 0) {
+        s0[u] = gstr[e0[u]];
+        o0[u] = gov[e0[u]];
+        if (gpost) p0[u] = gpost[e0[u]];
+      }
+      if (e1[u] >= 0) {
+        s1[u] = gstr[e1[u]];
+        o1[u] = gov[e1[u]];
+        if (gpost) p1[u] = gpost[e1[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = tid + u * BLOCK;
+      if (i >= q) continue;
+      w.nb[2 * i] = c0[u] >= 0 ? c0[u] - st : -1;
+      w.nb[2 * i + 1] = c1[u] >= 0 ? c1[u] - st : -1;
+      w.eid[2 * i] = e0[u];
+      w.eid[2 * i + 1] = e1[u];
+      w.vid[i] = rv[u];
+      w.rlen[i] = rl[u];
+      w.es[2 * i] = (uint8_t)s0[u];
+      w.es[2 * i + 1] = (uint8_t)s1[u];
+      w.eo[2 * i] = o0[u];
+      w.eo[2 * i + 1] = o1[u];
+      w.ep[2 * i] = p0[u];
+      w.ep[2 * i + 1] = p1[u];
+    }
+  } else {
+    for (int i = tid; i < q; i += BLOCK) {
+      const int a = loc_row_ptr[st + i], b = loc_row_ptr[st + i + 1];
+      const int deg = b - a;
+      w.nb[2 * i] = deg >= 1 ? loc_col[a] - st : -1;
+      w.nb[2 * i + 1] = deg >= 2 ? loc_col[a + 1] - st : -1;
+      w.eid[2 * i] = deg >= 1 ? loc_eid[a] : -1;
+      w.eid[2 * i + 1] = deg >= 2 ? loc_eid[a + 1] : -1;
+    }
   }
   __syncthreads();
   // 2. start: the first read of local degree 1 (the smaller-id root, since
@@ -558,47 +642,52 @@ __device__ __forceinline__ void walk_component(
   const int rank_c = parts.comp_rank[c];
   for (int i = tid; i < q; i += BLOCK) {
     int rank = 0, pred = -1, succ = -1, succ_e = -1;
+    int ss = -1;  // slot of i leading to its successor
     if (i == s0) {
-      if (w.nb[2 * i] >= 0) { succ = w.nb[2 * i]; succ_e = w.eid[2 * i]; }
-      else if (w.nb[2 * i + 1] >= 0) { succ = w.nb[2 * i + 1]; succ_e = w.eid[2 * i + 1]; }
+      if (w.nb[2 * i] >= 0) ss = 2 * i;
+      else if (w.nb[2 * i + 1] >= 0) ss = 2 * i + 1;
     } else {
       for (int k = 0; k < 2; ++k) {
         if (w.nb[2 * i + k] >= 0 && w.endv[2 * i + k] == s0) {
           rank = w.dist[2 * i + k];
           pred = w.nb[2 * i + k];
           const int o = 1 - k;
-          if (w.nb[2 * i + o] >= 0) { succ = w.nb[2 * i + o]; succ_e = w.eid[2 * i + o]; }
+          if (w.nb[2 * i + o] >= 0) ss = 2 * i + o;
         }
       }
     }
-    const int32_t v = perm[st + i];
-    int orient;
-    int pe = -1;  // the entry pred -> i, read in pred's row
-    if (i == s0) {
-      orient = succ_e >= 0 ? (g.strand[succ_e] & 1) : 0;
-    } else if (pred >= 0) {
-      pe = w.nb[2 * pred] == i ? w.eid[2 * pred] : w.eid[2 * pred + 1];
-      orient = (g.strand[pe] >> 1) & 1;
-    } else {
-      orient = 0;  // unreachable for a chain: every read but the start has a predecessor
+    if (ss >= 0) {
+      succ = w.nb[ss];
+      succ_e = w.eid[ss];
     }
+    int ps = -1;  // slot of pred leading to i (its entry pred -> i)
+    if (i != s0 && pred >= 0) ps = w.nb[2 * pred] == i ? 2 * pred : 2 * pred + 1;
+    // strand bits, overlap or coordinates of the two entries, and the read
+    const int32_t v = kLds ? w.vid[i] : perm[st + i];
+    const uint32_t L = kLds ? w.rlen[i] : g.read_len[v];
+    const uint32_t ses = ss < 0 ? 0u : (kLds ? w.es[ss] : (uint32_t)g.strand[succ_e]);
+    const uint32_t pes = ps < 0 ? 0u : (kLds ? w.es[ps] : (uint32_t)g.strand[w.eid[ps]]);
+    int orient;
+    if (i == s0) orient = ss >= 0 ? (int)(ses & 1) : 0;
+    else if (ps >= 0) orient = (int)((pes >> 1) & 1);
+    else orient = 0;  // unreachable for a chain: every read but the start has a predecessor
     // the piece: walking offsets [skip, end] of the read (Section 4.4: from
     // post of the entering entry to pre of the leaving one, in stored
     // coordinates; from overlap lengths: the read minus its overlap with the
     // successor)
-    const uint32_t L = g.read_len[v];
     uint32_t skip = 0, plen = L;
     if (g.pre) {
-      const int64_t first = pe >= 0 ? (orient ? (int64_t)L - 1 - g.post[pe] : g.post[pe]) : 0;
-      const int64_t last = succ_e >= 0
-                               ? (orient ? (int64_t)L - 1 - g.pre[succ_e] : g.pre[succ_e])
-                               : (int64_t)L - 1;
+      const uint32_t post_in = ps < 0 ? 0u : (kLds ? w.ep[ps] : g.post[w.eid[ps]]);
+      const uint32_t pre_out = ss < 0 ? 0u : (kLds ? w.eo[ss] : g.pre[succ_e]);
+      const int64_t first = ps >= 0 ? (orient ? (int64_t)L - 1 - post_in : post_in) : 0;
+      const int64_t last =
+          ss >= 0 ? (orient ? (int64_t)L - 1 - pre_out : pre_out) : (int64_t)L - 1;
       skip = (uint32_t)first;
       plen = last >= first ? (uint32_t)(last - first + 1) : 0u;
-    } else if (succ_e >= 0) {
-      plen -= g.ovl[succ_e];
+    } else if (ss >= 0) {
+      plen -= kLds ? w.eo[ss] : g.ovl[succ_e];
     }
-    if (succ_e >= 0 && (int)(g.strand[succ_e] & 1) != orient) s_sej = 1;
+    if (ss >= 0 && (int)(ses & 1) != orient) s_sej = 1;
     R_vid[rank] = v;
     R_rev[rank] = (uint8_t)orient;
     R_len[rank] = plen;

@@ -20,7 +20,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
                                                          cg_contigs out, Scratch s,
                                                          int32_t *gbuf) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
-      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap];
+      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
+  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
+  __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int nc = *parts.d_n_comp;
   const int n = g.n;
@@ -28,7 +30,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
     const int q = parts.comp_size[c];
     const int st = parts.comp_start[c];
     if (q <= kWalkCap) {
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
+      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
       walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
                            local.loc_eid, out, s, nullptr, sh_scan);
     } else {

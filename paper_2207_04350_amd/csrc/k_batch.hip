@@ -89,6 +89,7 @@ struct BatchDev {
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
+  int2 *job_cnt;                    // [n_jobs] (components, component reads) of each job
   int32_t *comp_job;                // [sum n] job of each batch-wide component
   int32_t *chunk_job;               // [sum n / 64 + n_jobs] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
@@ -99,7 +100,8 @@ struct BatchDev {
   int32_t n_jobs, n_vtiles, n_mtiles;
 };
 
-// index j with base[j] <= i < base[j+1] (base ascending, base[0] = 0)
+// index j with base[j] <= i < base[j+1] (base ascending, base[0] = 0; of
+// several jobs with the same base, the last, which is the one holding i)
 __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jobs, int32_t i) {
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {
@@ -665,14 +667,17 @@ __global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
 
 // 4. LPT per job (one workgroup each), bin offsets, bucket cursors; the last
 // workgroup lays out the batch-wide component and piece item ranges
+// the batched form's LPT runs one job per workgroup of 256 threads, so that
+// all jobs' workgroups are resident at once
+constexpr int kBatchLptBlock = 256;
 constexpr int kBatchSortCap = 2048;
 constexpr int kBatchBinCap = 256;
 
-__global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
+__global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
   __shared__ uint64_t s_keys[kBatchSortCap];
   __shared__ int32_t s_bin[kBatchSortCap];
   __shared__ uint64_t s_binA[kBatchBinCap], s_binB[kBatchBinCap];
-  __shared__ int64_t sh[kLptBlock / kWave + 1];
+  __shared__ int64_t sh[kBatchLptBlock / kWave + 1];
   const int j = blockIdx.x;
   const BJob J = job_at(B.jobs, j);
   const int P = J.P;
@@ -680,33 +685,34 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   const uint64_t *wts = J.weight == CG_WEIGHT_BASES ? J.s.comp_w : nullptr;
   int m_e;
   if (nc <= kBatchSortCap && P <= kBatchBinCap)
-    m_e = lpt_body(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
+    m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
                    J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.s.bin_reads,
                    &B.fixed->status, J.parts.comp_kind, J.s.estart);
   else
-    m_e = lpt_body(nc, P, J.parts.comp_size, wts, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
+    m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
                    J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
                    J.s.bin_reads, &B.fixed->status, J.parts.comp_kind, J.s.estart);
   __syncthreads();
   // bin boundaries: prefix of the reads of each bin
   int64_t carry = 0;
-  for (int base = 0; base < P; base += kLptBlock) {
+  for (int base = 0; base < P; base += kBatchLptBlock) {
     const int b = base + threadIdx.x;
     const int64_t x = b < P ? (int64_t)__hip_atomic_load(J.s.bin_reads + b, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT)
                             : 0;
     int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t, kLptBlock>(x, sh, &tot);
+    const int64_t ex = block_excl_scan<int64_t, kBatchLptBlock>(x, sh, &tot);
     if (b < P) J.local.bin_vptr[b] = (int32_t)(carry + ex);
     carry += tot;
   }
-  for (int c = threadIdx.x; c < nc; c += kLptBlock) J.s.fill[c] = 0;
+  for (int c = threadIdx.x; c < nc; c += kBatchLptBlock) J.s.fill[c] = 0;
   __shared__ int last;
   if (threadIdx.x == 0) {
     J.local.bin_vptr[P] = (int32_t)carry;
     J.local.d_sizes[0] = (int32_t)carry;
     J.local.d_sizes[1] = m_e;
     J.local.loc_row_ptr[carry] = m_e;
+    B.job_cnt[j] = make_int2(nc, (int32_t)carry);  // dense, for the last workgroup
     __threadfence();
     last = atomicAdd(&B.counters[2], 1u) == (unsigned)B.n_jobs - 1;
   }
@@ -714,19 +720,20 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
   if (!last) return;
   __threadfence();
   int64_t cc = 0, pc = 0, hc = 0;
-  for (int base = 0; base < B.n_jobs; base += kLptBlock) {
+  for (int base = 0; base < B.n_jobs; base += kBatchLptBlock) {
     const int i = base + threadIdx.x;
     int64_t xc = 0, xp = 0;
     if (i < B.n_jobs) {
-      const BJob &K = B.jobs[i];
-      xc = __hip_atomic_load(K.parts.d_n_comp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      xp = __hip_atomic_load(K.local.bin_vptr + K.P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      xc = (int32_t)(uint32_t)w;
+      xp = (int32_t)(uint32_t)(w >> 32);
     }
     const int64_t xh = (xp + kWave - 1) / kWave;
     int64_t tc, tp, th;
-    const int64_t ec = block_excl_scan<int64_t, kLptBlock>(xc, sh, &tc);
-    const int64_t ep = block_excl_scan<int64_t, kLptBlock>(xp, sh, &tp);
-    const int64_t eh = block_excl_scan<int64_t, kLptBlock>(xh, sh, &th);
+    const int64_t ec = block_excl_scan<int64_t, kBatchLptBlock>(xc, sh, &tc);
+    const int64_t ep = block_excl_scan<int64_t, kBatchLptBlock>(xp, sh, &tp);
+    const int64_t eh = block_excl_scan<int64_t, kBatchLptBlock>(xh, sh, &th);
     if (i < B.n_jobs) {
       B.comp_base[i] = (int32_t)(cc + ec);
       B.piece_base[i] = (int32_t)(pc + ep);
@@ -743,30 +750,33 @@ __global__ __launch_bounds__(kLptBlock) void kb_lpt(BatchDev B) {
     B.counters[2] = 0;
     B.counters[3] += 1u;  // the next run's forest tag
   }
-  __syncthreads();
-  // the job of every batch-wide component and copy chunk, so that the
-  // persistent passes find it with one load
-  // (each wave loads the bounds of 64 jobs at once, then its lanes fill the
-  // entries of one job after the other)
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int j0 = (threadIdx.x / kWave) * kWave; j0 < B.n_jobs; j0 += kLptBlock) {
-    const int jl = j0 + lane;
-    int32_t c0 = 0, c1 = 0, h0 = 0, h1 = 0;
-    if (jl < B.n_jobs) {
-      c0 = B.comp_base[jl];
-      c1 = B.comp_base[jl + 1];
-      h0 = B.chunk_base[jl];
-      h1 = B.chunk_base[jl + 1];
-    }
-    const int cnt = B.n_jobs - j0 < kWave ? B.n_jobs - j0 : kWave;
-    for (int t = 0; t < cnt; ++t) {
-      const int32_t a0 = __shfl(c0, t), a1 = __shfl(c1, t);
-      const int32_t b0 = __shfl(h0, t), b1 = __shfl(h1, t);
-      for (int32_t i = a0 + lane; i < a1; i += kWave) B.comp_job[i] = j0 + t;
-      for (int32_t i = b0 + lane; i < b1; i += kWave) B.chunk_job[i] = j0 + t;
-    }
-  }
   __threadfence();
+}
+
+// 4b. the job of every batch-wide component and copy chunk, so that the
+// persistent passes find it with one load: one entry per thread, by binary
+// search in the bases (staged in LDS up to kTablesJobCap jobs)
+constexpr int kTablesBlock = 256;
+constexpr int kTablesJobCap = 4096;
+
+__global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
+  __shared__ int32_t s_cb[kTablesJobCap + 1], s_hb[kTablesJobCap + 1];
+  const int nj = B.n_jobs;
+  const bool in_lds = nj <= kTablesJobCap;
+  if (in_lds) {
+    for (int i = threadIdx.x; i <= nj; i += kTablesBlock) {
+      s_cb[i] = B.comp_base[i];
+      s_hb[i] = B.chunk_base[i];
+    }
+    __syncthreads();
+  }
+  const int32_t tc = B.comp_base[nj], th = B.chunk_base[nj];
+  const int32_t nmax = tc > th ? tc : th;
+  for (int32_t i = blockIdx.x * kTablesBlock + threadIdx.x; i < nmax;
+       i += gridDim.x * kTablesBlock) {
+    if (i < tc) B.comp_job[i] = job_of(in_lds ? s_cb : B.comp_base, nj, i);
+    if (i < th) B.chunk_job[i] = job_of(in_lds ? s_hb : B.chunk_base, nj, i);
+  }
 }
 
 // 5. each eligible read claims a slot in its component's block
@@ -788,20 +798,31 @@ __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
 // time (round r: k in [64r, 64r + 64)), each lane of the first wave loading
 // one candidate's read count, and packs those with lo < q <= hi into list in
 // increasing i.  Returns how many it packed; all threads see the list.
+// With desc given, the hits' descriptors come along in the same round of
+// loads: desc[t] = (job, component in the job, reads, first local number).
 __device__ __forceinline__ int gather_components(const BatchDev &B, int32_t total, int r, int lo,
-                                                 int hi, int32_t *list, int *s_cnt) {
+                                                 int hi, int32_t *list, int *s_cnt,
+                                                 int4 *desc = nullptr) {
   __syncthreads();  // the previous round's list is no longer read
   if (threadIdx.x < kWave) {
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x + ((int64_t)r * kWave + lane) * gridDim.x;
     bool hit = false;
+    int j = 0, c = 0, q = 0, st = 0;
     if (i < total) {
-      const int j = ld_const(B.comp_job, i);
-      const int q = B.jobs[j].parts.comp_size[i - ld_const(B.comp_base, j)];
+      j = ld_const(B.comp_job, i);
+      c = (int)(i - ld_const(B.comp_base, j));
+      const cg_parts &P = B.jobs[j].parts;
+      q = P.comp_size[c];
+      st = P.comp_start[c];
       hit = q > lo && q <= hi;
     }
     const uint64_t m = __ballot(hit);
-    if (hit) list[__popcll(m & ((1ull << lane) - 1ull))] = (int32_t)i;
+    const int at = __popcll(m & ((1ull << lane) - 1ull));
+    if (hit) {
+      list[at] = (int32_t)i;
+      if (desc) desc[at] = make_int4(j, c, q, st);
+    }
     if (lane == 0) *s_cnt = __popcll(m);
   }
   __syncthreads();
@@ -816,15 +837,16 @@ __device__ __forceinline__ int gather_rounds(int32_t total) {
 // 6. induced subgraph of each component: sorted local numbers and local CSR
 // rows (persistent over all components of the batch)
 template <int BLOCK, int CAP>
-__device__ __forceinline__ void induce_listed(const BatchDev &B, int32_t i, int32_t *a,
+__device__ __forceinline__ void induce_listed(const BatchDev &B, int4 d, int32_t *a,
                                               int32_t *sh_scan) {
-  const int j = ld_const(B.comp_job, i);
+  // d = (job, component, reads, first local number), uniform
+  const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
+  const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
   const BJob J = job_at(B.jobs, j);
-  const int c = i - ld_const(B.comp_base, j);
-  const int32_t *members = J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : J.parts.comp_start[c]);
-  induce_component<BLOCK, CAP>(J.parts.comp_size[c], J.parts.comp_start[c], J.s.estart[c],
-                               members, J.flags, J.g.row_ptr, J.g.col, J.local.perm, J.s.lidx,
-                               J.local.loc_row_ptr, J.local.loc_col, J.local.loc_eid, a, sh_scan);
+  const int32_t *members = J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : st);
+  induce_component<BLOCK, CAP>(q, st, J.s.estart[c], members, J.flags, J.g.row_ptr, J.g.col,
+                               J.local.perm, J.s.lidx, J.local.loc_row_ptr, J.local.loc_col,
+                               J.local.loc_eid, a, sh_scan);
 }
 
 // 6a. components of at most kIndSmallCap reads: one wave each
@@ -832,14 +854,13 @@ __global__ __launch_bounds__(kIndSmallBlock) void kb_induce_small(BatchDev B) {
   __shared__ int32_t a[kIndSmallCap];
   __shared__ int32_t sh_scan[kIndSmallBlock / kWave + 1];
   __shared__ int32_t list[kWave];
+  __shared__ int4 desc[kWave];
   __shared__ int cnt;
   const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, 0, kIndSmallCap, list, &cnt);
-    for (int t = 0; t < k; ++t)
-      induce_listed<kIndSmallBlock, kIndSmallCap>(B, __builtin_amdgcn_readfirstlane(list[t]), a,
-                                                  sh_scan);
+    const int k = gather_components(B, total, r, 0, kIndSmallCap, list, &cnt, desc);
+    for (int t = 0; t < k; ++t) induce_listed<kIndSmallBlock, kIndSmallCap>(B, desc[t], a, sh_scan);
   }
 }
 
@@ -848,13 +869,13 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t a[kIndLocalCap];
   __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
   __shared__ int32_t list[kWave];
+  __shared__ int4 desc[kWave];
   __shared__ int cnt;
   const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, kIndSmallCap, 0x7FFFFFFF, list, &cnt);
-    for (int t = 0; t < k; ++t)
-      induce_listed<kIndBlock, kIndLocalCap>(B, __builtin_amdgcn_readfirstlane(list[t]), a, sh_scan);
+    const int k = gather_components(B, total, r, kIndSmallCap, 0x7FFFFFFF, list, &cnt, desc);
+    for (int t = 0; t < k; ++t) induce_listed<kIndBlock, kIndLocalCap>(B, desc[t], a, sh_scan);
   }
 }
 
@@ -862,23 +883,27 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
 // 7a. components of at most kWalkSmallCap reads: one wave each
 __global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
-      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap];
+      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
+  __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
+  __shared__ uint8_t s_es[2 * kWalkSmallCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   __shared__ int32_t list[kWave];
+  __shared__ int4 desc[kWave];
   __shared__ int cnt;
   const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, 0, kWalkSmallCap, list, &cnt);
+    const int k = gather_components(B, total, r, 0, kWalkSmallCap, list, &cnt, desc);
     for (int t = 0; t < k; ++t) {
-      const int32_t i = __builtin_amdgcn_readfirstlane(list[t]);  // uniform: scalar job loads
-      const int j = ld_const(B.comp_job, i);
+      // (job, component, reads, first local number), uniform: scalar job loads
+      const int4 d = desc[t];
+      const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
+      const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
       const BJob J = job_at(B.jobs, j);
-      const int c = i - ld_const(B.comp_base, j);
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
+      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
       walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
-          c, J.parts.comp_size[c], J.parts.comp_start[c], w, J.g, J.parts, J.local.perm,
-          J.local.loc_row_ptr, J.local.loc_col, J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+          c, q, st, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr, J.local.loc_col,
+          J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
     }
   }
 }
@@ -886,23 +911,24 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
 // 7b. the larger components
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
-      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap];
+      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
+  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
+  __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   __shared__ int32_t list[kWave];
+  __shared__ int4 desc[kWave];
   __shared__ int cnt;
   const int32_t total = ld_const(B.comp_base, B.n_jobs);
   const int rounds = gather_rounds(total);
   for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, kWalkSmallCap, 0x7FFFFFFF, list, &cnt);
+    const int k = gather_components(B, total, r, kWalkSmallCap, 0x7FFFFFFF, list, &cnt, desc);
     for (int t = 0; t < k; ++t) {
-      const int32_t i = __builtin_amdgcn_readfirstlane(list[t]);  // uniform: scalar job loads
-      const int j = ld_const(B.comp_job, i);
+      const int4 d = desc[t];
+      const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
+      const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
       const BJob J = job_at(B.jobs, j);
-      const int c = i - ld_const(B.comp_base, j);
-      const int q = J.parts.comp_size[c];
-      const int st = J.parts.comp_start[c];
       if (q <= kWalkCap) {
-        WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv};
+        WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
         walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, J.g, J.parts, J.local.perm,
                                                    J.local.loc_row_ptr, J.local.loc_col,
                                                    J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
@@ -1079,6 +1105,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const size_t o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
+  const size_t o_jcnt = take(sizeof(int2) * (n_jobs > 0 ? n_jobs : 1));
   int64_t sum_n = 0, sum_chunks = 0;
   for (int i = 0; i < n_jobs; ++i) {
     sum_n += jobs[i].g.n;
@@ -1187,6 +1214,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.comp_base = (int32_t *)(b->mem + o_cbase);
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
+  d.job_cnt = (int2 *)(b->mem + o_jcnt);
   d.comp_job = (int32_t *)(b->mem + o_cjob);
   d.chunk_job = (int32_t *)(b->mem + o_hjob);
   d.counters = (unsigned int *)(b->mem + o_counters);
@@ -1225,7 +1253,8 @@ int cg_batch_run(cg_batch *b, void *stream) {
     else if (T == 512) CG_LAUNCH(ctx, kb_weight<512>, dim3(b->n_vtiles), dim3(512), st, B);
     else CG_LAUNCH(ctx, kb_weight<1024>, dim3(b->n_vtiles), dim3(1024), st, B);
   }
-  CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kLptBlock), st, B);
+  CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kBatchLptBlock), st, B);
+  CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
   if (b->any_single) {
     if (T == 256) launch_vertex_fill<256>(b, st);
     else if (T == 512) launch_vertex_fill<512>(b, st);

@@ -88,10 +88,10 @@ __global__ __launch_bounds__(kLptBlock) void k_part_lpt(int32_t P, const int32_t
   __shared__ uint64_t s_binA[kBinCapLds], s_binB[kBinCapLds];
   const int nc = *d_n_comp;
   if (nc <= kSortCapLds && P <= kBinCapLds)
-    lpt_body(nc, P, comp_size, weight, s_keys, s_bin, s_binA, s_binB, comp_bin, comp_rank,
+    lpt_body<kLptBlock>(nc, P, comp_size, weight, s_keys, s_bin, s_binA, s_binB, comp_bin, comp_rank,
              comp_start, bin_load, bin_reads, status);
   else
-    lpt_body(nc, P, comp_size, weight, g_keys, g_bin, g_bins, g_bins + P, comp_bin, comp_rank,
+    lpt_body<kLptBlock>(nc, P, comp_size, weight, g_keys, g_bin, g_bins, g_bins + P, comp_bin, comp_rank,
              comp_start, bin_load, bin_reads, status);
 }
 
