@@ -875,14 +875,26 @@ constexpr int kCopyUnroll = 2;  // groups per lane per step
 // One step of the copy: kCopyUnroll groups per lane (groups g, g + 64, ...),
 // their pieces' descriptors and store windows.
 struct CopyStage {
-  uint32_t win[kCopyUnroll][5];
+  uint32_t win[kCopyUnroll][5];  // word 4 only where the neighbouring lane lacks it (nb)
   uint32_t hlo[kCopyUnroll], hhi[kCopyUnroll];  // store words of the next piece's head
   CopyD d[kCopyUnroll];
   CopyE e[kCopyUnroll];
   uint32_t k[kCopyUnroll];
   int t[kCopyUnroll];
   bool ok[kCopyUnroll];
+  bool nb[kCopyUnroll];  // word 4 is word 0 of the next group's window, held by lane l + 1
+                         // (forward) or l - 1 (reverse)
 };
+
+// x of lane l - 1 in lane l, by a DPP wave shift (wave_shr:1); lane 0 keeps
+// its own x
+__device__ __forceinline__ uint32_t wave_prev_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x138, 0xF, 0xF, false);
+}
+// x of lane l + 1 in lane l (wave_shl:1); lane 63 keeps its own x
+__device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x130, 0xF, 0xF, false);
+}
 
 // Find the pieces of a step's groups and start its loads.
 __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G, uint32_t gstart,
@@ -930,6 +942,17 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     // the ends of the store, where the words outside it are never used
     const uint64_t sb = rev ? d.base - 16 * w : d.base + 16 * w;
     const int64_t sw = S.ok[u] ? (int64_t)sb >> 4 : 0;
+    // the neighbouring lane's group is the next one of the same piece: its
+    // window starts at word 4 of this one
+    // (both shifts by every lane, then the choice: a shift must never run
+    // with part of the wave switched off)
+    const uint32_t tk = (uint32_t)S.t[u] | (S.ok[u] ? 0x80000000u : 0u);
+    const uint32_t tprev = wave_prev_u32(tk), tnext = wave_next_u32(tk);
+    const uint32_t tnb = rev ? tprev : tnext;
+    const int tn = (int)(tnb & 0x7FFFFFFFu);
+    const bool okn = (tnb >> 31) != 0u;
+    const bool edge = rev ? lane == 0 : lane == kWave - 1;
+    S.nb[u] = false;
     if (sw >= 0 && sw + 5 <= (int64_t)nwords) {
       u32x4 a;
       __builtin_memcpy(&a, seq + sw, 16);
@@ -937,7 +960,8 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
       S.win[u][1] = a.y;
       S.win[u][2] = a.z;
       S.win[u][3] = a.w;
-      S.win[u][4] = seq[sw + 4];
+      S.nb[u] = S.ok[u] && okn && !edge && tn == S.t[u];
+      S.win[u][4] = S.nb[u] ? 0u : seq[sw + 4];
     } else {
 #pragma unroll
       for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
@@ -959,17 +983,21 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
                                           uint64_t nwords, CG_GLOBAL uint32_t *__restrict__ bases) {
 #pragma unroll
   for (int u = 0; u < kCopyUnroll; ++u) {
+    // word 4 from the neighbouring lane, while every lane is still active
+    const uint32_t up = wave_next_u32(S.win[u][0]), dn = wave_prev_u32(S.win[u][0]);
     if (!S.ok[u]) continue;
     const CopyD &d = S.d[u];
     const bool rev = d.info & 32u;
+    uint32_t win[5] = {S.win[u][0], S.win[u][1], S.win[u][2], S.win[u][3],
+                       S.nb[u] ? (rev ? dn : up) : S.win[u][4]};
     const uint32_t sh = 2u * (uint32_t)((rev ? d.base - 16 * (d.w0 + S.k[u])
                                             : d.base + 16 * (d.w0 + S.k[u])) & 15);
     const uint32_t nw = d.nw - S.k[u] < 4 ? d.nw - S.k[u] : 4;
     uint32_t out[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      out[i] = rev ? revcomp16(__builtin_amdgcn_alignbit(S.win[u][4 - i], S.win[u][3 - i], sh))
-                   : __builtin_amdgcn_alignbit(S.win[u][i + 1], S.win[u][i], sh);
+      out[i] = rev ? revcomp16(__builtin_amdgcn_alignbit(win[4 - i], win[3 - i], sh))
+                   : __builtin_amdgcn_alignbit(win[i + 1], win[i], sh);
     const int fs = (int)(d.info & 31u);
     if (S.k[u] + nw == d.nw && fs < 16) {
       // the piece's last word: its own fs bases, then the next piece(s) or
