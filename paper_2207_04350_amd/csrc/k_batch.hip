@@ -90,6 +90,13 @@ struct BatchDev {
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
   int2 *job_cnt;                    // [n_jobs] (components, component reads) of each job
+  // work queue of the per-component passes: every component of the batch as
+  // (job, component, reads, first local number), in decreasing read count
+  int4 *wq;                         // [upper bound on the batch's components]
+  int32_t *wq_hist;                 // [kWqBuckets] components per read count (capped)
+  int32_t *wq_cur;                  // [kWqBuckets] placement cursors
+  int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
+                                    // reads, 2: above kIndSmallCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
   int32_t *chunk_job;               // [sum n / 64 + n_jobs] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
@@ -670,6 +677,7 @@ __global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
 // the batched form's LPT runs one job per workgroup of 256 threads, so that
 // all jobs' workgroups are resident at once
 constexpr int kBatchLptBlock = 256;
+constexpr int kWqBuckets = 4096;  // read counts from kWqBuckets - 1 up share the top bucket
 constexpr int kBatchSortCap = 2048;
 constexpr int kBatchBinCap = 256;
 
@@ -750,6 +758,10 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
     B.counters[2] = 0;
     B.counters[3] += 1u;  // the next run's forest tag
   }
+  for (int b = threadIdx.x; b < kWqBuckets; b += kBatchLptBlock) {
+    B.wq_hist[b] = 0;
+    B.wq_cur[b] = 0;
+  }
   __threadfence();
 }
 
@@ -761,6 +773,8 @@ constexpr int kTablesJobCap = 4096;
 
 __global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
   __shared__ int32_t s_cb[kTablesJobCap + 1], s_hb[kTablesJobCap + 1];
+  __shared__ int32_t s_hist[kWqBuckets];
+  for (int b = threadIdx.x; b < kWqBuckets; b += kTablesBlock) s_hist[b] = 0;
   const int nj = B.n_jobs;
   const bool in_lds = nj <= kTablesJobCap;
   if (in_lds) {
@@ -768,14 +782,90 @@ __global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
       s_cb[i] = B.comp_base[i];
       s_hb[i] = B.chunk_base[i];
     }
-    __syncthreads();
   }
+  __syncthreads();
   const int32_t tc = B.comp_base[nj], th = B.chunk_base[nj];
   const int32_t nmax = tc > th ? tc : th;
   for (int32_t i = blockIdx.x * kTablesBlock + threadIdx.x; i < nmax;
        i += gridDim.x * kTablesBlock) {
-    if (i < tc) B.comp_job[i] = job_of(in_lds ? s_cb : B.comp_base, nj, i);
+    if (i < tc) {
+      const int j = job_of(in_lds ? s_cb : B.comp_base, nj, i);
+      B.comp_job[i] = j;
+      // the work queue's histogram: components per read count
+      const int32_t q = B.jobs[j].parts.comp_size[i - (in_lds ? s_cb[j] : B.comp_base[j])];
+      atomicAdd(s_hist + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
+    }
     if (i < th) B.chunk_job[i] = job_of(in_lds ? s_hb : B.chunk_base, nj, i);
+  }
+  // (counted in LDS: many components share a read count, and their global
+  // atomics would queue on one address)
+  __syncthreads();
+  for (int b = threadIdx.x; b < kWqBuckets; b += kTablesBlock)
+    if (s_hist[b]) atomicAdd(B.wq_hist + b, s_hist[b]);
+}
+
+// 4c. the work queue: every component of the batch in decreasing read count
+// (within a bucket in any order), as (job, component, reads, first local
+// number), and the queue heads of the four per-component passes.  Handing
+// the largest components out first to whichever workgroup is free is LPT
+// list scheduling of the whole batch's components onto the workgroups.
+// Components of at most kWalkSmallCap (kIndSmallCap) reads form the queue's
+// tail, which the one-wave passes take.
+constexpr int kWqBlock = 256;
+constexpr int kWqPer = kWqBuckets / kWqBlock;
+
+__global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
+  __shared__ int32_t s_start[kWqBuckets], s_cnt[kWqBuckets], s_base[kWqBuckets];
+  __shared__ int32_t sh[kWqBlock / kWave + 1];
+  // start of each bucket: the components in larger buckets (a scan from the
+  // top bucket down; thread t holds buckets kWqBuckets-1-t*kWqPer ... down)
+  int32_t h[kWqPer], loc = 0;
+#pragma unroll
+  for (int k = 0; k < kWqPer; ++k) {
+    h[k] = __hip_atomic_load(B.wq_hist + (kWqBuckets - 1 - (threadIdx.x * kWqPer + k)),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    loc += h[k];
+  }
+  int32_t tot;
+  int32_t run = block_excl_scan<int32_t, kWqBlock>(loc, sh, &tot);
+#pragma unroll
+  for (int k = 0; k < kWqPer; ++k) {
+    s_start[kWqBuckets - 1 - (threadIdx.x * kWqPer + k)] = run;
+    run += h[k];
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    B.wq_meta[0] = tot;
+    B.wq_meta[1] = s_start[kWalkSmallCap];  // components above kWalkSmallCap reads
+    B.wq_meta[2] = s_start[kIndSmallCap];   // above kIndSmallCap
+  }
+  // this workgroup's components: a contiguous range; counted per bucket in
+  // LDS, one reservation per bucket in the queue, placed by LDS cursors
+  const int32_t tc = B.comp_base[B.n_jobs];
+  const int32_t per = (tc + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+  const int32_t i0 = (int32_t)blockIdx.x * per;
+  const int32_t i1 = i0 + per < tc ? i0 + per : tc;
+  for (int b = threadIdx.x; b < kWqBuckets; b += kWqBlock) s_cnt[b] = 0;
+  __syncthreads();
+  for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
+    const int j = B.comp_job[i];
+    const int32_t q = B.jobs[j].parts.comp_size[i - B.comp_base[j]];
+    atomicAdd(s_cnt + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kWqBuckets; b += kWqBlock) {
+    const int32_t k = s_cnt[b];
+    s_base[b] = k ? s_start[b] + atomicAdd(B.wq_cur + b, k) : 0;
+    s_cnt[b] = 0;
+  }
+  __syncthreads();
+  for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
+    const int j = B.comp_job[i];
+    const int32_t c = i - B.comp_base[j];
+    const cg_parts &P = B.jobs[j].parts;
+    const int32_t q = P.comp_size[c], st = P.comp_start[c];
+    const int b = q < kWqBuckets - 1 ? q : kWqBuckets - 1;
+    B.wq[s_base[b] + atomicAdd(s_cnt + b, 1)] = make_int4(j, c, q, st);
   }
 }
 
@@ -793,49 +883,27 @@ __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   J.s.tmp[J.parts.comp_start[c] + slot] = (int32_t)v;
 }
 
-// The batch-wide components a block of a persistent pass owns are
-// i = blockIdx.x + k * gridDim.x.  gather_components looks at 64 of them at a
-// time (round r: k in [64r, 64r + 64)), each lane of the first wave loading
-// one candidate's read count, and packs those with lo < q <= hi into list in
-// increasing i.  Returns how many it packed; all threads see the list.
-// With desc given, the hits' descriptors come along in the same round of
-// loads: desc[t] = (job, component in the job, reads, first local number).
-__device__ __forceinline__ int gather_components(const BatchDev &B, int32_t total, int r, int lo,
-                                                 int hi, int32_t *list, int *s_cnt,
-                                                 int4 *desc = nullptr) {
-  __syncthreads();  // the previous round's list is no longer read
-  if (threadIdx.x < kWave) {
-    const int lane = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x + ((int64_t)r * kWave + lane) * gridDim.x;
-    bool hit = false;
-    int j = 0, c = 0, q = 0, st = 0;
-    if (i < total) {
-      j = ld_const(B.comp_job, i);
-      c = (int)(i - ld_const(B.comp_base, j));
-      const cg_parts &P = B.jobs[j].parts;
-      q = P.comp_size[c];
-      st = P.comp_start[c];
-      hit = q > lo && q <= hi;
-    }
-    const uint64_t m = __ballot(hit);
-    const int at = __popcll(m & ((1ull << lane) - 1ull));
-    if (hit) {
-      list[at] = (int32_t)i;
-      if (desc) desc[at] = make_int4(j, c, q, st);
-    }
-    if (lane == 0) *s_cnt = __popcll(m);
-  }
-  __syncthreads();
-  return *s_cnt;
+// The per-component passes take their part of the work queue [lo, hi) in a
+// snake order over the grid: round r gives workgroup w entry r*W + w, or
+// r*W + W-1-w on odd rounds.  The queue is in decreasing read count, so this
+// deals the components out like LPT list scheduling, with no atomics.
+// Returns the entry of round r, or -1 past the end.
+__device__ __forceinline__ int32_t wq_entry(int32_t lo, int32_t hi, int32_t r) {
+  const int32_t W = (int32_t)gridDim.x, w = (int32_t)blockIdx.x;
+  const int64_t x = (int64_t)lo + (int64_t)r * W + ((r & 1) ? W - 1 - w : w);
+  return x < hi ? (int32_t)x : -1;
 }
 
-__device__ __forceinline__ int gather_rounds(int32_t total) {
-  const int64_t per = (int64_t)kWave * gridDim.x;
-  return (int)(((int64_t)total - blockIdx.x + per - 1) / per);
+// entry x (uniform): (job, component, reads, first local number)
+__device__ __forceinline__ int4 wq_at(const BatchDev &B, int32_t x) {
+  const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(B.wq + x);
+  const uint64_t a = p[0], b = p[1];
+  return make_int4((int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)(uint32_t)b,
+                   (int)(uint32_t)(b >> 32));
 }
 
 // 6. induced subgraph of each component: sorted local numbers and local CSR
-// rows (persistent over all components of the batch)
+// rows
 template <int BLOCK, int CAP>
 __device__ __forceinline__ void induce_listed(const BatchDev &B, int4 d, int32_t *a,
                                               int32_t *sh_scan) {
@@ -849,99 +917,69 @@ __device__ __forceinline__ void induce_listed(const BatchDev &B, int4 d, int32_t
                                J.local.loc_eid, a, sh_scan);
 }
 
-// 6a. components of at most kIndSmallCap reads: one wave each
+// 6a. components of at most kIndSmallCap reads (the queue's tail): one wave each
 __global__ __launch_bounds__(kIndSmallBlock) void kb_induce_small(BatchDev B) {
   __shared__ int32_t a[kIndSmallCap];
   __shared__ int32_t sh_scan[kIndSmallBlock / kWave + 1];
-  __shared__ int32_t list[kWave];
-  __shared__ int4 desc[kWave];
-  __shared__ int cnt;
-  const int32_t total = ld_const(B.comp_base, B.n_jobs);
-  const int rounds = gather_rounds(total);
-  for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, 0, kIndSmallCap, list, &cnt, desc);
-    for (int t = 0; t < k; ++t) induce_listed<kIndSmallBlock, kIndSmallCap>(B, desc[t], a, sh_scan);
-  }
+  const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 0);
+  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r)
+    induce_listed<kIndSmallBlock, kIndSmallCap>(B, wq_at(B, x), a, sh_scan);
 }
 
-// 6b. the larger components
+// 6b. the larger components (the queue's head, largest first)
 __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t a[kIndLocalCap];
   __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
-  __shared__ int32_t list[kWave];
-  __shared__ int4 desc[kWave];
-  __shared__ int cnt;
-  const int32_t total = ld_const(B.comp_base, B.n_jobs);
-  const int rounds = gather_rounds(total);
-  for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, kIndSmallCap, 0x7FFFFFFF, list, &cnt, desc);
-    for (int t = 0; t < k; ++t) induce_listed<kIndBlock, kIndLocalCap>(B, desc[t], a, sh_scan);
-  }
+  const int32_t hi = ld_const(B.wq_meta, 2);
+  for (int32_t r = 0, x; (x = wq_entry(0, hi, r)) >= 0; ++r)
+    induce_listed<kIndBlock, kIndLocalCap>(B, wq_at(B, x), a, sh_scan);
 }
 
-// 7. walk every component (persistent grids over all components)
-// 7a. components of at most kWalkSmallCap reads: one wave each
+// 7. walk every component
+// 7a. components of at most kWalkSmallCap reads (the queue's tail): one wave each
 __global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
       s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
   __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
   __shared__ uint8_t s_es[2 * kWalkSmallCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
-  __shared__ int32_t list[kWave];
-  __shared__ int4 desc[kWave];
-  __shared__ int cnt;
-  const int32_t total = ld_const(B.comp_base, B.n_jobs);
-  const int rounds = gather_rounds(total);
-  for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, 0, kWalkSmallCap, list, &cnt, desc);
-    for (int t = 0; t < k; ++t) {
-      // (job, component, reads, first local number), uniform: scalar job loads
-      const int4 d = desc[t];
-      const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
-      const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
-      const BJob J = job_at(B.jobs, j);
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
-      walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
-          c, q, st, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr, J.local.loc_col,
-          J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-    }
+  const int32_t lo = ld_const(B.wq_meta, 1), hi = ld_const(B.wq_meta, 0);
+  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
+    const int4 d = wq_at(B, x);
+    const BJob J = job_at(B.jobs, d.x);
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
+        d.y, d.z, d.w, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr, J.local.loc_col,
+        J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
   }
 }
 
-// 7b. the larger components
+// 7b. the larger components (the queue's head, largest first)
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
   __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
   __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
-  __shared__ int32_t list[kWave];
-  __shared__ int4 desc[kWave];
-  __shared__ int cnt;
-  const int32_t total = ld_const(B.comp_base, B.n_jobs);
-  const int rounds = gather_rounds(total);
-  for (int r = 0; r < rounds; ++r) {
-    const int k = gather_components(B, total, r, kWalkSmallCap, 0x7FFFFFFF, list, &cnt, desc);
-    for (int t = 0; t < k; ++t) {
-      const int4 d = desc[t];
-      const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
-      const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
-      const BJob J = job_at(B.jobs, j);
-      if (q <= kWalkCap) {
-        WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
-        walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, J.g, J.parts, J.local.perm,
-                                                   J.local.loc_row_ptr, J.local.loc_col,
-                                                   J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-      } else {
-        const int64_t n = J.g.n;
-        int32_t *gb = J.s.walk;
-        WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st,
-                     gb + 4 * n + 4 * (int64_t)st, gb + 8 * n + 4 * (int64_t)st,
-                     gb + 12 * n + 4 * (int64_t)st};
-        walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, J.g, J.parts, J.local.perm,
-                                                    J.local.loc_row_ptr, J.local.loc_col,
-                                                    J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-      }
+  const int32_t hi = ld_const(B.wq_meta, 1);
+  for (int32_t r = 0, x; (x = wq_entry(0, hi, r)) >= 0; ++r) {
+    const int4 d = wq_at(B, x);
+    const int c = d.y, q = d.z, st = d.w;
+    const BJob J = job_at(B.jobs, d.x);
+    if (q <= kWalkCap) {
+      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+      walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, J.g, J.parts, J.local.perm,
+                                                 J.local.loc_row_ptr, J.local.loc_col,
+                                                 J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
+    } else {
+      const int64_t n = J.g.n;
+      int32_t *gb = J.s.walk;
+      WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st,
+                   gb + 4 * n + 4 * (int64_t)st, gb + 8 * n + 4 * (int64_t)st,
+                   gb + 12 * n + 4 * (int64_t)st};
+      walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, J.g, J.parts, J.local.perm,
+                                                  J.local.loc_row_ptr, J.local.loc_col,
+                                                  J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
     }
   }
 }
@@ -1112,6 +1150,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     sum_chunks += (jobs[i].g.n + kWave - 1) / kWave;
   }
   const size_t o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
+  const size_t o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
+  const size_t o_wqh = take(sizeof(int32_t) * kWqBuckets);
+  const size_t o_wqc = take(sizeof(int32_t) * kWqBuckets);
+  const size_t o_wqm = take(sizeof(int32_t) * 8);
   const size_t o_hjob = take(sizeof(int32_t) * (size_t)(sum_chunks > 0 ? sum_chunks : 1));
   const size_t o_counters = take(sizeof(unsigned int) * 8);
   const size_t o_order = take(sizeof(int32_t) * n_jobs);
@@ -1215,6 +1257,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
   d.job_cnt = (int2 *)(b->mem + o_jcnt);
+  d.wq = (int4 *)(b->mem + o_wq);
+  d.wq_hist = (int32_t *)(b->mem + o_wqh);
+  d.wq_cur = (int32_t *)(b->mem + o_wqc);
+  d.wq_meta = (int32_t *)(b->mem + o_wqm);
   d.comp_job = (int32_t *)(b->mem + o_cjob);
   d.chunk_job = (int32_t *)(b->mem + o_hjob);
   d.counters = (unsigned int *)(b->mem + o_counters);
@@ -1255,6 +1301,7 @@ int cg_batch_run(cg_batch *b, void *stream) {
   }
   CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kBatchLptBlock), st, B);
   CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
+  CG_LAUNCH(ctx, kb_wq_place, dim3(128), dim3(kWqBlock), st, B);
   if (b->any_single) {
     if (T == 256) launch_vertex_fill<256>(b, st);
     else if (T == 512) launch_vertex_fill<512>(b, st);
