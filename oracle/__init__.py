@@ -39,7 +39,7 @@ def _lib():
     if _LIB is None:
         _LIB = ctypes.CDLL(build())
         for name in ("cgo_validate", "cgo_mask", "cgo_components", "cgo_table", "cgo_lpt",
-                     "cgo_order", "cgo_induce", "cgo_assemble"):
+                     "cgo_order", "cgo_induce", "cgo_assemble", "cgo_reduce"):
             getattr(_LIB, name).argtypes = None
         _LIB.cgo_validate.restype = ctypes.c_int64
         _LIB.cgo_table.restype = ctypes.c_int32
@@ -49,6 +49,7 @@ def _lib():
         _LIB.cgo_lpt.restype = None
         _LIB.cgo_order.restype = None
         _LIB.cgo_induce.restype = None
+        _LIB.cgo_reduce.restype = ctypes.c_int64
     return _LIB
 
 
@@ -246,3 +247,29 @@ def contig_codes(contigs, k):
     off = int(contigs["base_off"][k])
     idx = off + np.arange(L, dtype=np.int64)
     return ((contigs["bases"][idx >> 4] >> (2 * (idx & 15)).astype(np.uint32)) & 3).astype(np.uint8)
+
+
+def reduce(r, fuzz=0):
+    """Prune(IsContainedRead) and TransitiveReduction (Algorithm 1; Section 2)
+    of an overlap graph r (fields as a string graph's).  Returns (contained
+    u8[n], kept u8[m], the reduced graph as a copy of r with its CSR arrays
+    replaced)."""
+    import dataclasses
+    n = r.n
+    m = int(r.row_ptr[n]) if n else 0
+    row_ptr, col = _c(r.row_ptr, np.int32), _c(r.col, np.int32)
+    ovl, strand = _c(r.ovl, np.uint32), _c(r.strand, np.uint8)
+    read_len = _c(r.read_len, np.uint32)
+    contained = np.zeros(max(n, 1), np.uint8)
+    kept = np.zeros(max(m, 1), np.uint8)
+    s_row_ptr = np.zeros(n + 1, np.int32)
+    s_col = np.zeros(max(m, 1), np.int32)
+    s_ovl = np.zeros(max(m, 1), np.uint32)
+    s_strand = np.zeros(max(m, 1), np.uint8)
+    ms = _lib().cgo_reduce(_i32(n), _p(row_ptr), _p(col), _p(ovl), _p(strand), _p(read_len),
+                           ctypes.c_uint32(int(fuzz)), _p(contained), _p(kept), _p(s_row_ptr),
+                           _p(s_col), _p(s_ovl), _p(s_strand))
+    s = dataclasses.replace(r, m=int(ms), row_ptr=s_row_ptr, col=s_col[:ms].copy(),
+                            ovl=s_ovl[:ms].copy(), strand=s_strand[:ms].copy(), pre=None,
+                            post=None)
+    return contained[:n], kept[:m], s

@@ -482,3 +482,72 @@ int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, cons
     free(by_rank);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Before the path: Prune(IsContainedRead) and TransitiveReduction           */
+/* (Algorithm 1; Section 2: redundant vertices and redundant edges)          */
+/* ------------------------------------------------------------------------ */
+
+int64_t cgo_reduce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *ovl,
+                   const uint8_t *strand, const uint32_t *read_len, uint32_t fuzz,
+                   uint8_t *contained, uint8_t *kept, int32_t *s_row_ptr, int32_t *s_col,
+                   uint32_t *s_ovl, uint8_t *s_strand)
+{
+    const int64_t m = row_ptr[n];
+    /* redundant vertices: a read whose every base lies in an overlap with a
+     * longer read (of equal reads, all but the smallest id) */
+    for (int32_t v = 0; v < n; ++v) {
+        contained[v] = 0;
+        for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+            const int32_t u = col[j];
+            if (ovl[j] >= read_len[v] &&
+                (read_len[u] > read_len[v] || (read_len[u] == read_len[v] && u < v)))
+                contained[v] = 1;
+        }
+    }
+    /* redundant edges: entries with a parallel two-edge walk of the same
+     * overhang */
+    uint8_t *trans = (uint8_t *)calloc((size_t)(m > 0 ? m : 1), 1);
+    for (int32_t u = 0; u < n; ++u) {
+        if (contained[u]) continue;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t w = col[e];
+            if (contained[w]) continue;
+            const int64_t sfx_uw = (int64_t)read_len[w] - ovl[e];
+            for (int64_t f = row_ptr[u]; f < row_ptr[u + 1] && !trans[e]; ++f) {
+                const int32_t v = col[f];
+                if (v == w || contained[v]) continue;
+                const int64_t g = find_entry(row_ptr, col, v, w);
+                if (g < 0) continue;
+                const int s_uv = strand[f] & 1, d_uv = (strand[f] >> 1) & 1;
+                const int s_vw = strand[g] & 1, d_vw = (strand[g] >> 1) & 1;
+                const int s_uw = strand[e] & 1, d_uw = (strand[e] >> 1) & 1;
+                if (s_uv != s_uw || d_uv != s_vw || d_vw != d_uw) continue;
+                const int64_t sum = ((int64_t)read_len[v] - ovl[f]) + ((int64_t)read_len[w] - ovl[g]);
+                const int64_t diff = sum > sfx_uw ? sum - sfx_uw : sfx_uw - sum;
+                if (diff <= (int64_t)fuzz) trans[e] = 1;
+            }
+        }
+    }
+    /* S: the pairs with neither entry transitive and no contained read */
+    int64_t at = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        s_row_ptr[u] = (int32_t)at;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const int32_t w = col[e];
+            const int64_t twin = find_entry(row_ptr, col, w, u);
+            const int keep = !contained[u] && !contained[w] && !trans[e] &&
+                             !(twin >= 0 && trans[twin]);
+            kept[e] = (uint8_t)keep;
+            if (keep) {
+                s_col[at] = w;
+                s_ovl[at] = ovl[e];
+                s_strand[at] = strand[e];
+                ++at;
+            }
+        }
+    }
+    s_row_ptr[n] = (int32_t)at;
+    free(trans);
+    return at;
+}

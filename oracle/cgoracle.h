@@ -104,6 +104,30 @@ int32_t cgo_assemble(int32_t n, const int32_t *row_ptr, const int32_t *col, cons
                      uint8_t *layout_rev, uint32_t *bases, uint64_t cap_words,
                      uint64_t *total_words);
 
+/* The step before the path (Algorithm 1: Prune(IsContainedRead), then
+ * TransitiveReduction; Section 2's string-graph definitions), on an overlap
+ * graph R given like S (symmetric CSR, overlap length and strand bits per
+ * entry):
+ *   contained[v] = 1 when some entry u->v covers all of v (ovl >= len(v))
+ *                  and u is longer than v, or as long with a smaller id
+ *                  (reading: of identical reads the smallest id stays);
+ *   an entry u->w between reads that are not contained is transitive when a
+ *   third read v, not contained, has entries u->v and v->w that make a valid
+ *   walk u, v, w with the same end orientations as u->w (s(u->v) = s(u->w),
+ *   d(u->v) = s(v->w), d(v->w) = d(u->w)) and whose overhangs add up to that
+ *   of u->w within fuzz: |sfx(u->v) + sfx(v->w) - sfx(u->w)| <= fuzz, with
+ *   sfx(x->y) = len(y) - ovl(x->y) (reading: a parallel path of two edges
+ *   carrying the same information);
+ *   the pair {u, w} leaves S when either of its entries is transitive or
+ *   either read is contained.
+ * kept[e] = 1 for the entries of R that stay; S keeps R's column order
+ * (s_row_ptr[n+1], s_col / s_ovl / s_strand of up to row_ptr[n] entries).
+ * Returns the number of entries of S. */
+int64_t cgo_reduce(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *ovl,
+                   const uint8_t *strand, const uint32_t *read_len, uint32_t fuzz,
+                   uint8_t *contained, uint8_t *kept, int32_t *s_row_ptr, int32_t *s_col,
+                   uint32_t *s_ovl, uint8_t *s_strand);
+
 #ifdef __cplusplus
 }
 #endif

@@ -314,6 +314,64 @@ def simulate(G, cov, mean_len, sd_len, err, extra_rate, seed, repeats=None, P=64
     return g
 
 
+def overlap_graph(g: StringGraph, min_overlap: int = MIN_OVERLAP) -> StringGraph:
+    """The overlap graph g was reduced from (the input of Algorithm 1's
+    pruning and transitive reduction): every pair of reads whose true
+    intervals overlap by at least min_overlap bases, contained reads
+    included, plus g's extra edges with g's values (an extra edge replaces a
+    true overlap of the same pair).  A true pair's entry from the read that
+    comes first in (start asc, end desc, id asc) order carries (its
+    orientation, the other's), as g's edges do.  Same reads and ids as g."""
+    import dataclasses
+    n = g.n
+    a = np.asarray(g.truth["start"], dtype=np.int64)
+    b = np.asarray(g.truth["end"], dtype=np.int64)
+    rc = np.asarray(g.truth["rc"], dtype=np.int64)
+    order = np.lexsort((np.arange(n), -b, a))
+    A, Bv = a[order], b[order]
+    us, vs, ovs = [], [], []
+    k = 1
+    while k < n:
+        i = np.arange(n - k)
+        j = i + k
+        cand = A[j] + min_overlap <= Bv[i]   # starts are sorted: none further once this fails
+        if not cand.any():
+            break
+        ov = np.minimum(Bv[i], Bv[j]) - A[j]
+        ok = cand & (ov >= min_overlap)
+        us.append(order[i[ok]])
+        vs.append(order[j[ok]])
+        ovs.append(ov[ok])
+        k += 1
+    u = np.concatenate(us) if us else np.zeros(0, np.int64)
+    v = np.concatenate(vs) if vs else np.zeros(0, np.int64)
+    o = np.concatenate(ovs) if ovs else np.zeros(0, np.int64)
+    s_, d_ = rc[u], rc[v]
+    extra = np.asarray(g.truth.get("extra_edges", np.zeros((0, 2))), dtype=np.int64).reshape(-1, 2)
+    if len(extra):
+        key = lambda x, y: np.minimum(x, y) * n + np.maximum(x, y)
+        drop = np.isin(key(u, v), key(extra[:, 0], extra[:, 1]))
+        u, v, o, s_, d_ = u[~drop], v[~drop], o[~drop], s_[~drop], d_[~drop]
+        eu, ev, eo, es, ed = [], [], [], [], []
+        for x, y in extra.tolist():
+            lo, hi = int(g.row_ptr[x]), int(g.row_ptr[x + 1])
+            jj = lo + int(np.searchsorted(g.col[lo:hi], y))
+            eu.append(x)
+            ev.append(y)
+            eo.append(int(g.ovl[jj]))
+            es.append(int(g.strand[jj]) & 1)
+            ed.append((int(g.strand[jj]) >> 1) & 1)
+        u = np.concatenate([u, eu])
+        v = np.concatenate([v, ev])
+        o = np.concatenate([o, eo])
+        s_ = np.concatenate([s_, es])
+        d_ = np.concatenate([d_, ed])
+    row_ptr, col, ovl, strand = csr_from_edges(n, u, v, o, s_, d_)
+    meta = dict(g.meta, overlap_graph=True, min_overlap=int(min_overlap))
+    return dataclasses.replace(g, m=int(col.shape[0]), row_ptr=row_ptr, col=col, ovl=ovl,
+                               strand=strand, meta=meta, pre=None, post=None)
+
+
 def _substitute(rng, seq, off, ln, err):
     """Uniform substitution errors in the packed store, in place."""
     total = int(ln.sum())
