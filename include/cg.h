@@ -230,6 +230,31 @@ int cg_ctx_profile(cg_ctx *ctx, int32_t max_launches);
 int cg_ctx_profile_read(cg_ctx *ctx, int32_t cap, const char **names, int64_t *launches,
                         double *ms, int32_t *n_kernels, int64_t *dropped);
 
+/* ---- before the path: an overlap graph reduced to a string graph ------- */
+
+/* Prune(IsContainedRead) and TransitiveReduction (Algorithm 1; Section 2
+ * defines redundant vertices and redundant edges) of an overlap graph r,
+ * given like a string graph (symmetric CSR with overlap lengths and strand
+ * bits, and read lengths; sequences and pre/post are not read):
+ *   contained[v] = 1 when an entry u->v covers all of v (ovl >= len(v)) and
+ *   u is longer than v, or as long with a smaller id;
+ *   an entry u->w between reads that are not contained is transitive when a
+ *   third read v, not contained, gives a valid walk u, v, w with u->w's end
+ *   orientations (s(u->v) = s(u->w), d(u->v) = s(v->w), d(v->w) = d(u->w))
+ *   whose overhangs sfx(x->y) = len(y) - ovl(x->y) add up to u->w's within
+ *   `fuzz` bases;
+ *   a pair leaves the string graph when either of its entries is transitive
+ *   or either read is contained.
+ * Outputs [device, caller-owned]: contained u8[n]; kept u8[r->m], 1 for the
+ * entries of r that stay; the string graph as s_row_ptr i32[n+1], s_col
+ * i32[r->m], s_ovl u32[r->m], s_strand u8[r->m] (r's column order within a
+ * row; contained reads keep their ids with empty rows); d_m i32[1] its entry
+ * count.  Needs a context sized for (r->n, r->m, 1).  Errors: CG_EINVAL for
+ * NULL arguments or a malformed frame, CG_ENOMEM for a small context. */
+int cg_reduce(cg_ctx *ctx, const cg_graph *r, uint32_t fuzz, uint8_t *contained, uint8_t *kept,
+              int32_t *s_row_ptr, int32_t *s_col, uint32_t *s_ovl, uint8_t *s_strand,
+              int32_t *d_m, void *stream);
+
 /* Thread-local text of the last error. */
 const char *cg_last_error(void);
 

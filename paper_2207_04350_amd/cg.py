@@ -93,6 +93,8 @@ def lib():
         L.cg_ctx_profile_read.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_char_p),
                                           P(ctypes.c_int64), P(ctypes.c_double),
                                           P(ctypes.c_int32), P(ctypes.c_int64)]
+        L.cg_reduce.argtypes = [_vp, P(CgGraph), ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp]
         L.cg_batch_create.argtypes = [_vp, ctypes.c_int32, P(CgJob), P(CgBatchParams), P(_vp)]
         L.cg_batch_run.argtypes = [_vp, _vp]
         L.cg_batch_capture.argtypes = [_vp, _vp]
@@ -102,7 +104,7 @@ def lib():
                      "cg_batch_destroy", "cg_ctx_profile", "cg_ctx_profile_read",
                      "cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
                      "cg_validate", "cg_mask_branches", "cg_components", "cg_partition",
-                     "cg_induce", "cg_assemble"):
+                     "cg_induce", "cg_assemble", "cg_reduce"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -298,6 +300,36 @@ def mask_branches(ctx, dg, flags, d_counts, stream=None):
 def components(ctx, dg, flags, label, stream=None):
     _check(lib().cg_components(ctx.handle, ctypes.byref(dg.struct), _ptr(flags), _ptr(label),
                                _stream(stream)))
+
+
+class Reduced:
+    """Outputs of cg_reduce for an overlap graph of n reads and m entries."""
+
+    def __init__(self, n, m, device="cuda"):
+        import torch
+        e = lambda size, dt: torch.empty(max(int(size), 1), dtype=dt, device=device)
+        self.n, self.m_cap = int(n), int(m)
+        self.contained = e(n, torch.uint8)
+        self.kept = e(m, torch.uint8)
+        self.row_ptr = torch.empty(int(n) + 1, dtype=torch.int32, device=device)
+        self.col, self.ovl, self.strand = e(m, torch.int32), e(m, torch.int32), e(m, torch.uint8)
+        self.d_m = e(1, torch.int32)
+
+    def graph(self, r_dg):
+        """The string graph as a resident graph (reads of r_dg); reads the
+        device entry count."""
+        m = int(self.d_m.item())
+        t = dict(row_ptr=self.row_ptr, col=self.col, ovl=self.ovl, strand=self.strand,
+                 read_len=r_dg.read_len, read_off=r_dg.read_off, seq=r_dg.seq)
+        return DeviceGraph.from_tensors(self.n, m, t, r_dg.seq_words, r_dg.device)
+
+
+def reduce(ctx, r_dg, out, fuzz=0, stream=None):
+    """cg_reduce: contained-read pruning and transitive reduction of the
+    overlap graph r_dg into `out` (a Reduced)."""
+    _check(lib().cg_reduce(ctx.handle, ctypes.byref(r_dg.struct), ctypes.c_uint32(int(fuzz)),
+                           _ptr(out.contained), _ptr(out.kept), _ptr(out.row_ptr), _ptr(out.col),
+                           _ptr(out.ovl), _ptr(out.strand), _ptr(out.d_m), _stream(stream)))
 
 
 WEIGHT_READS, WEIGHT_BASES = 0, 1

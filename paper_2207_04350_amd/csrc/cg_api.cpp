@@ -270,6 +270,20 @@ int cg_validate(cg_ctx *ctx, const cg_graph *g, int64_t *d_bad, void *stream) {
   return launch_validate(ctx, *g, d_bad, (hipStream_t)stream);
 }
 
+int cg_reduce(cg_ctx *ctx, const cg_graph *r, uint32_t fuzz, uint8_t *contained, uint8_t *kept,
+              int32_t *s_row_ptr, int32_t *s_col, uint32_t *s_ovl, uint8_t *s_strand,
+              int32_t *d_m, void *stream) {
+  int rc = check_graph(r, false);
+  if (rc) return rc;
+  if (!s_row_ptr || !d_m || (r->n > 0 && (!contained || !r->read_len)) ||
+      (r->m > 0 && (!kept || !s_col || !s_ovl || !s_strand)))
+    return set_error(CG_EINVAL, "NULL argument");
+  Scratch s;
+  if ((rc = check_ctx(ctx, r, 1, &s))) return rc;
+  return launch_reduce(ctx, *r, s, fuzz, contained, kept, s_row_ptr, s_col, s_ovl, s_strand, d_m,
+                       (hipStream_t)stream);
+}
+
 int cg_mask_branches(cg_ctx *ctx, const cg_graph *g, uint8_t *flags, int32_t *d_counts,
                      void *stream) {
   int rc = check_graph(g, false);

@@ -836,14 +836,18 @@ __device__ __forceinline__ uint32_t piece_head16(const CG_GLOBAL uint32_t *__res
 // array are the words whose first base lies in the piece.
 //   base  forward: stored base of output base 0 of the bases array, so word
 //         w starts at stored base base + 16 w; reverse: stored base at which
-//         the 64-base window of a group starting at word w begins is
-//         base - 16 w (everything modulo 2^64)
+//         the (16 kGroupWords)-base window of a group starting at word w
+//         begins is base - 16 w (everything modulo 2^64)
 //   info  bits 0-4: bases of the piece in its last owned word (1..16);
 //         bit 5: reverse; bit 6: the piece ends its contig
 struct CopyD {
   uint64_t base, w0;
   uint32_t nw, info;
 };
+
+// words per group: a lane's share of one row of a step
+constexpr int kGroupWords = 4;
+static_assert(kGroupWords % 4 == 0, "groups are moved in 16-byte units");
 // What a word straddling into the next piece needs of it.
 struct CopyE {
   uint64_t hsrc;   // head_src of the piece
@@ -858,7 +862,7 @@ __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
   c.nw = (uint32_t)(j1 - j0);
   const uint32_t fs = (uint32_t)(pend - 16 * (j1 - 1));
   c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u);
-  c.base = d.rev ? d.src + d.rlen - 64 - d.skip + d.poff + 16 * d.cb
+  c.base = d.rev ? d.src + d.rlen - 16 * kGroupWords - d.skip + d.poff + 16 * d.cb
                  : d.src + d.skip - d.poff - 16 * d.cb;
   return c;
 }
@@ -875,15 +879,16 @@ constexpr int kCopyUnroll = 2;  // groups per lane per step
 // One step of the copy: kCopyUnroll groups per lane (groups g, g + 64, ...),
 // their pieces' descriptors and store windows.
 struct CopyStage {
-  uint32_t win[kCopyUnroll][5];  // word 4 only where the neighbouring lane lacks it (nb)
+  uint32_t win[kCopyUnroll][kGroupWords + 1];  // the last word only where the neighbouring
+                                               // lane lacks it (nb)
   uint32_t hlo[kCopyUnroll], hhi[kCopyUnroll];  // store words of the next piece's head
   CopyD d[kCopyUnroll];
   CopyE e[kCopyUnroll];
   uint32_t k[kCopyUnroll];
   int t[kCopyUnroll];
   bool ok[kCopyUnroll];
-  bool nb[kCopyUnroll];  // word 4 is word 0 of the next group's window, held by lane l + 1
-                         // (forward) or l - 1 (reverse)
+  bool nb[kCopyUnroll];  // the last word is word 0 of the next group's window, held by
+                         // lane l + 1 (forward) or l - 1 (reverse)
 };
 
 // x of lane l - 1 in lane l, by a DPP wave shift (wave_shr:1); lane 0 keeps
@@ -928,7 +933,7 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     const uint32_t gs = __shfl(gstart, t);
     const uint32_t g = gb + lane + kWave * u;
     S.ok[u] = g < G;
-    S.k[u] = S.ok[u] ? 4 * (g - gs) : 0;  // first owned word of the group
+    S.k[u] = S.ok[u] ? kGroupWords * (g - gs) : 0;  // first owned word of the group
   }
   // loads only, so that nothing here waits for memory and the step's loads
   // stay in flight while the previous step is finished
@@ -937,13 +942,13 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     const CopyD &d = S.d[u];
     const bool rev = d.info & 32u;
     const uint64_t w = d.w0 + S.k[u];
-    // the piece's window: 5 store words covering the group's 64 bases, as
-    // one 16-byte load (dword aligned) and a dword; clamped word by word at
-    // the ends of the store, where the words outside it are never used
+    // the piece's window: kGroupWords + 1 store words covering the group's
+    // bases, as 16-byte loads (dword aligned) and a dword; clamped word by
+    // word at the ends of the store, where the words outside it are never used
     const uint64_t sb = rev ? d.base - 16 * w : d.base + 16 * w;
     const int64_t sw = S.ok[u] ? (int64_t)sb >> 4 : 0;
     // the neighbouring lane's group is the next one of the same piece: its
-    // window starts at word 4 of this one
+    // window starts at the last word of this one
     // (both shifts by every lane, then the choice: a shift must never run
     // with part of the wave switched off)
     const uint32_t tk = (uint32_t)S.t[u] | (S.ok[u] ? 0x80000000u : 0u);
@@ -953,23 +958,26 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
     const bool okn = (tnb >> 31) != 0u;
     const bool edge = rev ? lane == 0 : lane == kWave - 1;
     S.nb[u] = false;
-    if (sw >= 0 && sw + 5 <= (int64_t)nwords) {
-      u32x4 a;
-      __builtin_memcpy(&a, seq + sw, 16);
-      S.win[u][0] = a.x;
-      S.win[u][1] = a.y;
-      S.win[u][2] = a.z;
-      S.win[u][3] = a.w;
+    if (sw >= 0 && sw + kGroupWords + 1 <= (int64_t)nwords) {
+#pragma unroll
+      for (int v = 0; v < kGroupWords / 4; ++v) {
+        u32x4 a;
+        __builtin_memcpy(&a, seq + sw + 4 * v, 16);
+        S.win[u][4 * v] = a.x;
+        S.win[u][4 * v + 1] = a.y;
+        S.win[u][4 * v + 2] = a.z;
+        S.win[u][4 * v + 3] = a.w;
+      }
       S.nb[u] = S.ok[u] && okn && !edge && tn == S.t[u];
-      S.win[u][4] = S.nb[u] ? 0u : seq[sw + 4];
+      S.win[u][kGroupWords] = S.nb[u] ? 0u : seq[sw + kGroupWords];
     } else {
 #pragma unroll
-      for (int i = 0; i < 5; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
+      for (int i = 0; i <= kGroupWords; ++i) S.win[u][i] = seq[clamp_word(sw + i, nwords)];
     }
     // the next piece's first 16 bases, for the group holding the piece's
     // last word
     S.hlo[u] = S.hhi[u] = 0;
-    if (S.ok[u] && S.k[u] + 4 >= d.nw) {
+    if (S.ok[u] && S.k[u] + kGroupWords >= d.nw) {
       const int64_t hw = (int64_t)S.e[u].hsrc >> 4;
       S.hlo[u] = seq[clamp_word(hw, nwords)];
       S.hhi[u] = seq[clamp_word(hw + 1, nwords)];
@@ -983,20 +991,24 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
                                           uint64_t nwords, CG_GLOBAL uint32_t *__restrict__ bases) {
 #pragma unroll
   for (int u = 0; u < kCopyUnroll; ++u) {
-    // word 4 from the neighbouring lane, while every lane is still active
+    // the last window word from the neighbouring lane, while every lane is
+    // still active
     const uint32_t up = wave_next_u32(S.win[u][0]), dn = wave_prev_u32(S.win[u][0]);
     if (!S.ok[u]) continue;
     const CopyD &d = S.d[u];
     const bool rev = d.info & 32u;
-    uint32_t win[5] = {S.win[u][0], S.win[u][1], S.win[u][2], S.win[u][3],
-                       S.nb[u] ? (rev ? dn : up) : S.win[u][4]};
+    uint32_t win[kGroupWords + 1];
+#pragma unroll
+    for (int i = 0; i < kGroupWords; ++i) win[i] = S.win[u][i];
+    win[kGroupWords] = S.nb[u] ? (rev ? dn : up) : S.win[u][kGroupWords];
     const uint32_t sh = 2u * (uint32_t)((rev ? d.base - 16 * (d.w0 + S.k[u])
                                             : d.base + 16 * (d.w0 + S.k[u])) & 15);
-    const uint32_t nw = d.nw - S.k[u] < 4 ? d.nw - S.k[u] : 4;
-    uint32_t out[4];
+    const uint32_t nw = d.nw - S.k[u] < kGroupWords ? d.nw - S.k[u] : kGroupWords;
+    uint32_t out[kGroupWords];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      out[i] = rev ? revcomp16(__builtin_amdgcn_alignbit(win[4 - i], win[3 - i], sh))
+    for (int i = 0; i < kGroupWords; ++i)
+      out[i] = rev ? revcomp16(__builtin_amdgcn_alignbit(win[kGroupWords - i],
+                                                         win[kGroupWords - 1 - i], sh))
                    : __builtin_amdgcn_alignbit(win[i + 1], win[i], sh);
     const int fs = (int)(d.info & 31u);
     if (S.k[u] + nw == d.nw && fs < 16) {
@@ -1028,12 +1040,15 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
       out[nw - 1] = x;
     }
     CG_GLOBAL uint32_t *o = bases + d.w0 + S.k[u];
-    if (nw == 4) {
-      const u32x4 v = {out[0], out[1], out[2], out[3]};
-      __builtin_memcpy(o, &v, 16);  // one 16-byte store, dword aligned
+    if (nw == kGroupWords) {
+#pragma unroll
+      for (int v = 0; v < kGroupWords / 4; ++v) {
+        const u32x4 x4 = {out[4 * v], out[4 * v + 1], out[4 * v + 2], out[4 * v + 3]};
+        __builtin_memcpy(o + 4 * v, &x4, 16);  // 16-byte stores, dword aligned
+      }
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < kGroupWords; ++i)
         if (i < (int)nw) o[i] = out[i];
     }
   }
@@ -1041,7 +1056,7 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
 
 // One wave copies the chunk of cnt (<= 64) consecutive pieces starting at
 // piece c0 of a graph with n_e pieces.  Lane l gathers piece c0+l's
-// descriptor; the chunk's four-word groups (each owned by the piece holding
+// descriptor; the chunk's kGroupWords-word groups (each owned by the piece holding
 // the first base of its words) are then spread over the lanes, 64 groups per
 // row, so lanes of one row work on different pieces.  Every word is a
 // funnel shift of two store words, reverse-complemented in registers for a
@@ -1060,7 +1075,7 @@ __device__ __forceinline__ void copy_chunk(const uint32_t *seq_, uint64_t nwords
   if (lane < cnt) {
     pd = load_piece(A, c0 + lane);
     my = copy_desc(pd);
-    ng = (my.nw + 3) >> 2;
+    ng = (my.nw + kGroupWords - 1) / kGroupWords;
   }
   // the next piece of every lane's piece: from the next lane, or loaded for
   // the chunk's last piece

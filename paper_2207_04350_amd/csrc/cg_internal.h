@@ -275,6 +275,9 @@ int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_
                   hipStream_t st);
 int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_parts &parts,
                     const cg_local &local, int32_t P, const cg_contigs &out, hipStream_t st);
+int launch_reduce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, uint32_t fuzz,
+                  uint8_t *contained, uint8_t *kept, int32_t *s_row_ptr, int32_t *s_col,
+                  uint32_t *s_ovl, uint8_t *s_strand, int32_t *d_m, hipStream_t st);
 
 inline ScanCtx scan_ctx(cg_ctx *ctx, const Scratch &s) {
   return ScanCtx{s.scan_status, &ctx->fixed->scan_ticket, &ctx->fixed->scan_done,

@@ -57,3 +57,17 @@ def test_null_arguments_rejected_on_host():
     g.pre = g.row_ptr = None
     g.n = 1 << 30
     assert lib.cg_components(None, ctypes.byref(g), None, None, None) == cg.CG_EINVAL
+
+
+def test_reduce_arguments_checked_on_host():
+    lib = cg.lib()
+    g = cg.CgGraph()
+    g.n, g.m = 4, 0
+    buf = (ctypes.c_int32 * 8)()
+    g.row_ptr = ctypes.cast(buf, ctypes.c_void_p)   # checked on the host only, never read
+    # no outputs, no context: argument errors before any device work
+    assert lib.cg_reduce(None, ctypes.byref(g), 0, None, None, None, None, None, None, None,
+                         None) == cg.CG_EINVAL
+    assert b"NULL" in lib.cg_last_error()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert lib.cg_reduce(None, ctypes.byref(g), 0, p, p, p, p, p, p, p, None) == cg.CG_EINVAL

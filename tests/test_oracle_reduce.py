@@ -107,3 +107,18 @@ def test_ids_do_not_matter_and_reduction_is_idempotent():
     want = sorted(zip(perm[srows].tolist(), perm[s.col].tolist()))
     prow = np.repeat(np.arange(ps.n), np.diff(ps.row_ptr))
     assert sorted(zip(prow.tolist(), ps.col.tolist())) == want
+
+
+def test_a_hub_keeps_its_first_neighbour_only():
+    # hub read 0 overlaps reads 1..k, each read i also overlaps read i + 1,
+    # with overhangs making 0 -> i -> i+1 exactly as long as 0 -> i+1
+    k = 40
+    rng = np.random.default_rng(1)
+    reads = [rng.integers(0, 4, size=100_000).astype(np.uint8)] + \
+            [rng.integers(0, 4, size=10_000).astype(np.uint8) for _ in range(k)]
+    edges = [(0, i, 10_000 - 5 * i, 0, 0) for i in range(1, k + 1)]
+    edges += [(i, i + 1, 9_995, 0, 0) for i in range(1, k)]
+    c, kept, s = oracle.reduce(synth.graph_from_edges(reads, edges))
+    assert not c.any()
+    assert s.row_ptr[1] == 1 and s.col[0] == 1
+    assert s.m == 2 * k
