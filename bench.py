@@ -190,7 +190,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g", "serve"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g", "serve", "reduce"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: measured requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests on the GPU")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -233,6 +233,8 @@ def main():
 
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "reduce":
+        return reduce_bench(args)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -501,6 +503,93 @@ def main():
             pool = cpu_pool_baseline(graphs, Ps, args.cpu_workers)
             result["cpu_baseline_pool"] = pool
             log("oracle pool: %d processes, %.2fs wall" % (args.cpu_workers, pool["seconds"]))
+    print(json.dumps(result), flush=True)
+
+
+def reduce_bench(args):
+    """The step before the path: contained-read pruning and transitive
+    reduction (cg_reduce) of the overlap graph of the 50 Mbp workload's reads
+    (every pair overlapping by >= 1000 bases, contained reads included)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2207_04350_amd import cg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cg.lib()
+    t0 = time.time()
+    g = synth.config_graph(2)
+    r = synth.overlap_graph(g)
+    log("overlap graph: n=%d, %d entries (string graph: %d) in %.1fs"
+        % (r.n, r.m, g.m, time.time() - t0))
+    ctx = cg.Context.for_graph(r.n, r.m, 1)
+    dg = cg.DeviceGraph(r, dev)
+    out = cg.Reduced(r.n, r.m, dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        cg.reduce(ctx, dg, out, 0, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        cg.reduce(ctx, dg, out, 0, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = e0.elapsed_time(e1) / args.steps
+    assert ctx.status(stream) == 0, "device status raised"
+    ctx.profile(8 * args.reps + 8)
+    for _ in range(args.reps):
+        cg.reduce(ctx, dg, out, 0, stream)
+    prof = {k: v for k, v in ctx.profile_read().items() if k[0] != "_"}
+    ctx.profile(0)
+    m_s = int(out.d_m.item())
+    identical = m_s == g.m and np.array_equal(out.col[:m_s].cpu().numpy(), g.col)
+    for k, (c, kms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log("  reduce %-16s %4d launches %9.3f ms/step" % (k, c, kms / args.reps))
+    n, m = r.n, r.m
+    # each array once: R's row_ptr, col, ovl, strand and read lengths read;
+    # contained, kept and the string graph written
+    algo = 4 * (n + 1) + 9 * m + 4 * n + n + m + 4 * (n + 1) + 9 * m_s
+    dom = max(prof, key=lambda k: prof[k][1])
+    dom_us = 1e3 * prof[dom][1] / prof[dom][0]
+    # the dominant kernel's own share: R read once, marks written
+    dom_bytes = {"k_red_trans": 4 * (n + 1) + 9 * m + 4 * n + n + m}.get(dom, algo)
+    result = {
+        "metric": "overlap-graph entries/s (contained-read pruning + transitive reduction)",
+        "value": m / (wall * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall,
+        "gpu_ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded simulated genome and reads; exact overlaps >= 1000 bases)",
+        "config": {"workload": "overlap graph of the 50 Mbp + 200x8 kbp repeats, 30x, "
+                               "LN(12k,4k) reads (125,000 reads)",
+                   "reads": n, "entries": m, "string_graph_entries": m_s,
+                   "equals_generator_string_graph": bool(identical)},
+        "kernels_ms": {k: v[1] / args.reps for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_us * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom_bytes / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": dom_us, "bytes_per_launch": dom_bytes,
+                     "note": "k_red_trans re-reads each neighbour's row once per row that "
+                             "holds it (sum of squared degrees), bound by those lookups"},
+    }
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        oc, ok, os_ = oracle.reduce(r)
+        sec = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": m / sec, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole overlap graph, single-threaded C oracle", "seconds": sec}
+        result["parity"] = {
+            "kept_identical": bool(np.array_equal(out.kept[:m].cpu().numpy(), ok)),
+            "contained_identical": bool(np.array_equal(out.contained[:n].cpu().numpy(), oc))}
+    ctx.close()
     print(json.dumps(result), flush=True)
 
 
