@@ -834,14 +834,20 @@ __device__ __forceinline__ uint32_t piece_head16(const CG_GLOBAL uint32_t *__res
 
 // Copy descriptor of one piece: output words [w0, w0 + nw) of the bases
 // array are the words whose first base lies in the piece.
-//   base  forward: stored base of output base 0 of the bases array, so word
-//         w starts at stored base base + 16 w; reverse: stored base at which
-//         the (16 kGroupWords)-base window of a group starting at word w
-//         begins is base - 16 w (everything modulo 2^64)
+//   sw0   store word at which the window of the piece's first group (output
+//         word w0) starts; the group at word w0 + k starts at sw0 + k
+//         (forward) or sw0 - k (reverse).  Signed: a reverse window may start
+//         before the store.  Forward, output word w begins at stored base
+//         16 sw0 + sh/2 + 16 (w - w0); reverse, the (16 kGroupWords)-base
+//         window of the group at word w begins there with w0 - w in place of
+//         w - w0.
 //   info  bits 0-4: bases of the piece in its last owned word (1..16);
-//         bit 5: reverse; bit 6: the piece ends its contig
+//         bit 5: reverse; bit 6: the piece ends its contig; bits 8-11: the
+//         window's first base within its first store word (the funnel shift
+//         is twice that)
 struct CopyD {
-  uint64_t base, w0;
+  int64_t sw0;
+  uint64_t w0;
   uint32_t nw, info;
 };
 
@@ -861,9 +867,11 @@ __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
   c.w0 = d.cb + j0;
   c.nw = (uint32_t)(j1 - j0);
   const uint32_t fs = (uint32_t)(pend - 16 * (j1 - 1));
-  c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u);
-  c.base = d.rev ? d.src + d.rlen - 16 * kGroupWords - d.skip + d.poff + 16 * d.cb
-                 : d.src + d.skip - d.poff - 16 * d.cb;
+  // stored base where the window of the first group begins (modulo 2^64)
+  const uint64_t sb0 = d.rev ? d.src + d.rlen - 16 * kGroupWords - d.skip + d.poff - 16 * j0
+                             : d.src + d.skip - d.poff + 16 * j0;
+  c.sw0 = (int64_t)sb0 >> 4;
+  c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u) | ((uint32_t)(sb0 & 15) << 8);
   return c;
 }
 
@@ -924,7 +932,7 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
 #pragma unroll
   for (int u = 0; u < kCopyUnroll; ++u) {
     const int t = S.t[u];
-    S.d[u].base = __shfl(my.base, t);
+    S.d[u].sw0 = __shfl(my.sw0, t);
     S.d[u].w0 = __shfl(my.w0, t);
     S.d[u].nw = __shfl(my.nw, t);
     S.d[u].info = __shfl(my.info, t);
@@ -941,12 +949,10 @@ __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G
   for (int u = 0; u < kCopyUnroll; ++u) {
     const CopyD &d = S.d[u];
     const bool rev = d.info & 32u;
-    const uint64_t w = d.w0 + S.k[u];
     // the piece's window: kGroupWords + 1 store words covering the group's
     // bases, as 16-byte loads (dword aligned) and a dword; clamped word by
     // word at the ends of the store, where the words outside it are never used
-    const uint64_t sb = rev ? d.base - 16 * w : d.base + 16 * w;
-    const int64_t sw = S.ok[u] ? (int64_t)sb >> 4 : 0;
+    const int64_t sw = S.ok[u] ? (rev ? d.sw0 - (int64_t)S.k[u] : d.sw0 + (int64_t)S.k[u]) : 0;
     // the neighbouring lane's group is the next one of the same piece: its
     // window starts at the last word of this one
     // (both shifts by every lane, then the choice: a shift must never run
@@ -1001,8 +1007,7 @@ __device__ __forceinline__ void copy_emit(const CopyStage &S, const PieceArrays 
 #pragma unroll
     for (int i = 0; i < kGroupWords; ++i) win[i] = S.win[u][i];
     win[kGroupWords] = S.nb[u] ? (rev ? dn : up) : S.win[u][kGroupWords];
-    const uint32_t sh = 2u * (uint32_t)((rev ? d.base - 16 * (d.w0 + S.k[u])
-                                            : d.base + 16 * (d.w0 + S.k[u])) & 15);
+    const uint32_t sh = 2u * ((d.info >> 8) & 15u);
     const uint32_t nw = d.nw - S.k[u] < kGroupWords ? d.nw - S.k[u] : kGroupWords;
     uint32_t out[kGroupWords];
 #pragma unroll
