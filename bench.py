@@ -79,11 +79,11 @@ def csrc_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of a batched kernel from the committed counter
-    profile (scaled FETCH_SIZE + WRITE_SIZE), or None when the kernel sources
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "batched_512graphs_hbm_bytes.md")
+def profiled_traffic(kernel, profile="batched_512graphs_hbm_bytes.md"):
+    """HBM bytes per launch of a kernel from a committed counter profile
+    (scaled FETCH_SIZE + WRITE_SIZE), or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     digest, mb = None, None
@@ -573,7 +573,10 @@ def reduce_bench(args):
         "kernels_ms": {k: v[1] / args.reps for k, v in prof.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_bytes / (dom_us * 1e-6) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_bytes / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom_bytes / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(dom, "reduce_50mbp_hbm_bytes.md"),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE "
+                                     "x1.0, profiles/reduce_50mbp_hbm_bytes.md)",
                      "avg_launch_us": dom_us, "bytes_per_launch": dom_bytes,
                      "note": "k_red_trans re-reads each neighbour's row once per row that "
                              "holds it (sum of squared degrees), bound by those lookups"},

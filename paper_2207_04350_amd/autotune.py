@@ -1,10 +1,11 @@
 """Launch-shape tuner for the batched form.
 
-Tries candidate cg_batch_params on the actual batch, times each candidate's
-captured HIP graph, and keeps the fastest.  Every candidate's outputs are
-compared, array by array on the device, with the first candidate's: a shape
-may change speed, never a byte of the result.  Results are cached per batch
-shape (number of jobs, reads, entries) in a JSON file.
+Tries candidate cg_batch_params on the actual batch, times each launch of
+each candidate's captured HIP graph, and keeps the one with the smallest
+median.  Every candidate's outputs are compared, array by array on the
+device, with the first candidate's: a shape may change speed, never a byte
+of the result.  Results are cached per batch shape (number of jobs, reads,
+entries) in a JSON file.
 """
 from __future__ import annotations
 
@@ -55,7 +56,7 @@ def _same(snap, jobs):
                for sa, sb in zip(snap, cur) for a, b in zip(sa, sb))
 
 
-def tune(ctx, jobs, stream, reps=3, candidates=None, use_cache=True, log=None):
+def tune(ctx, jobs, stream, reps=10, candidates=None, use_cache=True, log=None):
     """Return (best (vertex_tile, copy_block, persist_blocks), {shape: ms})."""
     import torch
     key = _key(jobs)
@@ -82,14 +83,15 @@ def tune(ctx, jobs, stream, reps=3, candidates=None, use_cache=True, log=None):
             ref = _snapshot(jobs)
         elif not _same(ref, jobs):
             raise RuntimeError("launch shape %s changed the result" % (shape,))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
         with torch.cuda.stream(stream):
-            e0.record(stream)
-            for _ in range(reps):
+            b.launch(stream)  # warm
+            ev[0].record(stream)
+            for i in range(reps):
                 b.launch(stream)
-            e1.record(stream)
+                ev[i + 1].record(stream)
         stream.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(reps))[reps // 2]
         table["%d/%d/%d" % shape] = ms
         if log:
             log("tune %s: %.3f ms" % (shape, ms))
