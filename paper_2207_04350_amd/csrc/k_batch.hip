@@ -5,12 +5,15 @@
 //                  the tiles of every job (tile -> job table)
 //  compaction      reduce-then-scan per job: tiles count, then each tile adds
 //                  up the counts of the tiles before it in its job
-//  component and   persistent grids stride over the batch-wide item ranges
+//  component and   persistent grids over the batch-wide item ranges
 //  piece passes    (components, pieces) whose per-job bases the last LPT
-//                  workgroup computes on the device
+//                  workgroup computes on the device; the per-component passes
+//                  take a work queue of every component of the batch in
+//                  decreasing read count
 //
 // Every counter a launch uses is reset by the launch itself, and the
-// union-find forest is reset by bumping its tag, so the ten launches can be
+// union-find forest is reset by bumping its tag, so the launches (twelve, or
+// more when one-read components are eligible or weights are bases) can be
 // captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
