@@ -16,9 +16,14 @@ constexpr int kWave = 64;
 // Fixed device state of a context: small counters that kernels clean up
 // themselves after use, so that every launch finds them zero.
 // ---------------------------------------------------------------------------
+// Workgroups of the plain mask pass at most (it strides over the reads).
+constexpr int kMaskMaxBlocks = 1024;
+
 struct Fixed {
-  unsigned long long mask_acc[2];  // branch count, kept-entry count
-  unsigned int mask_ticket;
+  // per workgroup of the mask pass: branch reads (low 32 bits), kept entries
+  // (high 32)
+  unsigned long long mask_part[kMaskMaxBlocks];
+  unsigned int mask_ticket;  // workgroups done, for grids that sum in the kernel
   unsigned int status;             // CG_STATUS_* bits
   unsigned long long valid_best;   // packed first failure of cg_validate
   unsigned int scan_ticket;        // look-back scan: block ticket
@@ -175,47 +180,70 @@ __device__ __forceinline__ unsigned long long atomic_ld64(unsigned long long *p)
 }
 
 // Publish the block aggregate, look back, publish the inclusive prefix;
-// returns the exclusive prefix of the block.  Thread 0 only.
+// returns the exclusive prefix of the block.  Called by every lane of the
+// block's first wave (the result is the same in every lane).
+//
+// The look-back reads a window of 64 predecessors at once, one per lane:
+// the nearest one holding an inclusive prefix ends the walk, and the
+// aggregates of the lanes before it are added to it; a window of aggregates
+// only adds all 64 and moves 64 blocks back.  (One predecessor per step made
+// block k wait about k round trips when all blocks start together.)  A status
+// word carries its flag and value in one 64-bit atomic and nothing else is
+// read through it, so relaxed device-scope atomics suffice: no L2 write-back
+// per publish and no L2 invalidation per poll.
 __device__ __forceinline__ unsigned long long lookback_publish(ScanCtx sc, int blk,
                                                                unsigned long long agg,
                                                                int seg_first = 0) {
+  const int lane = lane_id();
   if (blk == seg_first) {
-    __hip_atomic_store(&sc.status[blk], kFlagPre | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_store(&sc.status[blk], kFlagPre | agg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     return 0;
   }
-  __hip_atomic_store(&sc.status[blk], kFlagAgg | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  // the segment's first block publishes an inclusive prefix, so the walk
-  // below never leaves the segment
+  if (lane == 0)
+    __hip_atomic_store(&sc.status[blk], kFlagAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned long long excl = 0;
-  int p = blk - 1;
+  int top = blk - 1;
   long long spins = 0;
   while (true) {
-    unsigned long long s = __hip_atomic_load(&sc.status[p], __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long f = s & ~kValMask;
-    if (f == 0) {  // predecessor has not published yet (it is running)
+    // the segment's first block publishes an inclusive prefix, so no window
+    // needs a block before it
+    const int p = top - lane;
+    const unsigned long long s = p >= seg_first ? atomic_ld64(&sc.status[p]) : kFlagPre;
+    const unsigned long long f = s & ~kValMask;
+    const uint64_t pre = __ballot(f == kFlagPre);
+    const uint64_t none = __ballot(f == 0);
+    // lanes up to and including the nearest inclusive prefix (all if none)
+    const uint64_t upto = pre ? (pre ^ (pre - 1)) : ~0ull;
+    if (none & upto) {  // a predecessor has not published yet (it is running)
       if (++spins < kLookbackSpinLimit) continue;
-      atomicOr(sc.error, CG_STATUS_SCAN_STALLED);
+      if (lane == 0) atomicOr(sc.error, CG_STATUS_SCAN_STALLED);
       break;
     }
-    excl += s & kValMask;
-    if (f == kFlagPre) break;
-    --p;
+    unsigned long long v = ((upto >> lane) & 1ull) ? (s & kValMask) : 0ull;
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    excl += v;
+    if (pre) break;
+    top -= kWave;
   }
-  __hip_atomic_store(&sc.status[blk], kFlagPre | (excl + agg), __ATOMIC_RELEASE,
-                     __HIP_MEMORY_SCOPE_AGENT);
+  if (lane == 0)
+    __hip_atomic_store(&sc.status[blk], kFlagPre | (excl + agg), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   return excl;
 }
 
 // Called by every thread of every block at the very end of a look-back scan
-// kernel: the last block out clears the state for the next launch.
+// kernel: the last block out clears the state for the next launch.  The exit
+// count is a release, so a block's status stores are done before the last
+// block can clear them.
 __device__ __forceinline__ void lookback_finish(ScanCtx sc, int nblocks) {
   __shared__ int last;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned d = atomicAdd(sc.done, 1u);
+    unsigned d = __hip_atomic_fetch_add(sc.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     last = (d == (unsigned)nblocks - 1);
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   if (last) {
@@ -241,7 +269,10 @@ __device__ __forceinline__ unsigned long long lookback_block_scan(ScanCtx sc, in
   __shared__ unsigned long long base;
   unsigned long long agg;
   unsigned long long ex = block_excl_scan<unsigned long long, BLOCK>(val, sh, &agg);
-  if (threadIdx.x == 0) base = lookback_publish(sc, blk, agg, seg_first);
+  if (threadIdx.x < kWave) {
+    const unsigned long long b = lookback_publish(sc, blk, agg, seg_first);
+    if (threadIdx.x == 0) base = b;
+  }
   __syncthreads();
   *incl_end = base + agg;
   return base + ex;

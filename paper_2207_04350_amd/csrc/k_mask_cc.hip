@@ -10,59 +10,89 @@
 namespace cg {
 
 // ---------------------------------------------------------------------------
-// Mask: one thread per vertex.  row_ptr[v+1] comes from the neighbouring lane
+// Mask: one thread per vertex, a grid of at most kMaskMaxBlocks workgroups
+// striding over the vertices.  row_ptr[v+1] comes from the neighbouring lane
 // (one coalesced load per lane); the at most two neighbours of a degree <= 2
 // row are the only gathers.
 // ---------------------------------------------------------------------------
-constexpr int kMaskBlock = 256;
+constexpr int kMaskBlock = 512;
+
+// Grids of at most this many workgroups add the counts up in the kernel
+// (one release per workgroup); larger ones leave it to k_mask_sum.
+constexpr int kMaskSumInKernel = 64;
+
+__device__ __forceinline__ void store_counts(unsigned long long a, int32_t *d_counts) {
+  d_counts[0] = (int32_t)(uint32_t)a;
+  d_counts[1] = (int32_t)(uint32_t)(a >> 32);
+}
 
 __global__ __launch_bounds__(kMaskBlock) void k_mask(int32_t n, const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col,
                                                      uint8_t *__restrict__ flags, Fixed *fx,
                                                      int32_t *__restrict__ d_counts) {
-  const int64_t v = (int64_t)blockIdx.x * kMaskBlock + threadIdx.x;
-  const bool live = v < n;
-  int32_t b = v <= n ? row_ptr[v] : 0;  // row_ptr has n+1 entries
-  int32_t nxt = __shfl_down(b, 1);
-  if (lane_id() == kWave - 1 && live) nxt = row_ptr[v + 1];
-  const int32_t deg = live ? nxt - b : 0;
-  uint32_t f = 0;
-  if (live) {
-    f = vertex_flags(row_ptr, col, b, deg);
-    flags[v] = (uint8_t)f;
-  }
-  // counts: ballots per wave, one atomic per wave, last block publishes
-  unsigned long long nb = __popcll(__ballot(f & 1));
-  unsigned long long ml = __popcll(__ballot(f & 2)) + __popcll(__ballot(f & 4));
-  if (lane_id() == 0 && (nb | ml)) {
-    if (nb) atomicAdd(&fx->mask_acc[0], nb);
-    if (ml) atomicAdd(&fx->mask_acc[1], ml);
-    __threadfence();
-  }
-  __shared__ int last;
+  // counts: ballots per wave, summed per workgroup in LDS, one plain store
+  // per workgroup of a packed word (branch reads low, kept entries high:
+  // neither sum reaches 2^32).  A large grid leaves the sum to k_mask_sum
+  // and uses no atomics and no fences (an agent-scope release writes the L2
+  // back, which thousands of workgroups would each pay).
+  __shared__ unsigned long long s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(&fx->mask_ticket, 1u);
-    last = (t == gridDim.x - 1);
+  const int64_t stride = (int64_t)gridDim.x * kMaskBlock;
+  // every lane of a wave runs the same iterations (the bound is rounded up
+  // to whole workgroups), so the shuffle and the ballots see the whole wave
+  const int64_t end = ((int64_t)n + kMaskBlock - 1) / kMaskBlock * kMaskBlock;
+  for (int64_t v = (int64_t)blockIdx.x * kMaskBlock + threadIdx.x; v < end; v += stride) {
+    const bool live = v < n;
+    const int32_t b = v <= n ? row_ptr[v] : 0;  // row_ptr has n+1 entries
+    int32_t nxt = __shfl_down(b, 1);
+    if (lane_id() == kWave - 1 && live) nxt = row_ptr[v + 1];
+    const int32_t deg = live ? nxt - b : 0;
+    uint32_t f = 0;
+    if (live) {
+      f = vertex_flags(row_ptr, col, b, deg);
+      flags[v] = (uint8_t)f;
+    }
+    const uint32_t nb = (uint32_t)__popcll(__ballot(f & 1));
+    const uint32_t ml = (uint32_t)(__popcll(__ballot(f & 2)) + __popcll(__ballot(f & 4)));
+    if (lane_id() == 0 && (nb | ml)) atomicAdd(&s_cnt, (unsigned long long)ml << 32 | nb);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    unsigned long long a0 = atomicExch(&fx->mask_acc[0], 0ull);
-    unsigned long long a1 = atomicExch(&fx->mask_acc[1], 0ull);
-    d_counts[0] = (int32_t)a0;
-    d_counts[1] = (int32_t)a1;
-    fx->mask_ticket = 0;
-    __threadfence();
+  if (threadIdx.x != 0) return;
+  if (gridDim.x == 1) {
+    store_counts(s_cnt, d_counts);
+    return;
   }
+  fx->mask_part[blockIdx.x] = s_cnt;
+  if (gridDim.x > kMaskSumInKernel) return;
+  // the last workgroup out adds the parts up
+  const unsigned t =
+      __hip_atomic_fetch_add(&fx->mask_ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (t != gridDim.x - 1) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  unsigned long long a = 0;
+  for (unsigned i = 0; i < gridDim.x; ++i) a += fx->mask_part[i];
+  store_counts(a, d_counts);
+  fx->mask_ticket = 0;
+}
+
+__global__ __launch_bounds__(kWave) void k_mask_sum(int nparts, const Fixed *fx,
+                                                    int32_t *__restrict__ d_counts) {
+  unsigned long long a = 0;
+  for (int i = lane_id(); i < nparts; i += kWave) a += fx->mask_part[i];
+  for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if (lane_id() == 0) store_counts(a, d_counts);
 }
 
 int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_counts,
                 hipStream_t st) {
-  int grid = (int)((g.n + kMaskBlock - 1) / kMaskBlock);
-  if (grid == 0) grid = 1;
-  CG_LAUNCH(ctx, k_mask, dim3(grid), dim3(kMaskBlock), st, g.n, g.row_ptr, g.col, flags,
-                     ctx->fixed, d_counts);
+  int64_t grid = ((int64_t)g.n + kMaskBlock - 1) / kMaskBlock;
+  if (grid < 1) grid = 1;
+  if (grid > kMaskMaxBlocks) grid = kMaskMaxBlocks;
+  CG_LAUNCH(ctx, k_mask, dim3((unsigned)grid), dim3(kMaskBlock), st, g.n, g.row_ptr, g.col, flags,
+            ctx->fixed, d_counts);
+  if (grid > kMaskSumInKernel)
+    CG_LAUNCH(ctx, k_mask_sum, dim3(1), dim3(kWave), st, (int)grid, ctx->fixed, d_counts);
   return hip_check(hipGetLastError(), "k_mask");
 }
 
