@@ -101,7 +101,7 @@ struct BatchDev {
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
                                     // reads, 2: above kIndSmallCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
-  int32_t *chunk_job;               // [sum n / 64 + n_jobs] job of each copy chunk
+  int32_t *chunk_job;               // [sum of ceil(n / kChunkPieces)] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
   int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
@@ -680,6 +680,11 @@ __global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
 // the batched form's LPT runs one job per workgroup of 256 threads, so that
 // all jobs' workgroups are resident at once
 constexpr int kBatchLptBlock = 256;
+// pieces per copy chunk (one wave each).  Chunks are handed to waves as
+// slots free up, so the copy ends with a tail of the last chunks: 64 pieces
+// (about 75 us of one wave's work on 3 kbp pieces) left it long, 16 paid the
+// per-chunk setup too often.
+constexpr int kChunkPieces = 32;
 constexpr int kWqBuckets = 4096;  // read counts from kWqBuckets - 1 up share the top bucket
 constexpr int kBatchSortCap = 2048;
 constexpr int kBatchBinCap = 256;
@@ -740,7 +745,7 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
       xc = (int32_t)(uint32_t)w;
       xp = (int32_t)(uint32_t)(w >> 32);
     }
-    const int64_t xh = (xp + kWave - 1) / kWave;
+    const int64_t xh = (xp + kChunkPieces - 1) / kChunkPieces;
     int64_t tc, tp, th;
     const int64_t ec = block_excl_scan<int64_t, kBatchLptBlock>(xc, sh, &tc);
     const int64_t ep = block_excl_scan<int64_t, kBatchLptBlock>(xp, sh, &tp);
@@ -1007,7 +1012,8 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   }
 }
 
-// 9. packed copy: waves take chunks of 64 consecutive pieces of the batch
+// 9. packed copy: one wave per chunk of kChunkPieces consecutive pieces of a
+// job (the grid covers an upper bound on the chunks; waves past the last exit)
 __device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
   return piece_arrays(J.s.lay_contig, J.out.layout_vid, J.out.layout_rev, J.s.piece_off,
                       J.s.piece_len, J.s.piece_skip, J.g.read_off, J.g.read_len, J.out.len,
@@ -1025,8 +1031,8 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
     const BJob J = job_at(B.jobs, j);
     if (*J.out.d_total_words > J.out.cap_words) continue;
     const int32_t n_e = ld_const(B.piece_base, j + 1) - ld_const(B.piece_base, j);
-    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * kWave;
-    const int cnt = n_e - c0 < kWave ? n_e - c0 : kWave;
+    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * kChunkPieces;
+    const int cnt = n_e - c0 < kChunkPieces ? n_e - c0 : kChunkPieces;
     copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), c0, cnt, n_e, lane_id());
   }
 }
@@ -1043,6 +1049,7 @@ struct cg_batch {
   int32_t n_jobs, n_vtiles;
   bool any_single;  // a job with min_reads <= 1 (one-read components eligible)
   bool any_bases;   // a job partitioned by bases weights
+  int64_t chunk_slots;  // upper bound on the copy chunks of the batch
   cg_batch_params prm;
   BatchDev dev;
   char *mem;
@@ -1150,7 +1157,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   int64_t sum_n = 0, sum_chunks = 0;
   for (int i = 0; i < n_jobs; ++i) {
     sum_n += jobs[i].g.n;
-    sum_chunks += (jobs[i].g.n + kWave - 1) / kWave;
+    sum_chunks += (jobs[i].g.n + kChunkPieces - 1) / kChunkPieces;
   }
   const size_t o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
   const size_t o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
@@ -1178,6 +1185,7 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   b->ctx = ctx;
   b->n_jobs = n_jobs;
   b->n_vtiles = nv;
+  b->chunk_slots = sum_chunks;
   b->any_single = false;
   b->any_bases = false;
   for (int i = 0; i < n_jobs; ++i) {
@@ -1315,7 +1323,12 @@ int cg_batch_run(cg_batch *b, void *stream) {
   CG_LAUNCH(ctx, kb_walk_small, dim3(4 * PB), dim3(kWalkSmallBlock), st, B);
   CG_LAUNCH(ctx, kb_walk, dim3(PB), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);
-  CG_LAUNCH(ctx, kb_copy, dim3(PB), dim3(b->prm.copy_block), st, B);
+  // one wave per copy chunk slot: the hardware hands chunks to waves as
+  // slots free up (a persistent grid with a fixed share per wave left a
+  // tail of unevenly loaded waves); slots past the batch's chunks exit
+  const int64_t wpb = b->prm.copy_block / kWave;
+  const int64_t cgrid = (b->chunk_slots + wpb - 1) / wpb;
+  CG_LAUNCH(ctx, kb_copy, dim3((unsigned)(cgrid > 0 ? cgrid : 1)), dim3(b->prm.copy_block), st, B);
   return hip_check(hipGetLastError(), "cg_batch_run");
 }
 
