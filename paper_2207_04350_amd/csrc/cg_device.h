@@ -121,23 +121,64 @@ __device__ __forceinline__ int next_pow2(int x) {
   return p;
 }
 
+// One compare-exchange of a bitonic stage (k, j), j < 64, in registers: x is
+// element i of the array, held by lane i % 64, and its partner i ^ j is held
+// by lane (i % 64) ^ j of the same wave.  Every lane of the wave takes part.
+template <typename K>
+__device__ __forceinline__ K bitonic_lane_step(K x, int i, int j, int k) {
+  const K p = __shfl_xor(x, j);
+  const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+  const K mn = x < p ? x : p, mx = x < p ? p : x;
+  return keep_min ? mn : mx;
+}
+
+// Stages (k, j) of every k in [k0, k1] with j < 64, in registers, two
+// 64-element segments per wave at a time (independent chains, so their lane
+// shuffles overlap); no barrier: a wave only touches its own segments.
+// Elements past N2 (N2 < 64, or a missing second segment) are held as the
+// largest key and never meet a real one.
+template <typename K>
+__device__ __forceinline__ void bitonic_segments(K *a, int N2, int k0, int k1) {
+  const int nw = (int)(blockDim.x / kWave);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int l = lane_id();
+  const int nseg = (N2 + kWave - 1) / kWave;
+  for (int sgm = w; sgm < nseg; sgm += 2 * nw) {
+    const int i0 = sgm * kWave + l, i1 = (sgm + nw) * kWave + l;
+    K x0 = i0 < N2 ? a[i0] : ~K(0);
+    K x1 = i1 < N2 ? a[i1] : ~K(0);
+    for (int k = k0; k <= k1; k <<= 1)
+      for (int j = (k >> 1) < kWave ? (k >> 1) : kWave / 2; j > 0; j >>= 1) {
+        x0 = bitonic_lane_step(x0, i0, j, k);
+        x1 = bitonic_lane_step(x1, i1, j, k);
+      }
+    if (i0 < N2) a[i0] = x0;
+    if (i1 < N2) a[i1] = x1;
+  }
+}
+
+// Sort a[0, N2) ascending (N2 a power of two) with every thread of the
+// workgroup.  Only the stages whose pairs lie 64 or more apart go through
+// memory with a workgroup barrier each; the stages inside 64-element
+// segments run in registers (for N2 = 512: 6 barriers instead of 45).
 template <typename K>
 __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
-  for (int k = 2; k <= N2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-        int ixj = i ^ j;
-        if (ixj > i) {
-          K x = a[i], y = a[ixj];
-          bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
+  bitonic_segments(a, N2, 2, N2 < kWave ? N2 : kWave);
+  __syncthreads();
+  for (int k = 2 * kWave; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j >= kWave; j >>= 1) {
+      for (int t = threadIdx.x; t < N2 / 2; t += blockDim.x) {
+        const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // pair (i, i + j)
+        const K x = a[i], y = a[i + j];
+        if ((x > y) == ((i & k) == 0)) {
+          a[i] = y;
+          a[i + j] = x;
         }
       }
       __syncthreads();
     }
+    bitonic_segments(a, N2, k, k);
+    __syncthreads();
   }
 }
 
@@ -161,9 +202,20 @@ __device__ __forceinline__ uint64_t wave_next_u64(uint64_t x) {
   return ((uint64_t)nhi << 32) | nlo;
 }
 
+// x of lane l - 1 in lane l, by a DPP wave shift (wave_shr:1); lane 0 keeps
+// its own x
+__device__ __forceinline__ uint32_t wave_prev_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x138, 0xF, 0xF, false);
+}
+// x of lane l + 1 in lane l (wave_shl:1); lane 63 keeps its own x
+__device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x130, 0xF, 0xF, false);
+}
+
 // Bin keys are (load << 16) | bin: ascending key order is ascending
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
+constexpr int kNarrowBinBits = 6;  // bins of the 32-bit keys (at most 64)
 
 // With comp_kind and comp_estart given, it also writes each component's
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
@@ -183,11 +235,15 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
+  __shared__ unsigned long long s_wsum;
   const int tid = threadIdx.x;
   const int N2 = next_pow2(nc > 0 ? nc : 1);
+  if (tid == 0) s_wsum = 0;
+  __syncthreads();
 
   // 1. sort by (weight desc, label asc); components are indexed in label
   // order.  The weight is the read count, or the given weights (below 2^32).
+  unsigned long long wsum = 0;
   for (int i = tid; i < N2; i += blockDim.x) {
     uint64_t w = 0;
     if (i < nc) {
@@ -197,8 +253,11 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         w = 0xFFFFFFFFull;
       }
     }
+    wsum += w;
     keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)w) << 32) | (uint32_t)i : ~0ull;
   }
+  for (int off = kWave / 2; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
+  if (lane_id() == 0 && wsum) atomicAdd(&s_wsum, wsum);
   for (int b = tid; b < P; b += blockDim.x) binA[b] = (uint64_t)b;  // load 0, sorted
   __syncthreads();
   bitonic_sort(keys, N2);
@@ -212,6 +271,36 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   const int W = P < kWave ? P : kWave;
   const bool single_window = P <= kWave;
   int i0 = 0;
+  // Narrow keys: with at most 64 bins and a total weight below 2^26, a bin's
+  // key (load << 6) | bin fits 32 bits, and a step needs half the vector
+  // instructions of the 64-bit one.  Same order, same choices.
+  if (single_window && s_wsum < (1ull << (32 - kNarrowBinBits))) {
+    if (tid < kWave) {
+      const int l = tid;
+      uint32_t key = l < W ? (uint32_t)binA[l] : 0xFFFFFFFFu;  // loads are 0: key = bin
+      for (int base = 0; base < nc; base += kWave) {
+        const int cnt = __builtin_amdgcn_readfirstlane(nc - base < kWave ? nc - base : kWave);
+        const uint64_t item = l < cnt ? keys[base + l] : 0ull;
+        int32_t mine = 0;  // bin of item l
+        for (int t = 0; t < cnt; ++t) {
+          const uint32_t q =
+              0xFFFFFFFFu - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(item >> 32), t);
+          const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, 0);
+          mine = l == t ? (int32_t)(k0 & ((1u << kNarrowBinBits) - 1)) : mine;
+          const uint32_t nk = k0 + (q << kNarrowBinBits);
+          const int p = __popcll(__ballot(key < nk)) - 1;  // lanes 1.. below nk
+          const uint32_t nxt = wave_next_u32(key);
+          key = l < p ? nxt : (l == p ? nk : key);
+        }
+        if (l < cnt) bin_of[(uint32_t)item] = mine;
+      }
+      if (l < W)
+        binA[l] = ((uint64_t)(key >> kNarrowBinBits) << kBinBits) |
+                  (key & ((1u << kNarrowBinBits) - 1));
+    }
+    __syncthreads();
+    i0 = nc;
+  }
   while (i0 < nc) {
     const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
     if (tid < kWave) {
@@ -899,15 +988,6 @@ struct CopyStage {
                          // lane l + 1 (forward) or l - 1 (reverse)
 };
 
-// x of lane l - 1 in lane l, by a DPP wave shift (wave_shr:1); lane 0 keeps
-// its own x
-__device__ __forceinline__ uint32_t wave_prev_u32(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x138, 0xF, 0xF, false);
-}
-// x of lane l + 1 in lane l (wave_shl:1); lane 63 keeps its own x
-__device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x130, 0xF, 0xF, false);
-}
 
 // Find the pieces of a step's groups and start its loads.
 __device__ __forceinline__ void copy_fetch(CopyStage &S, uint32_t gb, uint32_t G, uint32_t gstart,
