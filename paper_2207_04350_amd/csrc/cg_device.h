@@ -216,6 +216,7 @@ __device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
 constexpr int kNarrowBinBits = 6;  // bins of the 32-bit keys (at most 64)
+constexpr int kLptRoundMin = 6;    // equal items taken as one round from this many
 
 // With comp_kind and comp_estart given, it also writes each component's
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
@@ -282,15 +283,47 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         const int cnt = __builtin_amdgcn_readfirstlane(nc - base < kWave ? nc - base : kWave);
         const uint64_t item = l < cnt ? keys[base + l] : 0ull;
         int32_t mine = 0;  // bin of item l
-        for (int t = 0; t < cnt; ++t) {
-          const uint32_t q =
-              0xFFFFFFFFu - (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(item >> 32), t);
+        const uint32_t iw = (uint32_t)(item >> 32);
+        for (int t = 0; t < cnt;) {
+          const uint32_t wt = (uint32_t)__builtin_amdgcn_readlane((int)iw, t);
+          const uint32_t q = 0xFFFFFFFFu - wt;
           const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, 0);
-          mine = l == t ? (int32_t)(k0 & ((1u << kNarrowBinBits) - 1)) : mine;
           const uint32_t nk = k0 + (q << kNarrowBinBits);
-          const int p = __popcll(__ballot(key < nk)) - 1;  // lanes 1.. below nk
-          const uint32_t nxt = wave_next_u32(key);
-          key = l < p ? nxt : (l == p ? nk : key);
+          const uint64_t below = __ballot(key < nk);  // lane 0 and the lanes below nk
+          // items t, t+1, ... of the same weight (within this batch)
+          const uint64_t same = __ballot(l < cnt && iw == wt) >> t;
+          const int run = ~same ? (int)__builtin_ctzll(~same) : kWave;
+          const int m = __popcll(below);
+          const int c = run < m ? run : m;
+          if (c >= kLptRoundMin) {
+            // a round: c equal items go to lanes 0..c-1 in order (each of
+            // those bins is below lane 0's raised key, so the steps would pick
+            // them one after another); the raised keys of lanes 0..c-1 and
+            // the keys of lanes c.. are two sorted runs, merged by rank
+            const uint32_t src = (uint32_t)__shfl((int)key, (l - t) & (kWave - 1));
+            if (l >= t && l < t + c) mine = (int32_t)(src & ((1u << kNarrowBinBits) - 1));
+            const uint32_t x = l < c ? key + (q << kNarrowBinBits) : key;
+            // rank in the other run: lanes 0..c-1 search lanes c..63, the
+            // others lanes 0..c-1 (every lane runs every step)
+            int lo = l < c ? c : 0, hi = l < c ? kWave : c;
+            for (int it = 0; it < 7; ++it) {
+              const int mid = (lo + hi) >> 1;
+              const uint32_t v = (uint32_t)__shfl((int)x, mid & (kWave - 1));
+              if (lo < hi) {
+                if (v < x) lo = mid + 1;
+                else hi = mid;
+              }
+            }
+            const int pos = l < c ? l + (lo - c) : (l - c) + lo;
+            key = (uint32_t)__builtin_amdgcn_ds_permute(pos * 4, (int)x);
+            t += c;
+          } else {
+            mine = l == t ? (int32_t)(k0 & ((1u << kNarrowBinBits) - 1)) : mine;
+            const int p = __popcll(below) - 1;  // lanes 1.. below nk
+            const uint32_t nxt = wave_next_u32(key);
+            key = l < p ? nxt : (l == p ? nk : key);
+            t += 1;
+          }
         }
         if (l < cnt) bin_of[(uint32_t)item] = mine;
       }
