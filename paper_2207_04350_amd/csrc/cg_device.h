@@ -438,11 +438,15 @@ constexpr int kIndLocalCap = 1024;
 constexpr int kIndSmallBlock = 64;
 constexpr int kIndSmallCap = 256;
 
+// lidx (the local number of each read) is written for every component when
+// lidx_always, else only for components above CAP reads (the ones whose
+// neighbours are then numbered through it instead of the sorted block)
 template <int BLOCK, int CAP>
 __device__ __forceinline__ void sort_component_block(int q, int st,
                                                      const int32_t *__restrict__ members,
                                                      int32_t *__restrict__ perm,
-                                                     int32_t *__restrict__ lidx, int32_t *a) {
+                                                     int32_t *__restrict__ lidx, int32_t *a,
+                                                     bool lidx_always = true) {
   if (q <= CAP) {
     int N2 = 1;
     while (N2 < q) N2 <<= 1;
@@ -466,7 +470,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
     for (int i = threadIdx.x; i < q; i += BLOCK) {
       const int32_t v = a[i];
       perm[st + i] = v;
-      lidx[v] = st + i;
+      if (lidx_always) lidx[v] = st + i;
     }
   } else {
     // large component: the rank of a read is the number of smaller ids in
@@ -496,7 +500,7 @@ __device__ __forceinline__ void induce_component(
     int32_t *__restrict__ perm, int32_t *__restrict__ lidx, int32_t *__restrict__ loc_row_ptr,
     int32_t *__restrict__ loc_col, int32_t *__restrict__ loc_eid, int32_t *a,
     int32_t *sh_scan) {
-  sort_component_block<BLOCK, CAP>(q, st, members, perm, lidx, a);  // ends with a barrier
+  sort_component_block<BLOCK, CAP>(q, st, members, perm, lidx, a, false);  // ends with a barrier
   const bool in_lds = q <= CAP;
   int carry = 0;
   for (int base = 0; base < q; base += BLOCK) {
