@@ -171,3 +171,23 @@ def test_batch_512_graphs(cg):
         assert bad == [], (i, bad)
     b.close()
     ctx.close()
+
+
+def test_batch_lpt_equal_runs(cg):
+    """Runs of equal read counts in the batched LPT (rounds with at most 64
+    bins), in LDS and beyond it (more than 2048 components)."""
+    import torch
+    rng = np.random.default_rng(9)
+    graphs = [_chain_graph(rng, [int(x) for x in rng.permutation(
+        [6] * 60 + [3] * 400 + [2] * 900)]) for _ in range(3)]
+    graphs.append(_chain_graph(rng, [int(x) for x in rng.permutation([4] * 300 + [2] * 2500)]))
+    params = [(P, 2, "reads") for P in (1, 7, 64, 33)]
+    wants = [oracle.run(g, P=P, min_reads=mr, weight=w) for g, (P, mr, w) in zip(graphs, params)]
+    _say("batch equal runs", [g.n for g in graphs])
+    ctx, dgs, outs, b = _make(cg, graphs, params)
+    b.run()
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    _check_all(cg, graphs, params, outs, wants, "equal runs")
+    b.close()
+    ctx.close()

@@ -149,6 +149,17 @@ def test_many_components_and_bins(cg):
         check(cg, g2, P, 2, name="windows-P%d" % P)  # windowed LPT with merges
 
 
+def test_lpt_equal_runs(cg):
+    """Long runs of components with equal read counts: with at most 64 bins
+    the LPT places such runs in rounds; the partition must stay the one the
+    oracle's component-by-component LPT gives."""
+    rng = np.random.default_rng(8)
+    sizes = [9] * 40 + [5] * 300 + [4] * 500 + [3] * 7 + [2] * 1200
+    g = _chain_graph(rng, [int(x) for x in rng.permutation(sizes)])
+    for P in (1, 7, 33, 64):
+        check(cg, g, P, 2, name="equal-runs-P%d" % P)
+
+
 def test_deterministic(cg):
     g = synth.config_graph(2)
     P = g.meta["P"]
