@@ -1050,6 +1050,11 @@ struct cg_batch {
   bool any_single;  // a job with min_reads <= 1 (one-read components eligible)
   bool any_bases;   // a job partitioned by bases weights
   int64_t chunk_slots;  // upper bound on the copy chunks of the batch
+  // workgroups of each per-component pass that fit on the device at once:
+  // their grids stay within it, so every workgroup of the snake order runs
+  // from the start (a workgroup that waits for a free slot starts its whole
+  // share late)
+  int res_induce_small, res_induce, res_walk_small, res_walk;
   cg_batch_params prm;
   BatchDev dev;
   char *mem;
@@ -1193,6 +1198,24 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     b->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
   }
   b->prm = prm;
+  {
+    int dev = 0, cus = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k1, kb_induce_small, kIndSmallBlock, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k2, kb_induce, kIndBlock, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k3, kb_walk_small, kWalkSmallBlock, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k4, kb_walk, kWalkBlock, 0) != hipSuccess) {
+      delete b;
+      return set_error(CG_EHIP, "occupancy query failed");
+    }
+    b->res_induce_small = k1 * cus;
+    b->res_induce = k2 * cus;
+    b->res_walk_small = k3 * cus;
+    b->res_walk = k4 * cus;
+  }
   b->mem_bytes = at;
   b->mem = nullptr;
   b->graph = nullptr;
@@ -1318,10 +1341,11 @@ int cg_batch_run(cg_batch *b, void *stream) {
     else if (T == 512) launch_vertex_fill<512>(b, st);
     else launch_vertex_fill<1024>(b, st);
   }
-  CG_LAUNCH(ctx, kb_induce_small, dim3(4 * PB), dim3(kIndSmallBlock), st, B);
-  CG_LAUNCH(ctx, kb_induce, dim3(PB), dim3(kIndBlock), st, B);
-  CG_LAUNCH(ctx, kb_walk_small, dim3(4 * PB), dim3(kWalkSmallBlock), st, B);
-  CG_LAUNCH(ctx, kb_walk, dim3(PB), dim3(kWalkBlock), st, B);
+  auto capped = [](int want, int fit) { return dim3((unsigned)(fit > 0 && fit < want ? fit : want)); };
+  CG_LAUNCH(ctx, kb_induce_small, capped(4 * PB, b->res_induce_small), dim3(kIndSmallBlock), st, B);
+  CG_LAUNCH(ctx, kb_induce, capped(PB, b->res_induce), dim3(kIndBlock), st, B);
+  CG_LAUNCH(ctx, kb_walk_small, capped(4 * PB, b->res_walk_small), dim3(kWalkSmallBlock), st, B);
+  CG_LAUNCH(ctx, kb_walk, capped(PB, b->res_walk), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);
   // one wave per copy chunk slot: the hardware hands chunks to waves as
   // slots free up (a persistent grid with a fixed share per wave left a
