@@ -132,11 +132,16 @@ def host_info():
             "cpu_model": model}
 
 
-def _pool_worker(idx, Ps, barrier, q):
+def _pool_worker(src, idx, Ps, barrier, q):
     import oracle
     import synth
-    # this worker's graphs of the batched workload, regenerated from their seeds
-    gs = synth.batch_graphs(512, only=idx)
+    # this worker's graphs, regenerated from their seeds: graphs idx of the
+    # batched workload, or requests idx of the serving pool of src[1]
+    if src[0] == "batch":
+        gs = synth.batch_graphs(512, only=idx)
+    else:
+        recipes = synth.request_params(src[1])
+        gs = [synth.simulate(**recipes[i]) for i in idx]
     barrier.wait()
     t0 = time.perf_counter()
     bases, busy = 0, 0.0
@@ -147,24 +152,29 @@ def _pool_worker(idx, Ps, barrier, q):
     q.put((bases, time.perf_counter() - t0, len(gs), busy))
 
 
-def cpu_pool_baseline(graphs, Ps, workers):
+def cpu_pool_baseline(graphs, Ps, workers, src=("batch", 512)):
     """The single-threaded oracle in `workers` processes, one graph at a time
     per process (graph-level parallelism only); graphs go to workers by LPT on
     their read counts.  Wall time runs from a barrier all workers reach after
-    building their inputs to the last worker's end."""
+    building their inputs to the last worker's end.  src names where the
+    workers regenerate the graphs from: ("batch", 512) for the batched
+    workload (graph k is the generator's graph of its name), ("request", n)
+    for the serving pool of n requests (graph k is request k)."""
     import multiprocessing as mp
     mpc = mp.get_context("spawn")
     load = [0] * workers
     part = [[] for _ in range(workers)]
     # graph k of the list is graph ids[k] of the batched workload's generator
-    ids = [int(g.meta["name"].rsplit("-", 1)[1]) for g in graphs]
+    ids = [int(g.meta["name"].rsplit("-", 1)[1]) for g in graphs] if src[0] == "batch" \
+        else list(range(len(graphs)))
     for i in sorted(range(len(graphs)), key=lambda i: (-graphs[i].n, i)):
         w = min(range(workers), key=lambda w: (load[w], w))
         part[w].append(i)
         load[w] += graphs[i].n
     barrier, q = mpc.Barrier(workers + 1), mpc.Queue()
     procs = [mpc.Process(target=_pool_worker,
-                         args=([ids[i] for i in part[w]], [Ps[i] for i in part[w]], barrier, q))
+                         args=(src, [ids[i] for i in part[w]], [Ps[i] for i in part[w]], barrier,
+                               q))
              for w in range(workers) if part[w]]
     barrier = barrier if len(procs) == workers else None
     if barrier is None:
@@ -203,7 +213,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int,
                     default=min(16, len(os.sched_getaffinity(0))),
-                    help="processes of the oracle pool baseline (batched workload)")
+                    help="processes of the oracle pool baseline (batched and serving workloads)")
     ap.add_argument("--shape", default="",
                     help="vertex_tile,copy_block,persist_blocks of the batched form (skips tuning)")
     ap.add_argument("--skip-plain", action="store_true",
@@ -620,7 +630,9 @@ def serve_bench(args):
     synthetic request graphs (genome 1-100 Mbp log-uniform, 15-30x, reads
     LN(12k, 4k), 1-2% branch edges, P = 64), a seeded Poisson stream sampling
     the pool at the rate that keeps the GPU busy about 80% of the time, and
-    p50 / p99 latency from arrival to the result in host memory."""
+    p50 / p99 latency from arrival to the result in host memory.  Measured
+    with the pool resident in HBM (the reported value) and with every
+    request uploading its graph (with_upload)."""
     import numpy as np
     import torch
 
@@ -635,74 +647,121 @@ def serve_bench(args):
     log("request pool: %d graphs (%.1f M reads, %.1f GB packed reads) in %.1fs" % (
         n_pool, sum(h.n for h in pool) / 1e6, sum(h.seq_words for h in pool) * 4 / 1e9,
         time.time() - t0))
-    srv = serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64, slots=args.slots)
+    def measure(resident):
+        """Alone service times, then the arrival rate for a device-busy
+        fraction of about 0.8 and the latency and throughput of that stream.
+        resident: the pool is uploaded once and requests hold only outputs;
+        else every request uploads its graph when admitted."""
+        mk = lambda slots: serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64,
+                                        slots=slots)
 
-    def stream(n, rate, seed, offset=0):
-        r = np.random.default_rng(seed)
-        pick = r.integers(0, n_pool, size=n)
-        arr = serve.poisson_arrivals(n, rate, seed + 1) if rate else np.zeros(n)
-        return [serve.Request(offset + i, pool[k], 64, 2, float(t))
-                for i, (k, t) in enumerate(zip(pick, arr))]
+        def stream(n, rate, seed):
+            r = np.random.default_rng(seed)
+            pick = r.integers(0, n_pool, size=n)
+            arr = serve.poisson_arrivals(n, rate, seed + 1) if rate else np.zeros(n)
+            return [serve.Request(i, pool[k], 64, 2, float(t), resident=resident)
+                    for i, (k, t) in enumerate(zip(pick, arr))]
 
-    # service time of each pool graph alone (also the warm-up)
-    srv1 = serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64, slots=1)
-    alone, _, _ = srv1.run([serve.Request(i, h, 64, 2, 0.0) for i, h in enumerate(pool)])
-    srv1.close()
-    svc = np.array([q.t_done - q.t_admit for q in alone])
-    rate = 0.8 / svc.mean()
-    log("alone: mean service %.2f ms -> arrival rate %.1f requests/s" % (1e3 * svc.mean(), rate))
-    n_warm = max(args.requests // 10, 10)
-    # bisection on the arrival rate for a device-busy fraction of about 0.8
-    # (proportional steps until the target is bracketed); the run closest to
-    # it is the one reported
-    lo = hi = None
-    best = None
-    for attempt in range(5):
-        reqs, span, peak = srv.run(stream(n_warm + args.requests, rate, 20220709 + attempt))
-        busy = serve.busy_fraction(reqs, span)
-        log("rate %.1f/s: busy %.2f over %.2fs" % (rate, busy, span))
-        if best is None or abs(busy - 0.8) < abs(best[0] - 0.8):
-            best = (busy, rate, reqs, span, peak)
-        if abs(busy - 0.8) <= 0.03:
-            break
-        if busy < 0.8:
-            lo = rate
-        else:
-            hi = rate
-        rate = 0.5 * (lo + hi) if lo is not None and hi is not None \
-            else rate * 0.8 / max(busy, 0.05)
-    busy, rate, reqs, span, peak = best
-    meas = sorted(reqs, key=lambda q: q.rid)[n_warm:]
-    lat = np.array([q.t_done - q.arrival for q in meas])
-    bases = sum(int(q.result["len"].sum()) for q in meas)
-    t_span = max(q.t_done for q in meas) - min(q.arrival for q in meas)
-    bad = sum(q.result["status"] != 0 for q in meas)
-    srv.close()
+        # service time of each pool graph alone (also the warm-up)
+        srv1 = mk(1)
+        if resident:
+            for h in pool:
+                srv1.make_resident(h)
+        alone, _, _ = srv1.run([serve.Request(i, h, 64, 2, 0.0, resident=resident)
+                                for i, h in enumerate(pool)])
+        srv1.close()
+        del srv1
+        svc = np.array([q.t_done - q.t_admit for q in alone])
+        rate = 0.8 / svc.mean()
+        tag = "resident" if resident else "upload"
+        log("%s, alone: mean service %.2f ms -> arrival rate %.1f requests/s"
+            % (tag, 1e3 * svc.mean(), rate))
+        srv = mk(args.slots)
+        if resident:
+            for h in pool:
+                srv.make_resident(h)
+        n_warm = max(args.requests // 10, 10)
+        # bisection on the arrival rate for a device-busy fraction of about
+        # 0.8 (proportional steps until the target is bracketed); the run
+        # closest to it is the one reported
+        lo = hi = None
+        best = None
+        for attempt in range(5):
+            reqs, span, peak = srv.run(stream(n_warm + args.requests, rate, 20220709 + attempt))
+            busy = serve.busy_fraction(reqs, span)
+            log("%s, rate %.1f/s: busy %.2f over %.2fs" % (tag, rate, busy, span))
+            if best is None or abs(busy - 0.8) < abs(best[0] - 0.8):
+                best = (busy, rate, reqs, span, peak)
+            if abs(busy - 0.8) <= 0.03:
+                break
+            if busy < 0.8:
+                lo = rate
+            else:
+                hi = rate
+            rate = 0.5 * (lo + hi) if lo is not None and hi is not None \
+                else rate * 0.8 / max(busy, 0.05)
+        busy, rate, reqs, span, peak = best
+        meas = sorted(reqs, key=lambda q: q.rid)[n_warm:]
+        lat = np.array([q.t_done - q.arrival for q in meas])
+        bases = sum(int(q.result["len"].sum()) for q in meas)
+        t_span = max(q.t_done for q in meas) - min(q.arrival for q in meas)
+        bad = sum(q.result["status"] != 0 for q in meas)
+        out = {"value": bases / t_span, "unit": "contig bases/s",
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "busy_fraction": busy, "rate_per_s": rate, "requests": len(meas),
+               "warmup_requests": n_warm, "slots": args.slots, "budget_bytes": srv.budget,
+               "peak_admitted_bytes": int(peak), "device_status_errors": int(bad),
+               "alone_service_ms": {"mean": float(svc.mean() * 1e3),
+                                    "max": float(svc.max() * 1e3)}}
+        srv.close()
+        return out
+
+    upload = measure(False)
+    res = measure(True)
     result = {
         "metric": "contig bases/s (serving, continuous batching)",
-        "value": bases / t_span,
+        "value": res["value"],
         "unit": "contig bases/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "busy_fraction": busy,
-        "rate_per_s": rate,
-        "requests": len(meas),
-        "warmup_requests": n_warm,
-        "slots": args.slots,
-        "budget_bytes": srv.budget,
-        "peak_admitted_bytes": int(peak),
-        "device_status_errors": int(bad),
-        "alone_service_ms": {"mean": float(svc.mean() * 1e3), "max": float(svc.max() * 1e3)},
+    }
+    result.update({k: v for k, v in res.items() if k not in ("value", "unit")})
+    result.update({
+        "with_upload": upload,
         "dtype": "int32",
         "data": "synthetic (seeded simulated genomes and reads; exact reduced string graphs)",
         "config": {"workload": "serving: Poisson stream over a pool of %d request graphs (genome "
                                "1-100 Mbp log-uniform, 15-30x, reads LN(12k, 4k), 1-2%% branch "
                                "edges, P = 64)" % n_pool,
-                   "latency": "arrival to contigs in pinned host memory (upload, all five "
-                              "steps, download included)"},
-    }
+                   "resident": "the pool's graphs are resident in HBM (uploaded once, before "
+                               "the stream); each request allocates its outputs, runs the five "
+                               "steps and downloads its contigs",
+                   "latency": "arrival to contigs in pinned host memory (all five steps and "
+                              "the download; with_upload: the graph's upload as well)"},
+    })
+    if not args.no_cpu:
+        import oracle
+        graphs = [h.graph for h in pool]
+        spent, cbases, passes = 0.0, 0, 0
+        while spent < min(MIN_CPU_SECONDS, args.cpu_seconds):
+            for g in graphs:
+                tm = {}
+                cbases += int(oracle.run(g, P=64, min_reads=2, timings=tm)["contigs"]["len"].sum())
+                spent += tm["total"]
+            passes += 1
+        result["cpu_baseline"] = {
+            "value": cbases / spent, "unit": "contig bases/s", "cores": 1, "kind": "oracle",
+            "sample": "%d pass(es) over the %d request graphs of the pool, single-threaded C "
+                      "oracle, whole path (no uploads)" % (passes, n_pool),
+            "seconds": spent}
+        result["host"] = host_info()
+        if args.cpu_workers > 1:
+            result["cpu_baseline_pool"] = cpu_pool_baseline(graphs, [64] * n_pool,
+                                                            args.cpu_workers,
+                                                            src=("request", n_pool))
+            log("oracle pool: %d processes, %.2fs" % (args.cpu_workers,
+                                                      result["cpu_baseline_pool"]["seconds"]))
     print(json.dumps(result), flush=True)
 
 

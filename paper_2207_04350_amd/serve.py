@@ -5,10 +5,13 @@ when a slot (a cg context with its own stream) is free and its device
 footprint fits in the HBM budget next to the requests already on the device;
 admitted requests run concurrently on their slots' streams, so a request that
 arrives while others are on the GPU starts as soon as a slot and memory free
-up.  Each request's graph is uploaded from pinned host memory, all five steps
-run on the device, and the contigs come back to pinned host memory: first
-the device-side counts, then exactly the records and bases they name.
-Latency is measured from arrival to the moment the result is in host memory.
+up.  A request's graph is either uploaded from pinned host memory when the
+request is admitted, or already resident: graphs made resident once
+(`Server.make_resident`) stay in HBM for the life of the server, charged to
+the budget, and requests on them hold only their outputs.  All five steps run
+on the device, and the contigs come back to pinned host memory: first the
+device-side counts, then exactly the records and bases they name.  Latency is
+measured from arrival to the moment the result is in host memory.
 
 The admission core (`Admission`) is plain host logic; `Server` drives it with
 real device work.  Every step of the path runs in libcg's kernels.
@@ -46,11 +49,14 @@ def output_bytes(n, P, cap_words):
             + 8 + 4 + 8 + 8)
 
 
-def request_footprint(g, P):
+def request_footprint(g, P, resident=False):
     """HBM a request holds while it is admitted (its slot's scratch is not
-    counted: slots own theirs for the life of the server)."""
-    return (graph_bytes(g.n, g.m, g.seq.shape[0], getattr(g, "pre", None) is not None)
-            + output_bytes(g.n, P, g.seq.shape[0] + g.n))
+    counted: slots own theirs for the life of the server; nor is a resident
+    graph, charged once when it was made resident)."""
+    out = output_bytes(g.n, P, g.seq.shape[0] + g.n)
+    if resident:
+        return out
+    return graph_bytes(g.n, g.m, g.seq.shape[0], getattr(g, "pre", None) is not None) + out
 
 
 # ---------------------------------------------------------------------------
@@ -120,14 +126,16 @@ class HostGraph:
 
 
 class Request:
-    """One contig-generation request: a graph in pinned host memory, its
+    """One contig-generation request: a graph in pinned host memory (uploaded
+    on admission), or one the server holds resident (`resident=True`), its
     parameters and its arrival time (seconds from the start of the run)."""
 
-    def __init__(self, rid, host, P, min_reads=2, arrival=0.0):
+    def __init__(self, rid, host, P, min_reads=2, arrival=0.0, resident=False):
         self.rid, self.host, self.P, self.min_reads = rid, host, int(P), int(min_reads)
         self.graph = host.graph
         self.arrival = float(arrival)
-        self.footprint = request_footprint(self.graph, self.P)
+        self.resident = bool(resident)
+        self.footprint = request_footprint(self.graph, self.P, self.resident)
         self.t_admit = self.t_done = None
         self.result = None
 
@@ -135,13 +143,15 @@ class Request:
 class _Resident:
     """A request's device state while it is admitted."""
 
-    def __init__(self, req, slot, stream, device):
+    def __init__(self, req, slot, stream, device, dg=None):
         import torch
         self.req, self.slot, self.stream = req, slot, stream
         g = req.graph
         with torch.cuda.stream(stream):
-            d = {k: v.to(device, non_blocking=True) for k, v in req.host.t.items()}
-            self.dg = cg.DeviceGraph.from_tensors(g.n, g.m, d, int(g.seq.shape[0]), device)
+            if dg is None:
+                d = {k: v.to(device, non_blocking=True) for k, v in req.host.t.items()}
+                dg = cg.DeviceGraph.from_tensors(g.n, g.m, d, int(g.seq.shape[0]), device)
+            self.dg = dg
             self.out = cg.Outputs(g.n, req.P, int(g.seq.shape[0]) + g.n, device)
             self.counts = torch.empty(4, dtype=torch.int64, pin_memory=True)
         self.phase = 0
@@ -168,11 +178,30 @@ class Server:
             budget = total - reserve - sum(c.scratch_bytes for c in self.ctxs)
         self.budget = int(budget)
         self.keep_outputs = keep_outputs
+        self.resident = {}  # id(HostGraph) -> DeviceGraph
+
+    def make_resident(self, host):
+        """Upload host (a HostGraph) once; requests with resident=True on it
+        then run on this copy.  Its bytes leave the budget for good."""
+        import torch
+        if id(host) in self.resident:
+            return
+        g = host.graph
+        fp = graph_bytes(g.n, g.m, g.seq.shape[0], getattr(g, "pre", None) is not None)
+        if fp > self.budget:
+            raise ValueError("graph needs %d bytes, above the %d-byte budget left" % (fp,
+                                                                                     self.budget))
+        d = {k: v.to(self.device) for k, v in host.t.items()}
+        self.resident[id(host)] = cg.DeviceGraph.from_tensors(g.n, g.m, d, int(g.seq.shape[0]),
+                                                              self.device)
+        torch.cuda.synchronize(self.device)
+        self.budget -= fp
 
     def close(self):
         for c in self.ctxs:
             c.close()
         self.ctxs = []
+        self.resident = {}
 
     # -- per-request device work ------------------------------------------
 
@@ -181,7 +210,12 @@ class Server:
         g = req.graph
         if g.n > self.max_n or g.m > self.max_m or req.P > self.max_P:
             raise ValueError("request %r exceeds the slot size" % (req.rid,))
-        r = _Resident(req, slot, self.streams[slot], self.device)
+        dg = None
+        if req.resident:
+            dg = self.resident.get(id(req.host))
+            if dg is None:
+                raise ValueError("request %r names a graph that is not resident" % (req.rid,))
+        r = _Resident(req, slot, self.streams[slot], self.device, dg)
         s = r.stream
         with torch.cuda.stream(s):
             cg.run_path(self.ctxs[slot], r.dg, r.out, req.P, req.min_reads, s)

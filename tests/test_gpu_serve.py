@@ -83,3 +83,32 @@ def test_budget_is_never_exceeded(pool):
     assert peak <= budget
     assert all(q.result is not None and q.result["status"] == 0 for q in reqs)
     assert all(q.t_done >= q.t_admit >= q.arrival for q in reqs)
+
+
+def test_resident_graphs_alone_and_mix(pool):
+    """Graphs made resident once: requests on them (outputs only) give the
+    same bytes alone and in a mix as requests that upload their graph, and
+    the budget charged for the resident copies comes off the total."""
+    from paper_2207_04350_amd import serve
+    rng = np.random.default_rng(10)
+    order = list(range(len(pool))) + list(rng.integers(0, len(pool), 10))
+
+    def reqs(arrivals, resident):
+        return [serve.Request(i, pool[k], 64 if pool[k].n > 5000 else 8, 2, float(t),
+                              resident=resident)
+                for i, (k, t) in enumerate(zip(order, arrivals))]
+
+    srv = _server(serve, pool, slots=1)
+    up, _, _ = srv.run(reqs([0.0] * len(order), False))
+    srv.close()
+    _say("resident mix", len(order))
+    srv = _server(serve, pool, slots=4)
+    before = srv.budget
+    for h in pool:
+        srv.make_resident(h)
+    assert srv.budget == before - sum(serve.graph_bytes(h.n, h.m, h.seq_words) for h in pool)
+    mix, span, peak = srv.run(reqs(serve.poisson_arrivals(len(order), 2000.0, 5), True))
+    srv.close()
+    assert peak <= srv.budget
+    for qa, qm in zip(sorted(up, key=lambda q: q.rid), sorted(mix, key=lambda q: q.rid)):
+        assert _same(qa.result, qm.result), qa.rid

@@ -58,6 +58,8 @@ def test_footprint_matches_the_allocations():
     assert serve.graph_bytes(g.n, g.m, g.seq.shape[0]) == gb
     assert serve.output_bytes(g.n, P, int(g.seq.shape[0]) + g.n) == ob
     assert serve.request_footprint(g, P) == gb + ob
+    # a request on a resident graph holds its outputs only
+    assert serve.request_footprint(g, P, resident=True) == ob
 
 
 def test_busy_fraction_and_arrivals():
