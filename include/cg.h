@@ -340,8 +340,11 @@ typedef struct {
  * never results. */
 typedef struct {
   int32_t vertex_tile;     /* vertices per workgroup in vertex passes: 256 (default), 512, 1024 */
-  int32_t copy_block;      /* threads per workgroup of the base copy, multiple of 64 (256) */
-  int32_t persist_blocks;  /* workgroups of the persistent passes (4 per compute unit) */
+  int32_t copy_block;      /* threads per workgroup of the base copy, multiple of 64 (256);
+                              the copy runs one wave per chunk of 32 pieces */
+  int32_t persist_blocks;  /* workgroups of the persistent per-component passes (4 per
+                              compute unit; the one-wave passes take 4x as many), each
+                              capped at the workgroups that fit on the device at once */
 } cg_batch_params;
 
 typedef struct cg_batch cg_batch;
