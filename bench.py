@@ -403,6 +403,9 @@ def main():
     # rows, flags written, labels written (each array once)
     maskcc_bytes = 4 * (st["N"] + 1) + 4 * st["m_nb"] + st["N"] + 4 * st["N"]
 
+    mc = [profiled_traffic(k) for k in ("kb_mask_list", "kb_cc_prep", "kb_cc_local")]
+    maskcc_traffic = sum(mc) if all(t is not None for t in mc) and args.workload == "batch" else None
+
     def maskcc(ph):
         ms = ph["mask"] + ph["components"]
         return {"ms": ms, "edges_per_s": st["m"] / (ms * 1e-3),
@@ -476,7 +479,13 @@ def main():
                     if maskcc_ms else None,
                     "cold_median": maskcc(cold_ph), "warm_median": maskcc(warm_ph),
                     "kernels": "kb_mask_list + kb_cc_prep + kb_cc_local (the last also builds the component "
-                               "table and groups members)"},
+                               "table and groups members)",
+                    # what the phase's kernels move in all (the calibrated
+                    # counters of the committed profile): random lines and the
+                    # arrays the later steps need, far above the fused minimum
+                    "counter_traffic_bytes": maskcc_traffic,
+                    "counter_traffic_frac": maskcc_traffic / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                    if maskcc_traffic and maskcc_ms else None},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic(kname(dom).replace("k_", "kb_", 1))
