@@ -215,8 +215,7 @@ __device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
 // Bin keys are (load << 16) | bin: ascending key order is ascending
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
-constexpr int kNarrowBinBits = 6;  // bins of the 32-bit keys (at most 64)
-constexpr int kLptRoundMin = 6;    // equal items taken as one round from this many
+constexpr int kLptRoundMin = 6;  // equal items taken as one round from this many
 
 // With comp_kind and comp_estart given, it also writes each component's
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
@@ -271,24 +270,31 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   // window is merged back into the sorted bin list.
   const int W = P < kWave ? P : kWave;
   const bool single_window = P <= kWave;
+  // Narrow keys: with kb bits for the bin index (2^kb >= P) and a total
+  // weight below 2^(32 - kb) - 1, a bin's key (load << kb) | bin fits 32 bits
+  // below the padding value 0xFFFFFFFF, and a step needs about 12 vector
+  // instructions instead of 17.  Same order, same choices.  The bin lists
+  // hold narrow keys zero-extended, so the window merge is unchanged.
+  int kb = 0;
+  while ((1 << kb) < P) ++kb;
+  const bool narrow = kb <= 16 && s_wsum + 1 < (1ull << (32 - kb));
   int i0 = 0;
-  // Narrow keys: with at most 64 bins and a total weight below 2^26, a bin's
-  // key (load << 6) | bin fits 32 bits, and a step needs half the vector
-  // instructions of the 64-bit one.  Same order, same choices.
-  if (single_window && s_wsum < (1ull << (32 - kNarrowBinBits))) {
-    if (tid < kWave) {
+  while (i0 < nc) {
+    const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
+    if (tid < kWave && narrow) {
       const int l = tid;
-      uint32_t key = l < W ? (uint32_t)binA[l] : 0xFFFFFFFFu;  // loads are 0: key = bin
-      for (int base = 0; base < nc; base += kWave) {
-        const int cnt = __builtin_amdgcn_readfirstlane(nc - base < kWave ? nc - base : kWave);
-        const uint64_t item = l < cnt ? keys[base + l] : 0ull;
+      const uint32_t bmask = (1u << kb) - 1u;
+      uint32_t key = l < W ? (uint32_t)binA[l] : 0xFFFFFFFFu;
+      for (int base = 0; base < T; base += kWave) {
+        const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
+        const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
         int32_t mine = 0;  // bin of item l
         const uint32_t iw = (uint32_t)(item >> 32);
         for (int t = 0; t < cnt;) {
           const uint32_t wt = (uint32_t)__builtin_amdgcn_readlane((int)iw, t);
           const uint32_t q = 0xFFFFFFFFu - wt;
           const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, 0);
-          const uint32_t nk = k0 + (q << kNarrowBinBits);
+          const uint32_t nk = k0 + (q << kb);
           const uint64_t below = __ballot(key < nk);  // lane 0 and the lanes below nk
           // items t, t+1, ... of the same weight (within this batch)
           const uint64_t same = __ballot(l < cnt && iw == wt) >> t;
@@ -301,8 +307,8 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
             // them one after another); the raised keys of lanes 0..c-1 and
             // the keys of lanes c.. are two sorted runs, merged by rank
             const uint32_t src = (uint32_t)__shfl((int)key, (l - t) & (kWave - 1));
-            if (l >= t && l < t + c) mine = (int32_t)(src & ((1u << kNarrowBinBits) - 1));
-            const uint32_t x = l < c ? key + (q << kNarrowBinBits) : key;
+            if (l >= t && l < t + c) mine = (int32_t)(src & bmask);
+            const uint32_t x = l < c ? key + (q << kb) : key;
             // rank in the other run: lanes 0..c-1 search lanes c..63, the
             // others lanes 0..c-1 (every lane runs every step)
             int lo = l < c ? c : 0, hi = l < c ? kWave : c;
@@ -318,7 +324,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
             key = (uint32_t)__builtin_amdgcn_ds_permute(pos * 4, (int)x);
             t += c;
           } else {
-            mine = l == t ? (int32_t)(k0 & ((1u << kNarrowBinBits) - 1)) : mine;
+            mine = l == t ? (int32_t)(k0 & bmask) : mine;
             const int p = __popcll(below) - 1;  // lanes 1.. below nk
             const uint32_t nxt = wave_next_u32(key);
             key = l < p ? nxt : (l == p ? nk : key);
@@ -327,16 +333,8 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         }
         if (l < cnt) bin_of[(uint32_t)item] = mine;
       }
-      if (l < W)
-        binA[l] = ((uint64_t)(key >> kNarrowBinBits) << kBinBits) |
-                  (key & ((1u << kNarrowBinBits) - 1));
-    }
-    __syncthreads();
-    i0 = nc;
-  }
-  while (i0 < nc) {
-    const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
-    if (tid < kWave) {
+      if (l < W) win[l] = key;
+    } else if (tid < kWave) {
       const int l = tid;
       uint64_t key = l < W ? binA[l] : ~0ull;
       for (int base = 0; base < T; base += kWave) {
@@ -386,9 +384,12 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     __syncthreads();
     i0 += T;
   }
-  for (int b = tid; b < P; b += blockDim.x) {
-    const uint64_t k = binA[b];
-    bin_load[k & ((1u << kBinBits) - 1)] = k >> kBinBits;
+  {
+    const int bb = narrow ? kb : kBinBits;
+    for (int b = tid; b < P; b += blockDim.x) {
+      const uint64_t k = binA[b];
+      bin_load[k & ((1ull << bb) - 1)] = k >> bb;
+    }
   }
 
   // 3. (bin, label) order, read offsets and the reads of each bin
