@@ -89,6 +89,9 @@ def test_config_full(cg, cfg):
 def test_config3_full(cg):
     g = synth.config_graph(3)
     check(cg, g, g.meta["P"], 2, name="config3")
+    # the most bins there can be: 231k contig reads need more than the 16 load
+    # bits a 32-bit key leaves, so the LPT takes its 64-bit keys
+    check(cg, g, 65536, 2, name="config3-P65536")
 
 
 def test_batch_and_request_graphs(cg):
