@@ -45,6 +45,9 @@ struct BJob {
   int32_t *conn_map;           // [n] slot of a listed read in conn_list
   int32_t vt_first, vt_count;  // the job's vertex tiles (covering 0..n)
   int32_t mt_first, mt_count;  // the job's mask tiles
+  int32_t external;            // 1: the job runs through the single-graph kernels before the
+                               // batched launches, which then leave it alone
+  int32_t pad_;
 };
 
 // A job's descriptor by value.  The job table is read-only while a launch
@@ -289,6 +292,8 @@ constexpr int kCcBlock = 1024;
 constexpr int kCcCap = 16384;
 constexpr int kCcPer = kCcCap / kCcBlock;
 constexpr int kCcTileCap = 1024;
+// jobs with more directed entries go through the single-graph kernels
+constexpr int64_t kExternalEntries = 2 * (int64_t)kCcCap;
 constexpr int32_t kNotEligible = -(1 << 30);
 
 __device__ __forceinline__ int lds_find(int32_t *par, int x) {
@@ -328,6 +333,7 @@ __global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
   __shared__ int64_t sh64[kCcBlock / kWave + 1];
   const int j = ld_const(B.job_order, blockIdx.x);
   const BJob J = job_at(B.jobs, j);
+  if (J.external) return;
   const int nt = J.mt_count;
   const int tid = threadIdx.x;
   const bool table = J.min_reads >= 2;
@@ -614,7 +620,7 @@ __global__ __launch_bounds__(T) void kb_tilecount(BatchDev B) {
   __shared__ int32_t sh[T / kWave];
   const int t = blockIdx.x;
   const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2) return;  // table and members come from the components pass
+  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   uint32_t c = 0;
   const bool e = eligible<T>(J, v, &c);
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
   __shared__ int32_t sh[T / kWave + 1];
   const int t = blockIdx.x;
   const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2) return;  // table and members come from the components pass
+  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
   int32_t before = 0;
   for (int i = J.vt_first + (int)threadIdx.x; i < t; i += T) before += B.tile_cnt[i];
   before = wave_sum(before);
@@ -668,7 +674,7 @@ template <int T>
 __global__ __launch_bounds__(T) void kb_weight(BatchDev B) {
   const int t = blockIdx.x;
   const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.weight != CG_WEIGHT_BASES) return;
+  if (J.weight != CG_WEIGHT_BASES || J.external) return;
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   if (v >= J.g.n) return;
   const int32_t c = J.parts.label_comp[J.label[v]];
@@ -699,36 +705,43 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
   const int P = J.P;
   const int nc = *J.parts.d_n_comp;
   const uint64_t *wts = J.weight == CG_WEIGHT_BASES ? J.s.comp_w : nullptr;
-  int m_e;
-  if (nc <= kBatchSortCap && P <= kBatchBinCap)
-    m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
-                   J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.s.bin_reads,
-                   &B.fixed->status, J.parts.comp_kind, J.s.estart);
-  else
-    m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
-                   J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
-                   J.s.bin_reads, &B.fixed->status, J.parts.comp_kind, J.s.estart);
-  __syncthreads();
-  // bin boundaries: prefix of the reads of each bin
+  const bool ext = J.external != 0;
+  int m_e = 0;
   int64_t carry = 0;
-  for (int base = 0; base < P; base += kBatchLptBlock) {
-    const int b = base + threadIdx.x;
-    const int64_t x = b < P ? (int64_t)__hip_atomic_load(J.s.bin_reads + b, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                            : 0;
-    int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t, kBatchLptBlock>(x, sh, &tot);
-    if (b < P) J.local.bin_vptr[b] = (int32_t)(carry + ex);
-    carry += tot;
+  if (!ext) {
+    if (nc <= kBatchSortCap && P <= kBatchBinCap)
+      m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
+                     J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load, J.s.bin_reads,
+                     &B.fixed->status, J.parts.comp_kind, J.s.estart);
+    else
+      m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, J.s.keys, J.s.aux, J.s.bins, J.s.bins + P,
+                     J.parts.comp_bin, J.parts.comp_rank, J.parts.comp_start, J.parts.bin_load,
+                     J.s.bin_reads, &B.fixed->status, J.parts.comp_kind, J.s.estart);
+    __syncthreads();
+    // bin boundaries: prefix of the reads of each bin
+    for (int base = 0; base < P; base += kBatchLptBlock) {
+      const int b = base + threadIdx.x;
+      const int64_t x = b < P ? (int64_t)__hip_atomic_load(J.s.bin_reads + b, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)
+                              : 0;
+      int64_t tot;
+      const int64_t ex = block_excl_scan<int64_t, kBatchLptBlock>(x, sh, &tot);
+      if (b < P) J.local.bin_vptr[b] = (int32_t)(carry + ex);
+      carry += tot;
+    }
+    for (int c = threadIdx.x; c < nc; c += kBatchLptBlock) J.s.fill[c] = 0;
   }
-  for (int c = threadIdx.x; c < nc; c += kBatchLptBlock) J.s.fill[c] = 0;
   __shared__ int last;
   if (threadIdx.x == 0) {
-    J.local.bin_vptr[P] = (int32_t)carry;
-    J.local.d_sizes[0] = (int32_t)carry;
-    J.local.d_sizes[1] = m_e;
-    J.local.loc_row_ptr[carry] = m_e;
-    B.job_cnt[j] = make_int2(nc, (int32_t)carry);  // dense, for the last workgroup
+    if (!ext) {
+      J.local.bin_vptr[P] = (int32_t)carry;
+      J.local.d_sizes[0] = (int32_t)carry;
+      J.local.d_sizes[1] = m_e;
+      J.local.loc_row_ptr[carry] = m_e;
+    }
+    // dense, for the last workgroup; an external job adds no components or
+    // pieces to the batch-wide queues
+    B.job_cnt[j] = ext ? make_int2(0, 0) : make_int2(nc, (int32_t)carry);
     __threadfence();
     last = atomicAdd(&B.counters[2], 1u) == (unsigned)B.n_jobs - 1;
   }
@@ -882,7 +895,7 @@ template <int T>
 __global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
   const int t = blockIdx.x;
   const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2) return;  // table and members come from the components pass
+  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
   const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
   if (v >= J.g.n) return;
   const int32_t c = J.parts.label_comp[J.label[v]];
@@ -996,6 +1009,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
 __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   const BJob J = job_at(B.jobs, blockIdx.x);
+  if (J.external) return;  // its offsets come from the single-graph assemble step
   const int nc = *J.parts.d_n_comp;
   unsigned long long carry = 0;
   for (int base = 0; base < nc; base += kScanBlock) {
@@ -1055,6 +1069,10 @@ struct cg_batch {
   // from the start (a workgroup that waits for a free slot starts its whole
   // share late)
   int res_induce_small, res_induce, res_walk_small, res_walk;
+  // jobs too large for one workgroup's components pass: they run through the
+  // single-graph kernels (grid-wide) ahead of the batched launches
+  std::vector<cg_job> ext_jobs;
+  std::vector<Scratch> ext_s;
   cg_batch_params prm;
   BatchDev dev;
   char *mem;
@@ -1174,8 +1192,11 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const size_t o_order = take(sizeof(int32_t) * n_jobs);
   int32_t n_mt = 0;
   for (int i = 0; i < n_jobs; ++i) {
+    // a job whose reads of degree 1-2 (about half its entries) would not fit
+    // the components pass's LDS goes through the single-graph kernels
+    hj[i].external = jobs[i].g.m > kExternalEntries ? 1 : 0;
     hj[i].mt_first = n_mt;
-    hj[i].mt_count = (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
+    hj[i].mt_count = hj[i].external ? 0 : (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
     n_mt += hj[i].mt_count;
   }
   const size_t o_mtiles = take(sizeof(MaskTile) * (n_mt > 0 ? n_mt : 1));
@@ -1249,12 +1270,16 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
       // the list and its index live in scratch that later steps reuse
       h.conn_list = (int4 *)h.s.walk;
       h.conn_map = h.s.lidx;
+      if (h.external) {
+        b->ext_jobs.push_back(J);
+        b->ext_s.push_back(h.s);
+      }
     }
     std::vector<MaskTile> mt;
     mt.reserve(n_mt);
     int2 *d_mtcnt = (int2 *)(b->mem + o_mtcnt);
     for (int i = 0; i < n_jobs; ++i)
-      for (int32_t v0 = 0; v0 < jobs[i].g.n; v0 += kMaskTile)
+      for (int32_t v0 = 0; !hj[i].external && v0 < jobs[i].g.n; v0 += kMaskTile)
         mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, jobs[i].flags, jobs[i].label,
                               jobs[i].parts.label_comp, hj[i].conn_list, hj[i].conn_map,
                               d_mtcnt + (int32_t)mt.size(), jobs[i].g.n, v0,
@@ -1316,6 +1341,17 @@ int cg_batch_run(cg_batch *b, void *stream) {
   const BatchDev &B = b->dev;
   const int T = b->prm.vertex_tile;
   const int PB = b->prm.persist_blocks;
+  for (size_t e = 0; e < b->ext_jobs.size(); ++e) {
+    const cg_job &J = b->ext_jobs[e];
+    const Scratch &s = b->ext_s[e];
+    int rc = launch_mask(ctx, J.g, J.flags, J.d_counts, st);
+    if (!rc) rc = launch_components(ctx, J.g, J.flags, J.label, st);
+    if (!rc)
+      rc = launch_partition(ctx, J.g, s, J.flags, J.label, J.P, J.min_reads, J.weight, J.parts, st);
+    if (!rc) rc = launch_induce(ctx, J.g, s, J.flags, J.label, J.parts, J.P, J.local, st);
+    if (!rc) rc = launch_assemble(ctx, J.g, s, J.parts, J.local, J.P, J.contigs, st);
+    if (rc) return rc;
+  }
   if (B.n_mtiles > 0) {
     CG_LAUNCH(ctx, kb_mask_list, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
     CG_LAUNCH(ctx, kb_cc_prep, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);

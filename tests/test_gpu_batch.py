@@ -42,10 +42,17 @@ def _mixed_graphs():
     gs.append(synth.with_alignment_ends(synth.config_graph(1), np.random.default_rng(8), 3))
     ra = np.random.default_rng(18)
     gs += [_random_pre_post(synth.adversarial(ra), ra) for _ in range(6)]
-    # beyond the LDS components pass: with and without one-read components
+    # more than 32768 entries: run through the single-graph kernels inside
+    # the batch, with and without one-read components
     gs.append(_chain_graph(r, [6000, 6000, 5000, 2]))
     gs[-1].meta["min_reads"] = 2
     gs.append(_chain_graph(r, [7000, 5000, 1], cycles=[4000, 600]))
+    gs[-1].meta["min_reads"] = 1
+    # more listed reads than the components pass holds in LDS, but few
+    # entries: the tagged global forest of the batched components pass
+    gs.append(_chain_graph(r, [2] * 9000))
+    gs[-1].meta["min_reads"] = 2
+    gs.append(_chain_graph(r, [2] * 8800 + [3] * 50))
     gs[-1].meta["min_reads"] = 1
     return gs
 
