@@ -354,7 +354,9 @@ typedef struct cg_batch cg_batch;
  * per-job scratch (device memory owned by the batch).  The buffers the jobs
  * point to must stay valid and unmoved while the batch exists.  Runs every
  * step of Algorithm 2 for all jobs with one launch per phase; each job's
- * outputs are identical to the five single-graph calls on that job. */
+ * outputs are identical to the five single-graph calls on that job.  A job
+ * with more than 32768 directed entries is run by the single-graph kernels,
+ * in the same launch sequence ahead of the batched launches. */
 int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
                     const cg_batch_params *params, cg_batch **out);
 
