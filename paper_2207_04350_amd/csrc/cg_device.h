@@ -121,15 +121,98 @@ __device__ __forceinline__ int next_pow2(int x) {
   return p;
 }
 
-// One compare-exchange of a bitonic stage (k, j), j < 64, in registers: x is
-// element i of the array, held by lane i % 64, and its partner i ^ j is held
-// by lane (i % 64) ^ j of the same wave.  Every lane of the wave takes part.
-template <typename K>
-__device__ __forceinline__ K bitonic_lane_step(K x, int i, int j, int k) {
-  const K p = __shfl_xor(x, j);
-  const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+// Exclusive prefix minimum over the lanes of the wave (lane 0 gets
+// 0xFFFFFFFF): row shifts 1, 2, 4, 8 within rows of 16 lanes, then the row
+// broadcasts of lanes 15 and 31 (lanes without a source take the identity).
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_excl_min_u32(uint32_t x) {
+  const int id = -1;  // 0xFFFFFFFF
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x111, 0xF, 0xF, false));  // row_shr:1
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x112, 0xF, 0xF, false));  // row_shr:2
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x114, 0xF, 0xF, false));  // row_shr:4
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x118, 0xF, 0xF, false));  // row_shr:8
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x138, 0xF, 0xF, false);       // wave_shr:1
+}
+
+// x of lane l ^ J: quad permutes for J = 1, 2, row shifts by 4 for J = 4, a
+// rotation of each 16-lane row by 8 for J = 8, a swizzle for J = 16 and a
+// bpermute for J = 32.  Every lane of the wave must be active.
+template <int J>
+__device__ __forceinline__ uint32_t wave_xor_u32(uint32_t x) {
+  const int v = (int)x;
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (J == 4) {
+    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x104, 0xF, 0xF, false);  // row_shl:4
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    return (lane_id() & 4) ? dn : up;
+  } else if constexpr (J == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (J == 16) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x401F);  // lanes of 32: xor 16
+  } else {
+    static_assert(J == 32, "partner distance");
+    return (uint32_t)__shfl_xor(v, 32);
+  }
+}
+
+// Bitonic sort of one value per lane across the wave, ascending in lane
+// order: stage (K, J) for K = 2..64, J = K/2..1.  All lanes active.
+template <int K = 2, int J = 1>
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t x, int l) {
+  const uint32_t p = wave_xor_u32<J>(x);
+  const bool keep_min = ((l & J) == 0) == ((l & K) == 0);
+  x = keep_min ? min(x, p) : max(x, p);
+  if constexpr (J > 1) return wave_sort_u32<K, J / 2>(x, l);
+  else if constexpr (K < kWave) return wave_sort_u32<2 * K, K>(x, l);
+  else return x;
+}
+
+// One compare-exchange of a bitonic stage (k, J), J < 64, in registers: x is
+// element i of the array, held by lane i % 64, and its partner i ^ J is held
+// by lane (i % 64) ^ J of the same wave.  Every lane of the wave takes part.
+template <int J, typename K>
+__device__ __forceinline__ K bitonic_lane_step(K x, int i, int k) {
+  K p;
+  if constexpr (sizeof(K) == 8)
+    p = ((K)wave_xor_u32<J>((uint32_t)(x >> 32)) << 32) | wave_xor_u32<J>((uint32_t)x);
+  else
+    p = (K)wave_xor_u32<J>((uint32_t)x);
+  const bool keep_min = ((i & J) == 0) == ((i & k) == 0);
   const K mn = x < p ? x : p, mx = x < p ? p : x;
   return keep_min ? mn : mx;
+}
+
+// Stages (k, j) for j = min(k/2, 32) down to 1 on two independent elements
+// (k wave-uniform, so each test is a scalar branch)
+template <typename K>
+__device__ __forceinline__ void bitonic_lane_merge(K &x0, K &x1, int i0, int i1, int k) {
+  if (k >= 64) {
+    x0 = bitonic_lane_step<32>(x0, i0, k);
+    x1 = bitonic_lane_step<32>(x1, i1, k);
+  }
+  if (k >= 32) {
+    x0 = bitonic_lane_step<16>(x0, i0, k);
+    x1 = bitonic_lane_step<16>(x1, i1, k);
+  }
+  if (k >= 16) {
+    x0 = bitonic_lane_step<8>(x0, i0, k);
+    x1 = bitonic_lane_step<8>(x1, i1, k);
+  }
+  if (k >= 8) {
+    x0 = bitonic_lane_step<4>(x0, i0, k);
+    x1 = bitonic_lane_step<4>(x1, i1, k);
+  }
+  if (k >= 4) {
+    x0 = bitonic_lane_step<2>(x0, i0, k);
+    x1 = bitonic_lane_step<2>(x1, i1, k);
+  }
+  x0 = bitonic_lane_step<1>(x0, i0, k);
+  x1 = bitonic_lane_step<1>(x1, i1, k);
 }
 
 // Stages (k, j) of every k in [k0, k1] with j < 64, in registers, two
@@ -147,11 +230,7 @@ __device__ __forceinline__ void bitonic_segments(K *a, int N2, int k0, int k1) {
     const int i0 = sgm * kWave + l, i1 = (sgm + nw) * kWave + l;
     K x0 = i0 < N2 ? a[i0] : ~K(0);
     K x1 = i1 < N2 ? a[i1] : ~K(0);
-    for (int k = k0; k <= k1; k <<= 1)
-      for (int j = (k >> 1) < kWave ? (k >> 1) : kWave / 2; j > 0; j >>= 1) {
-        x0 = bitonic_lane_step(x0, i0, j, k);
-        x1 = bitonic_lane_step(x1, i1, j, k);
-      }
+    for (int k = k0; k <= k1; k <<= 1) bitonic_lane_merge(x0, x1, i0, i1, k);
     if (i0 < N2) a[i0] = x0;
     if (i1 < N2) a[i1] = x1;
   }
@@ -215,7 +294,8 @@ __device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
 // Bin keys are (load << 16) | bin: ascending key order is ascending
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
-constexpr int kLptRoundMin = 6;  // equal items taken as one round from this many
+constexpr int kLptRoundMin = 6;   // equal items taken as one round from this many
+constexpr int kLptPrefixMin = 8;  // prefix rounds (any weights) from this many items
 
 // With comp_kind and comp_estart given, it also writes each component's
 // first local CSR entry (2(q-1) entries for a path, 2q for a cycle, none for
@@ -236,31 +316,60 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   __shared__ uint64_t win[kWave];
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
   __shared__ unsigned long long s_wsum;
+  __shared__ unsigned int s_wmax;
   const int tid = threadIdx.x;
   const int N2 = next_pow2(nc > 0 ? nc : 1);
-  if (tid == 0) s_wsum = 0;
+  if (tid == 0) {
+    s_wsum = 0;
+    s_wmax = 0;
+  }
   __syncthreads();
 
   // 1. sort by (weight desc, label asc); components are indexed in label
   // order.  The weight is the read count, or the given weights (below 2^32).
+  // Keys are ((2^32-1 - w) << 32) | i, or, when every weight and index fits
+  // 16 bits, ((2^16-1 - w) << 16) | i in 32 bits (k32: the first half of
+  // keys holds them); ~0 pads to N2.
   unsigned long long wsum = 0;
+  uint32_t wmax = 0;
+  for (int i = tid; i < nc; i += blockDim.x) {
+    uint64_t w = weight ? weight[i] : (uint64_t)comp_size[i];
+    if (w > 0xFFFFFFFFull) {
+      atomicOr(status, CG_STATUS_WEIGHT_RANGE);
+      w = 0xFFFFFFFFull;
+    }
+    wsum += w;
+    wmax = w > wmax ? (uint32_t)w : wmax;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    wsum += __shfl_xor(wsum, off);
+    const uint32_t o = (uint32_t)__shfl_xor((int)wmax, off);
+    wmax = o > wmax ? o : wmax;
+  }
+  if (lane_id() == 0 && wsum) {
+    atomicAdd(&s_wsum, wsum);
+    atomicMax(&s_wmax, wmax);
+  }
+  for (int b = tid; b < P; b += blockDim.x) binA[b] = (uint64_t)b;  // load 0, sorted
+  __syncthreads();
+  const bool k32 = nc <= 0xFFFF && s_wmax <= 0xFFFFu;
+  uint32_t *keys32 = reinterpret_cast<uint32_t *>(keys);
   for (int i = tid; i < N2; i += blockDim.x) {
     uint64_t w = 0;
     if (i < nc) {
       w = weight ? weight[i] : (uint64_t)comp_size[i];
-      if (w > 0xFFFFFFFFull) {
-        atomicOr(status, CG_STATUS_WEIGHT_RANGE);
-        w = 0xFFFFFFFFull;
-      }
+      w = w > 0xFFFFFFFFull ? 0xFFFFFFFFull : w;
     }
-    wsum += w;
-    keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)w) << 32) | (uint32_t)i : ~0ull;
+    if (k32)
+      keys32[i] = i < nc ? ((0xFFFFu - (uint32_t)w) << 16) | (uint32_t)i : ~0u;
+    else
+      keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)w) << 32) | (uint32_t)i : ~0ull;
   }
-  for (int off = kWave / 2; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
-  if (lane_id() == 0 && wsum) atomicAdd(&s_wsum, wsum);
-  for (int b = tid; b < P; b += blockDim.x) binA[b] = (uint64_t)b;  // load 0, sorted
   __syncthreads();
-  bitonic_sort(keys, N2);
+  if (k32)
+    bitonic_sort(keys32, N2);
+  else
+    bitonic_sort(keys, N2);
 
   // 2. LPT.  The bins are kept sorted by (load, bin).  A window holds the W
   // least loaded bins in the lanes of wave 0 (sorted across lanes): each
@@ -287,7 +396,12 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
       uint32_t key = l < W ? (uint32_t)binA[l] : 0xFFFFFFFFu;
       for (int base = 0; base < T; base += kWave) {
         const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
-        const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
+        uint64_t item = 0;
+        if (l < cnt) {
+          const int at = i0 + base + l;
+          item = k32 ? ((uint64_t)(0xFFFF0000u | (keys32[at] >> 16)) << 32) | (keys32[at] & 0xFFFFu)
+                     : keys[at];
+        }
         int32_t mine = 0;  // bin of item l
         const uint32_t iw = (uint32_t)(item >> 32);
         for (int t = 0; t < cnt;) {
@@ -301,7 +415,29 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
           const int run = ~same ? (int)__builtin_ctzll(~same) : kWave;
           const int m = __popcll(below);
           const int c = run < m ? run : m;
-          if (c >= kLptRoundMin) {
+          // A prefix round: items t, t+1, ... go to lanes 0, 1, ... for as
+          // long as each lane's key is below every key the earlier items of
+          // the round raised (lane j is then the least loaded bin when item
+          // t + j comes), whatever the weights.  Only lanes below nk can
+          // qualify, so it is tried when m allows a long enough round and an
+          // equal run does not already take all m.
+          int cp = 0;
+          uint32_t r = 0xFFFFFFFFu;
+          if (m >= kLptPrefixMin && c < m) {
+            const bool has = l < cnt - t && l < W;
+            const uint32_t ql = 0xFFFFFFFFu - (uint32_t)__shfl((int)iw, (l + t) & (kWave - 1));
+            r = has ? key + (ql << kb) : 0xFFFFFFFFu;  // lane l's key after item t + l
+            const uint32_t lower = wave_excl_min_u32(r);
+            const uint64_t ok = __ballot(has && key < lower);
+            cp = ~ok ? (int)__builtin_ctzll(~ok) : kWave;
+          }
+          if (cp >= kLptPrefixMin) {
+            const uint32_t src = (uint32_t)__shfl((int)key, (l - t) & (kWave - 1));
+            if (l >= t && l < t + cp) mine = (int32_t)(src & bmask);
+            // raised keys in lanes 0..cp-1, the rest unchanged: sort the wave
+            key = wave_sort_u32(l < cp ? r : key, l);
+            t += cp;
+          } else if (c >= kLptRoundMin) {
             // a round: c equal items go to lanes 0..c-1 in order (each of
             // those bins is below lane 0's raised key, so the steps would pick
             // them one after another); the raised keys of lanes 0..c-1 and
@@ -339,7 +475,12 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
       uint64_t key = l < W ? binA[l] : ~0ull;
       for (int base = 0; base < T; base += kWave) {
         const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
-        const uint64_t item = l < cnt ? keys[i0 + base + l] : 0ull;
+        uint64_t item = 0;
+        if (l < cnt) {
+          const int at = i0 + base + l;
+          item = k32 ? ((uint64_t)(0xFFFF0000u | (keys32[at] >> 16)) << 32) | (keys32[at] & 0xFFFFu)
+                     : keys[at];
+        }
         int32_t mine = 0;  // bin of item l, kept in lane l until the batch ends
         for (int t = 0; t < cnt; ++t) {
           // t is uniform: broadcasts are lane reads into scalar registers
@@ -392,19 +533,32 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     }
   }
 
-  // 3. (bin, label) order, read offsets and the reads of each bin
-  for (int i = tid; i < N2; i += blockDim.x)
-    keys[i] = i < nc ? ((uint64_t)(uint32_t)bin_of[i] << 32) | (uint32_t)i : ~0ull;
-  for (int b = tid; b < P; b += blockDim.x) bin_reads[b] = 0;
+  // 3. (bin, label) order, read offsets and the reads of each bin; keys
+  // (bin << 16) | i in 32 bits when bin and index fit 16 bits
+  const bool b32 = nc <= 0xFFFF && P <= 0x10000;
+  for (int i = tid; i < N2; i += blockDim.x) {
+    if (b32)
+      keys32[i] = i < nc ? ((uint32_t)bin_of[i] << 16) | (uint32_t)i : ~0u;
+    else
+      keys[i] = i < nc ? ((uint64_t)(uint32_t)bin_of[i] << 32) | (uint32_t)i : ~0ull;
+  }
+  // the reads of each bin are summed in binB (free once the loads are out;
+  // in LDS when the bins are), then written once per bin
+  for (int b = tid; b < P; b += blockDim.x) binB[b] = 0;
   __syncthreads();
   for (int i = tid; i < nc; i += blockDim.x)
-    atomicAdd((unsigned long long *)bin_reads + bin_of[i], (unsigned long long)comp_size[i]);
-  bitonic_sort(keys, N2);
+    atomicAdd((unsigned long long *)binB + bin_of[i], (unsigned long long)comp_size[i]);
+  __syncthreads();
+  for (int b = tid; b < P; b += blockDim.x) bin_reads[b] = binB[b];
+  if (b32)
+    bitonic_sort(keys32, N2);
+  else
+    bitonic_sort(keys, N2);
   for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
   int carry = 0, ecarry = 0;
   for (int base = 0; base < nc; base += BLOCK) {
     const int i = base + tid;
-    const uint32_t c = i < nc ? (uint32_t)keys[i] : 0u;
+    const uint32_t c = i < nc ? (b32 ? keys32[i] & 0xFFFFu : (uint32_t)keys[i]) : 0u;
     const int32_t sz = i < nc ? comp_size[c] : 0;
     int32_t tot;
     const int32_t ex = block_excl_scan<int32_t, BLOCK>(sz, sh_scan, &tot);

@@ -708,6 +708,11 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
   const bool ext = J.external != 0;
   int m_e = 0;
   int64_t carry = 0;
+  // the work-queue buckets start from zero for kb_tables / kb_wq_place
+  for (int b = j * kBatchLptBlock + (int)threadIdx.x; b < kWqBuckets; b += (int)gridDim.x * kBatchLptBlock) {
+    B.wq_hist[b] = 0;
+    B.wq_cur[b] = 0;
+  }
   if (!ext) {
     if (nc <= kBatchSortCap && P <= kBatchBinCap)
       m_e = lpt_body<kBatchLptBlock>(nc, P, J.parts.comp_size, wts, s_keys, s_bin, s_binA, s_binB, J.parts.comp_bin,
@@ -778,10 +783,6 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
     B.chunk_base[B.n_jobs] = (int32_t)hc;
     B.counters[2] = 0;
     B.counters[3] += 1u;  // the next run's forest tag
-  }
-  for (int b = threadIdx.x; b < kWqBuckets; b += kBatchLptBlock) {
-    B.wq_hist[b] = 0;
-    B.wq_cur[b] = 0;
   }
   __threadfence();
 }

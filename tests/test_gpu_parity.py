@@ -163,6 +163,23 @@ def test_lpt_equal_runs(cg):
         check(cg, g, P, 2, name="equal-runs-P%d" % P)
 
 
+def test_lpt_prefix_rounds(cg):
+    """Components of many different read counts: the LPT places runs of
+    items whose bins stay the least loaded in one round (prefix rounds), with
+    and without windows of bins; the partition must stay the oracle's."""
+    rng = np.random.default_rng(9)
+    cases = [
+        ("spread", [int(x) for x in rng.integers(2, 400, size=700)]),
+        ("pow2", [int(2 ** x) for x in rng.integers(1, 9, size=500)]),
+        ("consecutive", list(range(2, 302))),
+        ("few-large", [300, 299, 298] + [int(x) for x in rng.integers(2, 6, size=900)]),
+    ]
+    for name, sizes in cases:
+        g = _chain_graph(rng, [int(x) for x in rng.permutation(sizes)])
+        for P in (2, 8, 63, 64, 100, 1024):
+            check(cg, g, P, 2, name="prefix-%s-P%d" % (name, P))
+
+
 def test_deterministic(cg):
     g = synth.config_graph(2)
     P = g.meta["P"]
