@@ -245,7 +245,28 @@ __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
   bitonic_segments(a, N2, 2, N2 < kWave ? N2 : kWave);
   __syncthreads();
   for (int k = 2 * kWave; k <= N2; k <<= 1) {
-    for (int j = k >> 1; j >= kWave; j >>= 1) {
+    int j = k >> 1;
+    // two stages (j, j/2) per barrier: each thread takes the four elements
+    // i, i + j/2, i + j, i + 3j/2 (bits j and j/2 of i clear), all sorted in
+    // the same direction since they differ only below k
+    for (; j >= 2 * kWave; j >>= 2) {
+      const int h = j >> 1;
+      for (int t = threadIdx.x; t < N2 / 4; t += blockDim.x) {
+        const int i = ((t & ~(h - 1)) << 2) | (t & (h - 1));
+        const bool up = (i & k) == 0;
+        K x0 = a[i], x1 = a[i + h], x2 = a[i + j], x3 = a[i + j + h];
+        if ((x0 > x2) == up) { const K tmp = x0; x0 = x2; x2 = tmp; }
+        if ((x1 > x3) == up) { const K tmp = x1; x1 = x3; x3 = tmp; }
+        if ((x0 > x1) == up) { const K tmp = x0; x0 = x1; x1 = tmp; }
+        if ((x2 > x3) == up) { const K tmp = x2; x2 = x3; x3 = tmp; }
+        a[i] = x0;
+        a[i + h] = x1;
+        a[i + j] = x2;
+        a[i + j + h] = x3;
+      }
+      __syncthreads();
+    }
+    if (j >= kWave) {  // one stage left above the register stages
       for (int t = threadIdx.x; t < N2 / 2; t += blockDim.x) {
         const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // pair (i, i + j)
         const K x = a[i], y = a[i + j];
@@ -315,6 +336,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
+  __shared__ int64_t sh_scan64[BLOCK / kWave + 1];
   __shared__ unsigned long long s_wsum;
   __shared__ unsigned int s_wmax;
   const int tid = threadIdx.x;
@@ -560,23 +582,31 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     const int i = base + tid;
     const uint32_t c = i < nc ? (b32 ? keys32[i] & 0xFFFFu : (uint32_t)keys[i]) : 0u;
     const int32_t sz = i < nc ? comp_size[c] : 0;
-    int32_t tot;
-    const int32_t ex = block_excl_scan<int32_t, BLOCK>(sz, sh_scan, &tot);
-    if (i < nc) {
-      comp_start[c] = carry + ex;
-      comp_rank[c] = i;
-    }
-    carry += tot;
     if (comp_estart) {
-      int32_t e2 = 0;
+      // reads and local entries in one scan: (reads << 32) | entries, each
+      // field's total below 2^32 (entries <= 2 * reads, reads < 2^31)
+      int64_t e2 = 0;
       if (i < nc) {
         const uint8_t kd = comp_kind[c];
         e2 = kd == CG_KIND_PATH ? 2 * (sz - 1) : (kd == CG_KIND_CYCLE ? 2 * sz : 0);
       }
-      int32_t etot;
-      const int32_t eex = block_excl_scan<int32_t, BLOCK>(e2, sh_scan, &etot);
-      if (i < nc) comp_estart[c] = ecarry + eex;
-      ecarry += etot;
+      int64_t tot;
+      const int64_t ex = block_excl_scan<int64_t, BLOCK>(((int64_t)sz << 32) | e2, sh_scan64, &tot);
+      if (i < nc) {
+        comp_start[c] = carry + (int32_t)(ex >> 32);
+        comp_estart[c] = ecarry + (int32_t)(uint32_t)ex;
+        comp_rank[c] = i;
+      }
+      carry += (int32_t)(tot >> 32);
+      ecarry += (int32_t)(uint32_t)tot;
+    } else {
+      int32_t tot;
+      const int32_t ex = block_excl_scan<int32_t, BLOCK>(sz, sh_scan, &tot);
+      if (i < nc) {
+        comp_start[c] = carry + ex;
+        comp_rank[c] = i;
+      }
+      carry += tot;
     }
   }
   return ecarry;
