@@ -238,8 +238,8 @@ __device__ __forceinline__ void bitonic_segments(K *a, int N2, int k0, int k1) {
 
 // Sort a[0, N2) ascending (N2 a power of two) with every thread of the
 // workgroup.  Only the stages whose pairs lie 64 or more apart go through
-// memory with a workgroup barrier each; the stages inside 64-element
-// segments run in registers (for N2 = 512: 6 barriers instead of 45).
+// memory, two per pass and barrier; the stages inside 64-element segments
+// run in registers (for N2 = 512: 4 passes through memory, 45 stages).
 template <typename K>
 __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
   bitonic_segments(a, N2, 2, N2 < kWave ? N2 : kWave);
