@@ -180,6 +180,17 @@ def test_lpt_prefix_rounds(cg):
             check(cg, g, P, 2, name="prefix-%s-P%d" % (name, P))
 
 
+def test_lpt_many_components(cg):
+    """More components than the LPT sorts hold in LDS (8192), with 32-bit
+    keys (fewer than 65536 components) and with 64-bit keys (more)."""
+    rng = np.random.default_rng(10)
+    for name, sizes in (("20k", [2] * 15000 + [int(x) for x in rng.integers(3, 40, size=5000)]),
+                        ("70k", [2] * 66000 + [int(x) for x in rng.integers(3, 9, size=4000)])):
+        g = _chain_graph(rng, [int(x) for x in rng.permutation(sizes)], len_lo=20, len_hi=30)
+        for P in (7, 64, 1024):
+            check(cg, g, P, 2, name="many-%s-P%d" % (name, P))
+
+
 def test_deterministic(cg):
     g = synth.config_graph(2)
     P = g.meta["P"]
