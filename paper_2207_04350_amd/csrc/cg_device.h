@@ -547,14 +547,6 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     __syncthreads();
     i0 += T;
   }
-  {
-    const int bb = narrow ? kb : kBinBits;
-    for (int b = tid; b < P; b += blockDim.x) {
-      const uint64_t k = binA[b];
-      bin_load[k & ((1ull << bb) - 1)] = k >> bb;
-    }
-  }
-
   // 3. (bin, label) order, read offsets and the reads of each bin; keys
   // (bin << 16) | i in 32 bits when bin and index fit 16 bits
   const bool b32 = nc <= 0xFFFF && P <= 0x10000;
@@ -571,12 +563,10 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   for (int i = tid; i < nc; i += blockDim.x)
     atomicAdd((unsigned long long *)binB + bin_of[i], (unsigned long long)comp_size[i]);
   __syncthreads();
-  for (int b = tid; b < P; b += blockDim.x) bin_reads[b] = binB[b];
   if (b32)
     bitonic_sort(keys32, N2);
   else
     bitonic_sort(keys, N2);
-  for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
   int carry = 0, ecarry = 0;
   for (int base = 0; base < nc; base += BLOCK) {
     const int i = base + tid;
@@ -609,6 +599,18 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
       carry += tot;
     }
   }
+  // the per-bin and per-component results, stored after the last barrier
+  // (a barrier waits for the stores issued before it); binA still holds the
+  // final bin list and binB the reads of each bin
+  {
+    const int bb = narrow ? kb : kBinBits;
+    for (int b = tid; b < P; b += blockDim.x) {
+      const uint64_t k = binA[b];
+      bin_load[k & ((1ull << bb) - 1)] = k >> bb;
+      bin_reads[b] = binB[b];
+    }
+  }
+  for (int i = tid; i < nc; i += blockDim.x) comp_bin[i] = bin_of[i];
   return ecarry;
 }
 

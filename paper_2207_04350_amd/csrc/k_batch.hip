@@ -753,34 +753,36 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
   __syncthreads();
   if (!last) return;
   __threadfence();
-  int64_t cc = 0, pc = 0, hc = 0;
-  for (int base = 0; base < B.n_jobs; base += kBatchLptBlock) {
-    const int i = base + threadIdx.x;
-    int64_t xc = 0, xp = 0;
-    if (i < B.n_jobs) {
-      const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      xc = (int32_t)(uint32_t)w;
-      xp = (int32_t)(uint32_t)(w >> 32);
-    }
-    const int64_t xh = (xp + kChunkPieces - 1) / kChunkPieces;
-    int64_t tc, tp, th;
-    const int64_t ec = block_excl_scan<int64_t, kBatchLptBlock>(xc, sh, &tc);
-    const int64_t ep = block_excl_scan<int64_t, kBatchLptBlock>(xp, sh, &tp);
-    const int64_t eh = block_excl_scan<int64_t, kBatchLptBlock>(xh, sh, &th);
-    if (i < B.n_jobs) {
-      B.comp_base[i] = (int32_t)(cc + ec);
-      B.piece_base[i] = (int32_t)(pc + ep);
-      B.chunk_base[i] = (int32_t)(hc + eh);
-    }
-    cc += tc;
-    pc += tp;
-    hc += th;
+  // each thread sums a run of consecutive jobs; two scans give the bases:
+  // (components << 32) | pieces (each total below 2^31) and chunks
+  const int per = (B.n_jobs + kBatchLptBlock - 1) / kBatchLptBlock;
+  const int i0 = (int)threadIdx.x * per;
+  const int i1 = i0 + per < B.n_jobs ? i0 + per : B.n_jobs;
+  int64_t xcp = 0, xh = 0;
+  for (int i = i0; i < i1; ++i) {
+    const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t xc = (int32_t)(uint32_t)w, xp = (int32_t)(uint32_t)(w >> 32);
+    xcp += (xc << 32) | xp;
+    xh += (xp + kChunkPieces - 1) / kChunkPieces;
+  }
+  int64_t tcp, th;
+  int64_t ecp = block_excl_scan<int64_t, kBatchLptBlock>(xcp, sh, &tcp);
+  int64_t eh = block_excl_scan<int64_t, kBatchLptBlock>(xh, sh, &th);
+  for (int i = i0; i < i1; ++i) {
+    const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t xc = (int32_t)(uint32_t)w, xp = (int32_t)(uint32_t)(w >> 32);
+    B.comp_base[i] = (int32_t)(ecp >> 32);
+    B.piece_base[i] = (int32_t)(uint32_t)ecp;
+    B.chunk_base[i] = (int32_t)eh;
+    ecp += (xc << 32) | xp;
+    eh += (xp + kChunkPieces - 1) / kChunkPieces;
   }
   if (threadIdx.x == 0) {
-    B.comp_base[B.n_jobs] = (int32_t)cc;
-    B.piece_base[B.n_jobs] = (int32_t)pc;
-    B.chunk_base[B.n_jobs] = (int32_t)hc;
+    B.comp_base[B.n_jobs] = (int32_t)(tcp >> 32);
+    B.piece_base[B.n_jobs] = (int32_t)(uint32_t)tcp;
+    B.chunk_base[B.n_jobs] = (int32_t)th;
     B.counters[2] = 0;
     B.counters[3] += 1u;  // the next run's forest tag
   }
