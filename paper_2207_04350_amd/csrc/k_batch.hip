@@ -135,7 +135,7 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 __device__ __forceinline__ uint32_t forest_tag(const BatchDev &B) { return B.counters[3] + 1u; }
 
 __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__restrict__ tiles) {
-  __shared__ int32_t sh[kMaskThreads / kWave + 1];
+  __shared__ int64_t sh[kMaskThreads / kWave + 1];
   const MaskTile D = tiles[blockIdx.x];
   const int32_t n = D.n;
   const int lane = lane_id();
@@ -176,6 +176,26 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__r
     u0[k] = (dg[k] == 1 || dg[k] == 2) ? D.col[bb[k]] : -1;
     u1[k] = dg[k] == 2 ? D.col[bb[k] + 1] : -1;
   }
+  // listed reads packed in id order: group 0 of every thread precedes group
+  // 1, so one scan of (listed, branch) counts of both groups, 16-bit fields
+  // (a tile holds fewer than 2^16 reads), gives every position.  The scan
+  // comes before any store: its barriers would wait for them.
+  static_assert(kMaskGroups == 2, "two groups per scan");
+  int64_t cnt = 0;
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    int64_t c = 0, b = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c += (dg[4 * g + i] == 1 || dg[4 * g + i] == 2) ? 1 : 0;
+      b += dg[4 * g + i] >= 3 ? 1 : 0;
+    }
+    cnt |= (c | (b << 16)) << (32 * g);
+  }
+  int64_t tot;
+  const int64_t ex = block_excl_scan<int64_t, kMaskThreads>(cnt, sh, &tot);
+  const int32_t listed0 = (int32_t)(tot & 0xFFFF);
+  int32_t pos[kMaskGroups] = {D.v0 + (int32_t)(ex & 0xFFFF), D.v0 + listed0 + (int32_t)((ex >> 32) & 0xFFFF)};
 #pragma unroll
   for (int g = 0; g < kMaskGroups; ++g) {
     uint32_t fw = 0;
@@ -195,35 +215,19 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__r
           D.label_comp[v + i] = D.lc_init;
         }
     }
-  }
-  // listed reads packed in id order: group g of every thread precedes group
-  // g + 1, so the tile is scanned group by group
-  int32_t tot_all = 0;
-#pragma unroll
-  for (int g = 0; g < kMaskGroups; ++g) {
-    int c = 0, b = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      c += (dg[4 * g + i] == 1 || dg[4 * g + i] == 2) ? 1 : 0;
-      b += dg[4 * g + i] >= 3 ? 1 : 0;
-    }
-    // listed count in the low 16 bits, branch count above (a tile holds
-    // fewer than 2^16 reads)
-    int32_t tot;
-    int32_t pos = D.v0 + (tot_all & 0xFFFF) +
-                  (block_excl_scan<int32_t, kMaskThreads>(c | (b << 16), sh, &tot) & 0xFFFF);
-    tot_all += tot;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 4 * g + i;
       if (dg[k] == 1 || dg[k] == 2) {
-        D.conn_list[pos] = make_int4(v0[g] + i, u0[k], u1[k], dg[k]);
-        D.conn_map[v0[g] + i] = pos;
-        ++pos;
+        D.conn_list[pos[g]] = make_int4(v0[g] + i, u0[k], u1[k], dg[k]);
+        D.conn_map[v0[g] + i] = pos[g];
+        ++pos[g];
       }
     }
   }
-  if (threadIdx.x == 0) *D.tile_cnt = make_int2(tot_all & 0xFFFF, tot_all >> 16);
+  if (threadIdx.x == 0)
+    *D.tile_cnt = make_int2(listed0 + (int32_t)((tot >> 32) & 0xFFFF),
+                            (int32_t)((tot >> 16) & 0xFFFF) + (int32_t)((tot >> 48) & 0xFFFF));
 }
 
 // 1b. the neighbour lookups of every listed read, spread over the whole chip
