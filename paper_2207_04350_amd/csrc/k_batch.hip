@@ -875,9 +875,16 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   const int32_t i1 = i0 + per < tc ? i0 + per : tc;
   for (int b = threadIdx.x; b < kWqBuckets; b += kWqBlock) s_cnt[b] = 0;
   __syncthreads();
+  // the thread's first component is kept in registers for the placement
+  // (with 128 workgroups of 256 threads, every component of a batch of up to
+  // 32768 is a first one); later ones are loaded again there
+  int4 first = make_int4(-1, 0, 0, 0);
   for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
     const int j = B.comp_job[i];
-    const int32_t q = B.jobs[j].parts.comp_size[i - B.comp_base[j]];
+    const int32_t c = i - B.comp_base[j];
+    const cg_parts &P = B.jobs[j].parts;
+    const int32_t q = P.comp_size[c];
+    if (i == i0 + (int32_t)threadIdx.x) first = make_int4(j, c, q, P.comp_start[c]);
     atomicAdd(s_cnt + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
   }
   __syncthreads();
@@ -888,12 +895,15 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   }
   __syncthreads();
   for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
-    const int j = B.comp_job[i];
-    const int32_t c = i - B.comp_base[j];
-    const cg_parts &P = B.jobs[j].parts;
-    const int32_t q = P.comp_size[c], st = P.comp_start[c];
-    const int b = q < kWqBuckets - 1 ? q : kWqBuckets - 1;
-    B.wq[s_base[b] + atomicAdd(s_cnt + b, 1)] = make_int4(j, c, q, st);
+    int4 e = first;
+    if (i != i0 + (int32_t)threadIdx.x) {
+      const int j = B.comp_job[i];
+      const int32_t c = i - B.comp_base[j];
+      const cg_parts &P = B.jobs[j].parts;
+      e = make_int4(j, c, P.comp_size[c], P.comp_start[c]);
+    }
+    const int b = e.z < kWqBuckets - 1 ? e.z : kWqBuckets - 1;
+    B.wq[s_base[b] + atomicAdd(s_cnt + b, 1)] = e;
   }
 }
 
