@@ -44,7 +44,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------ */
 #define CG_OK            0
 #define CG_EINVAL       -1  /* bad argument, shape or pointer                    */
-#define CG_ENOMEM       -2  /* context scratch smaller than cg_footprint() asks   */
+#define CG_ENOMEM       -2  /* context scratch smaller than cg_footprint() states */
 #define CG_EHIP         -3  /* HIP runtime error; text in cg_last_error()         */
 #define CG_ECAPACITY    -4  /* a device-side count exceeded a caller capacity     */
 #define CG_EUNSUPPORTED -5  /* valid request outside the library's limits         */
@@ -208,9 +208,27 @@ int cg_ctx_create(int device, size_t scratch_bytes, cg_ctx **out);
  * that uses it is still in flight. */
 int cg_ctx_destroy(cg_ctx *ctx);
 
-/* Scratch bytes a context needs for graphs of up to n vertices, m entries
- * and P bins.  bytes is [host]. */
-int cg_footprint(int32_t n, int32_t m, int32_t P, uint64_t *bytes);
+/* Device bytes of one graph of n reads, m directed entries, seq_words
+ * packed words and P bins (the signature of Algorithm 2: the string graph S
+ * and the read sequences, Section 4.1), for sizing a context and for
+ * admitting work by its HBM footprint.  All figures are exact sums of the
+ * buffer sizes this header states; allocator rounding is the caller's.
+ *   scratch  the context scratch the five calls need (cg_ctx_create)
+ *   graph    the cg_graph arrays: row_ptr (n+1), col, ovl, strand (m each),
+ *            read_len, read_off (n each), seq (seq_words), and pre, post (m
+ *            each) when coords is nonzero
+ *   outputs  every output buffer of the five calls at the capacities stated
+ *            below (n per record array, 2n local entries, P bins), with
+ *            cap_words = seq_words for the packed contigs
+ * out is [host].  Errors: CG_EINVAL for a NULL out, negative n, m or
+ * seq_words beyond 2^62, or P outside [1, 65536]. */
+typedef struct {
+  uint64_t scratch;
+  uint64_t graph;
+  uint64_t outputs;
+} cg_sizes;
+int cg_footprint(int32_t n, int32_t m, uint64_t seq_words, int32_t P, int32_t coords,
+                 cg_sizes *out);
 
 /* Device status bits (CG_STATUS_*) raised since the last clear.  Waits for
  * `stream`, then copies the word to *status [host]; clears it if `clear`. */

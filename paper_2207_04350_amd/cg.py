@@ -48,6 +48,11 @@ class CgContigs(ctypes.Structure):
                 ("d_total_words", _vp)]
 
 
+class CgSizes(ctypes.Structure):
+    _fields_ = [("scratch", ctypes.c_uint64), ("graph", ctypes.c_uint64),
+                ("outputs", ctypes.c_uint64)]
+
+
 class CgJob(ctypes.Structure):
     _fields_ = [("g", CgGraph), ("P", ctypes.c_int32), ("min_reads", ctypes.c_int32),
                 ("weight", ctypes.c_int32), ("flags", _vp), ("d_counts", _vp), ("label", _vp), ("parts", CgParts),
@@ -77,8 +82,8 @@ def lib():
         L.cg_last_error.restype = ctypes.c_char_p
         L.cg_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, P(_vp)]
         L.cg_ctx_destroy.argtypes = [_vp]
-        L.cg_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                   P(ctypes.c_uint64)]
+        L.cg_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                   ctypes.c_int32, ctypes.c_int32, P(CgSizes)]
         L.cg_ctx_status.argtypes = [_vp, _vp, P(ctypes.c_uint32), ctypes.c_int]
         L.cg_validate.argtypes = [_vp, P(CgGraph), _vp, _vp]
         L.cg_mask_branches.argtypes = [_vp, P(CgGraph), _vp, _vp, _vp]
@@ -125,10 +130,18 @@ def _stream(stream):
     return _vp(s.cuda_stream)
 
 
+def sizes(n, m, seq_words, P, coords=False):
+    """cg_footprint: device bytes of a graph of n reads, m entries and
+    seq_words packed words at P bins, as {"scratch", "graph", "outputs"}."""
+    out = CgSizes()
+    _check(lib().cg_footprint(int(n), int(m), int(seq_words), int(P), int(bool(coords)),
+                              ctypes.byref(out)))
+    return {"scratch": int(out.scratch), "graph": int(out.graph), "outputs": int(out.outputs)}
+
+
 def footprint(n, m, P):
-    out = ctypes.c_uint64(0)
-    _check(lib().cg_footprint(int(n), int(m), int(P), ctypes.byref(out)))
-    return int(out.value)
+    """Context scratch bytes for graphs of up to n reads, m entries, P bins."""
+    return sizes(n, m, 0, P)["scratch"]
 
 
 class Context:

@@ -111,7 +111,7 @@ static void prof_free(cg_ctx *ctx) {
 
 using namespace cg;
 
-static int check_graph(const cg_graph *g, bool need_seq) {
+int cg::check_graph(const cg_graph *g, bool need_seq) {
   if (!g) return set_error(CG_EINVAL, "graph is NULL");
   if (g->n < 0 || g->n >= (1 << 30)) return set_error(CG_EINVAL, "n=%d outside [0, 2^30)", g->n);
   if (g->m < 0) return set_error(CG_EINVAL, "m=%d is negative", g->m);
@@ -125,6 +125,33 @@ static int check_graph(const cg_graph *g, bool need_seq) {
   return CG_OK;
 }
 
+int cg::check_P(int32_t P) {
+  if (P < 1 || P > 65536) return set_error(CG_EINVAL, "P=%d outside [1, 65536]", P);
+  return CG_OK;
+}
+
+int cg::check_parts(const cg_parts *p) {
+  if (!p || !p->comp_label || !p->comp_size || !p->comp_kind || !p->comp_bin || !p->comp_rank ||
+      !p->comp_start || !p->bin_load || !p->label_comp || !p->d_n_comp)
+    return set_error(CG_EINVAL, "cg_parts has a NULL member");
+  return CG_OK;
+}
+
+int cg::check_local(const cg_local *l) {
+  if (!l || !l->perm || !l->bin_vptr || !l->loc_row_ptr || !l->loc_col || !l->loc_eid ||
+      !l->d_sizes)
+    return set_error(CG_EINVAL, "cg_local has a NULL member");
+  return CG_OK;
+}
+
+int cg::check_contigs(const cg_contigs *c) {
+  if (!c || !c->label || !c->bin || !c->start || !c->n_reads || !c->len || !c->base_off ||
+      !c->cflags || !c->layout_off || !c->layout_vid || !c->layout_rev || !c->d_total_words ||
+      (c->cap_words > 0 && !c->bases))
+    return set_error(CG_EINVAL, "cg_contigs has a NULL member");
+  return CG_OK;
+}
+
 static int check_ctx(cg_ctx *ctx, const cg_graph *g, int32_t P, Scratch *s) {
   if (!ctx) return set_error(CG_EINVAL, "context is NULL");
   if (!carve(ctx, g->n, g->m, P, s))
@@ -133,18 +160,26 @@ static int check_ctx(cg_ctx *ctx, const cg_graph *g, int32_t P, Scratch *s) {
   return CG_OK;
 }
 
-static int check_P(int32_t P) {
-  if (P < 1 || P > 65536) return set_error(CG_EINVAL, "P=%d outside [1, 65536]", P);
-  return CG_OK;
-}
-
 extern "C" {
 
 const char *cg_last_error(void) { return g_err; }
 
-int cg_footprint(int32_t n, int32_t m, int32_t P, uint64_t *bytes) {
-  if (!bytes || n < 0 || m < 0 || P < 1) return set_error(CG_EINVAL, "bad footprint arguments");
-  *bytes = (uint64_t)layout(n, m, P).total;
+int cg_footprint(int32_t n, int32_t m, uint64_t seq_words, int32_t P, int32_t coords,
+                 cg_sizes *out) {
+  if (!out || n < 0 || m < 0 || P < 1 || P > 65536 || seq_words >= (1ull << 62))
+    return set_error(CG_EINVAL, "bad footprint arguments (n=%d m=%d P=%d)", n, m, P);
+  const uint64_t N = (uint64_t)n, M = (uint64_t)m, Pb = (uint64_t)P;
+  out->scratch = (uint64_t)layout(n, m, P).total;
+  // row_ptr, col, ovl, strand, read_len, read_off, seq (+ pre, post)
+  out->graph = 4 * (N + 1) + M * (4 + 4 + 1) + N * (4 + 8) + 4 * seq_words +
+               (coords ? 8 * M : 0);
+  // per read: flags 1, label 4; cg_parts: comp_label, comp_size 8, comp_kind 1,
+  // comp_bin, comp_rank, comp_start 12, label_comp 4; cg_local: perm 4,
+  // loc_row_ptr 4 (+4 once), loc_col, loc_eid 16; cg_contigs: label, bin,
+  // start, n_reads 16, len, base_off 16, cflags, layout_off 8, layout_vid 4,
+  // layout_rev 1 -- 99 bytes; then d_counts 8, bin_load 8P, d_n_comp 4,
+  // bin_vptr 4(P+1), d_sizes 8, bases 4 cap_words, d_total_words 8
+  out->outputs = 99 * N + 4 + 8 + 8 * Pb + 4 + 4 * (Pb + 1) + 8 + 4 * seq_words + 8;
   return CG_OK;
 }
 
@@ -300,13 +335,6 @@ int cg_components(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, int32_t 
   return launch_components(ctx, *g, flags, label, (hipStream_t)stream);
 }
 
-static int check_parts(const cg_parts *p) {
-  if (!p || !p->comp_label || !p->comp_size || !p->comp_kind || !p->comp_bin || !p->comp_rank ||
-      !p->comp_start || !p->bin_load || !p->label_comp || !p->d_n_comp)
-    return set_error(CG_EINVAL, "cg_parts has a NULL member");
-  return CG_OK;
-}
-
 int cg_partition(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_t *label,
                  int32_t P, int32_t min_reads, int32_t weight, const cg_parts *out,
                  void *stream) {
@@ -327,9 +355,7 @@ int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_
               const cg_parts *parts, int32_t P, const cg_local *out, void *stream) {
   int rc = check_graph(g, false);
   if (rc || (rc = check_P(P)) || (rc = check_parts(parts))) return rc;
-  if (!out || !out->perm || !out->bin_vptr || !out->loc_row_ptr || !out->loc_col ||
-      !out->loc_eid || !out->d_sizes)
-    return set_error(CG_EINVAL, "cg_local has a NULL member");
+  if ((rc = check_local(out))) return rc;
   if (g->n > 0 && (!flags || !label)) return set_error(CG_EINVAL, "NULL argument");
   Scratch s;
   if ((rc = check_ctx(ctx, g, P, &s))) return rc;
@@ -343,10 +369,7 @@ int cg_assemble(cg_ctx *ctx, const cg_graph *g, const cg_parts *parts, const cg_
   if (!local || !local->perm || !local->bin_vptr || !local->loc_row_ptr || !local->loc_col ||
       !local->loc_eid)
     return set_error(CG_EINVAL, "cg_local has a NULL member");
-  if (!out || !out->label || !out->bin || !out->start || !out->n_reads || !out->len ||
-      !out->base_off || !out->cflags || !out->layout_off || !out->layout_vid ||
-      !out->layout_rev || !out->d_total_words || (out->cap_words > 0 && !out->bases))
-    return set_error(CG_EINVAL, "cg_contigs has a NULL member");
+  if ((rc = check_contigs(out))) return rc;
   Scratch s;
   if ((rc = check_ctx(ctx, g, P, &s))) return rc;
   return launch_assemble(ctx, *g, s, *parts, *local, P, *out, (hipStream_t)stream);

@@ -76,7 +76,7 @@ struct cg_ctx {
 
 namespace cg {
 
-// Scratch carving shared by cg_footprint and the calls.
+// Scratch carving shared by cg_footprint, the calls and the batch slices.
 struct Layout {
   size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
       estart, memb, piece_skip, comp_w, bin_reads, total;
@@ -87,6 +87,13 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);
 // error text (thread local) and HIP error translation
 int set_error(int code, const char *fmt, ...);
 int hip_check(hipError_t e, const char *what);
+
+// host-side argument checks shared by the entry points
+int check_graph(const cg_graph *g, bool need_seq);
+int check_P(int32_t P);
+int check_parts(const cg_parts *p);
+int check_local(const cg_local *l);
+int check_contigs(const cg_contigs *c);
 
 // ---------------------------------------------------------------------------
 // Device utilities

@@ -31,32 +31,22 @@ from . import cg
 # ---------------------------------------------------------------------------
 
 def graph_bytes(n, m, seq_words, pre_post=False):
-    """Device bytes of a resident graph (as DeviceGraph allocates it)."""
-    k, mm = max(n, 1), max(m, 1)
-    return (4 * (n + 1) + mm * (4 + 4 + 1 + (8 if pre_post else 0)) + k * (4 + 8)
-            + 4 * max(int(seq_words), 1))
+    """Device bytes of a resident graph (cg_footprint's `graph` figure)."""
+    return cg.sizes(n, m, seq_words, 1, pre_post)["graph"]
 
 
-def output_bytes(n, P, cap_words):
-    """Device bytes of one graph's outputs (as Outputs allocates them)."""
-    k = max(n, 1)
-    # per read: flags 1, label 4, comp_label/size 8, comp_kind 1, comp_bin/rank/
-    # start 12, label_comp 4, perm 4, loc_row_ptr 4, loc_col/eid 16, contig
-    # label/bin/start/n_reads 16, len/base_off 16, flags/layout_off 8,
-    # layout_vid 4, layout_rev 1
-    per_read = 99
-    return (k * per_read + 4 + 8 * P + 4 * (P + 1) + 4 * max(int(cap_words), 1)
-            + 8 + 4 + 8 + 8)
+def output_bytes(n, P, seq_words):
+    """Device bytes of one graph's outputs at cap_words = seq_words
+    (cg_footprint's `outputs` figure)."""
+    return cg.sizes(n, 0, seq_words, P)["outputs"]
 
 
 def request_footprint(g, P, resident=False):
     """HBM a request holds while it is admitted (its slot's scratch is not
     counted: slots own theirs for the life of the server; nor is a resident
     graph, charged once when it was made resident)."""
-    out = output_bytes(g.n, P, g.seq.shape[0] + g.n)
-    if resident:
-        return out
-    return graph_bytes(g.n, g.m, g.seq.shape[0], getattr(g, "pre", None) is not None) + out
+    s = cg.sizes(g.n, g.m, g.seq.shape[0], P, getattr(g, "pre", None) is not None)
+    return s["outputs"] if resident else s["graph"] + s["outputs"]
 
 
 # ---------------------------------------------------------------------------
@@ -152,7 +142,7 @@ class _Resident:
                 d = {k: v.to(device, non_blocking=True) for k, v in req.host.t.items()}
                 dg = cg.DeviceGraph.from_tensors(g.n, g.m, d, int(g.seq.shape[0]), device)
             self.dg = dg
-            self.out = cg.Outputs(g.n, req.P, int(g.seq.shape[0]) + g.n, device)
+            self.out = cg.Outputs(g.n, req.P, int(g.seq.shape[0]), device)
             self.counts = torch.empty(4, dtype=torch.int64, pin_memory=True)
         self.phase = 0
         self.event = None

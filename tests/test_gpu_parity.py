@@ -255,6 +255,23 @@ def test_alignment_ends(cg):
     ctx.close()
 
 
+def test_alignment_ends_long_components(cg):
+    """Explicit (pre, post) through every walk form: components of 200 and
+    900 reads (the LDS walk of one workgroup) and of 1,500 and 3,000 reads
+    (the walk over global arrays), as chains and as cycles, with consistent
+    x-drop clips and with arbitrary in-range coordinates (Section 4.4); and
+    the 50 Mbp workload with clips."""
+    from tests.test_oracle_overhangs import _random_pre_post
+    rng = np.random.default_rng(31)
+    g = _chain_graph(rng, [200, 900, 1500, 3000, 2], cycles=[200, 900, 1500, 3000],
+                     len_lo=30, len_hi=80)
+    check(cg, synth.with_alignment_ends(g, rng, max_clip=3), 4, 2, name="long-clipped")
+    check(cg, _random_pre_post(g, rng), 4, 2, name="long-random-coords")
+    check(cg, _random_pre_post(g, rng), 3, 1, name="long-random-coords-min1")
+    g2 = synth.with_alignment_ends(synth.config_graph(2), np.random.default_rng(32), max_clip=3)
+    check(cg, g2, 64, 2, name="config2-clipped")
+
+
 def test_bases_weighted_partition(cg):
     """GreedyPartitioning by bases (the total read length of a component)."""
     check(cg, synth.config_graph(1), 8, 2, name="config1-bases", weight="bases")

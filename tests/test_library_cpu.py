@@ -35,8 +35,16 @@ def test_footprint_grows_with_the_graph():
     b = cg.footprint(100000, 200000, 8)
     c = cg.footprint(100000, 200000, 4096)
     assert 0 < a < b < c
-    with pytest.raises(cg.CgError):
-        cg.footprint(-1, 0, 8)
+    s1 = cg.sizes(1000, 2000, 5000, 8)
+    s2 = cg.sizes(1000, 2000, 6000, 8)
+    s3 = cg.sizes(1000, 2000, 6000, 8, coords=True)
+    assert s2["graph"] - s1["graph"] == 4000 and s2["outputs"] - s1["outputs"] == 4000
+    assert s3["graph"] - s2["graph"] == 8 * 2000 and s3["outputs"] == s2["outputs"]
+    assert s1["scratch"] == a
+    for bad in ((-1, 0, 0, 8), (10, -1, 0, 8), (10, 10, 0, 0), (10, 10, 0, 70000),
+                (10, 10, 1 << 62, 8)):
+        with pytest.raises(cg.CgError):
+            cg.sizes(*bad)
 
 
 def test_null_arguments_rejected_on_host():

@@ -45,21 +45,29 @@ def test_oversized_request_is_rejected():
 
 
 def test_footprint_matches_the_allocations():
+    """The library's footprint (cg_footprint) equals the bytes the binding
+    allocates for a graph and its outputs, with and without coordinates."""
     import torch
     from paper_2207_04350_amd import cg
     g = synth.config_graph(1)
-    P = 8
-    dg = cg.DeviceGraph(g, "cpu")
-    out = cg.Outputs(g.n, P, int(g.seq.shape[0]) + g.n, "cpu")
-    gb = sum(t.numel() * t.element_size() for t in (dg.row_ptr, dg.col, dg.ovl, dg.strand,
-                                                     dg.read_len, dg.read_off, dg.seq))
-    ob = sum(t.numel() * t.element_size() for t in vars(out).values()
-             if isinstance(t, torch.Tensor))
-    assert serve.graph_bytes(g.n, g.m, g.seq.shape[0]) == gb
-    assert serve.output_bytes(g.n, P, int(g.seq.shape[0]) + g.n) == ob
-    assert serve.request_footprint(g, P) == gb + ob
-    # a request on a resident graph holds its outputs only
-    assert serve.request_footprint(g, P, resident=True) == ob
+    for coords in (False, True):
+        h = synth.with_alignment_ends(g) if coords else g
+        for P in (8, 1000):
+            dg = cg.DeviceGraph(h, "cpu")
+            out = cg.Outputs(h.n, P, int(h.seq.shape[0]), "cpu")
+            gb = sum(t.numel() * t.element_size() for t in (dg.row_ptr, dg.col, dg.ovl, dg.strand,
+                                                             dg.read_len, dg.read_off, dg.seq,
+                                                             dg.pre, dg.post) if t is not None)
+            ob = sum(t.numel() * t.element_size() for t in vars(out).values()
+                     if isinstance(t, torch.Tensor))
+            s = cg.sizes(h.n, h.m, h.seq.shape[0], P, coords)
+            assert s["graph"] == gb and s["outputs"] == ob, (coords, P)
+            assert s["scratch"] == cg.footprint(h.n, h.m, P)
+            assert serve.graph_bytes(h.n, h.m, h.seq.shape[0], coords) == gb
+            assert serve.output_bytes(h.n, P, int(h.seq.shape[0])) == ob
+            assert serve.request_footprint(h, P) == gb + ob
+            # a request on a resident graph holds its outputs only
+            assert serve.request_footprint(h, P, resident=True) == ob
 
 
 def test_busy_fraction_and_arrivals():
