@@ -337,6 +337,33 @@ int cg_induce(cg_ctx *ctx, const cg_graph *g, const uint8_t *flags, const int32_
 int cg_assemble(cg_ctx *ctx, const cg_graph *g, const cg_parts *parts, const cg_local *local,
                 int32_t P, const cg_contigs *out, void *stream);
 
+/* ---- without allocation ---------------------------------------------------- */
+
+/* Capacity of the allocation-free entry point: the graph's context scratch
+ * (cg_footprint's `scratch` figure) must fit in this many bytes. */
+#define CG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* ContigGeneration on one graph without a context and without allocating:
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Runs
+ * cg_mask_branches, cg_components, cg_partition, cg_induce and cg_assemble in
+ * that order on `stream` with the same kernels, and fills the same outputs
+ * (arguments as in those calls).  The scratch the steps need lives in a static
+ * device array of the library, CG_NOALLOC_SCRATCH_BYTES plus a few KB, one
+ * copy per GPU, held until the process ends; the call makes no allocation
+ * of any kind.  The first call on a device looks up that device's copy.
+ * d_status [device, optional] receives the CG_STATUS_* bits the call raised.
+ * Errors (before anything is enqueued): as the five calls; CG_EUNSUPPORTED
+ * when the graph needs more scratch than CG_NOALLOC_SCRATCH_BYTES.
+ * All calls on one GPU share its array, which keeps the last call's contents
+ * (each call clears what must start at zero): calls that overlap in time on
+ * one GPU (other streams or threads) race and give undefined results; calls
+ * one after another on one stream are safe. */
+int cg_contig_generation_noalloc(const cg_graph *g, int32_t P, int32_t min_reads, int32_t weight,
+                                 uint8_t *flags, int32_t *d_counts, int32_t *label,
+                                 const cg_parts *parts, const cg_local *local,
+                                 const cg_contigs *contigs, uint32_t *d_status, void *stream);
+
 /* ---- batched form -------------------------------------------------------- */
 
 /* One graph of a batch: its inputs, its parameters and the same output

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libcg.so")
-SOURCES = ["cg_api.cpp", "k_mask_cc.hip", "k_partition.hip", "k_induce.hip", "k_assemble.hip", "k_batch.hip",
+SOURCES = ["cg_api.cpp", "cg_noalloc.cpp", "k_mask_cc.hip", "k_partition.hip", "k_induce.hip", "k_assemble.hip", "k_batch.hip",
            "k_reduce.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

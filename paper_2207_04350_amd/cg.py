@@ -100,6 +100,9 @@ def lib():
                                           P(ctypes.c_int32), P(ctypes.c_int64)]
         L.cg_reduce.argtypes = [_vp, P(CgGraph), ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _vp]
+        L.cg_contig_generation_noalloc.argtypes = [P(CgGraph), ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.c_int32, _vp, _vp, _vp, P(CgParts),
+                                                   P(CgLocal), P(CgContigs), _vp, _vp]
         L.cg_batch_create.argtypes = [_vp, ctypes.c_int32, P(CgJob), P(CgBatchParams), P(_vp)]
         L.cg_batch_run.argtypes = [_vp, _vp]
         L.cg_batch_capture.argtypes = [_vp, _vp]
@@ -109,7 +112,7 @@ def lib():
                      "cg_batch_destroy", "cg_ctx_profile", "cg_ctx_profile_read",
                      "cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
                      "cg_validate", "cg_mask_branches", "cg_components", "cg_partition",
-                     "cg_induce", "cg_assemble", "cg_reduce"):
+                     "cg_induce", "cg_assemble", "cg_reduce", "cg_contig_generation_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -377,6 +380,19 @@ def run_path(ctx, dg, out, P, min_reads=2, stream=None, weight="reads"):
     partition(ctx, dg, out.flags, out.label, P, min_reads, out.parts, stream, weight)
     induce(ctx, dg, out.flags, out.label, out.parts, P, out.local, stream)
     assemble(ctx, dg, out.parts, out.local, P, out.contigs, stream)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def contig_generation_noalloc(dg, out, P, min_reads=2, stream=None, weight="reads",
+                              d_status=None):
+    """cg_contig_generation_noalloc: the five steps without a context and
+    without allocating (scratch in the library's static device array)."""
+    _check(lib().cg_contig_generation_noalloc(
+        ctypes.byref(dg.struct), int(P), int(min_reads), int(_weight(weight)), _ptr(out.flags),
+        _ptr(out.counts), _ptr(out.label), ctypes.byref(out.parts), ctypes.byref(out.local),
+        ctypes.byref(out.contigs), _ptr(d_status), _stream(stream)))
 
 
 def to_host(out, n):
