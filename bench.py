@@ -51,6 +51,10 @@ def algo_bytes(kernel, s):
         # flags + row_ptr + kept columns read; label updates not counted
         "k_cc_hook": N + 4 * N + 4 * m_nb,
         "k_cc_compress": 4 * N + 4 * N,
+        # the batched mask + components kernel: row_ptr, the columns of rows of
+        # degree <= 2, flags, labels and label_comp written, the component
+        # table (label, size, kind, member start) and the grouped members
+        "k_mask_cc": 4 * (N + 1) + 4 * m_nb + N + 4 * N + 4 * N + 13 * nc + 4 * n_e,
         "k_part_zero": 4 * N,
         "k_part_count": N + 4 * N,
         "k_part_compact": N + 4 * N + 4 * N + 9 * nc,
@@ -377,13 +381,14 @@ def main():
     def phases(kern):
         pick = lambda pred: sum(v[1] for k, v in kern.items() if pred(k))
         return {
-            # the batched form hooks in the mask pass
-            "mask": pick(lambda k: k in ("k_mask", "kb_mask_list")),
-            "components": pick(lambda k: k.startswith("k_cc") or k.startswith("kb_cc")),
-            "partition": pick(lambda k: k.startswith("k_part") or k.startswith("kb_compact")
-                              or k.startswith("kb_tilecount") or k in ("kb_lpt", "kb_tables")),
-            "induce": pick(lambda k: k.startswith("k_ind") or k.startswith("kb_fill")
-                           or k.startswith("kb_induce")),
+            # the batched form: degrees, bitmaps and lists over the whole chip
+            # (kb_mask_tiles), then kept entries, labels and the component
+            # table per graph (kb_mask_cc, counted here as components)
+            "mask": pick(lambda k: k in ("k_mask", "kb_mask_tiles")),
+            "components": pick(lambda k: k.startswith("k_cc") or k == "kb_mask_cc"),
+            "partition": pick(lambda k: k.startswith("k_part") or k.startswith("kb_weight")
+                              or k in ("kb_lpt", "kb_tables", "kb_wq_place")),
+            "induce": pick(lambda k: k.startswith("k_ind") or k.startswith("kb_induce")),
             "assemble": pick(lambda k: k.startswith("k_asm") or k.startswith("kb_walk")
                              or k in ("kb_offsets", "kb_copy")),
         }
@@ -403,7 +408,7 @@ def main():
     # rows, flags written, labels written (each array once)
     maskcc_bytes = 4 * (st["N"] + 1) + 4 * st["m_nb"] + st["N"] + 4 * st["N"]
 
-    mc = [profiled_traffic(k) for k in ("kb_mask_list", "kb_cc_prep", "kb_cc_local")]
+    mc = [profiled_traffic(k) for k in ("kb_mask_tiles", "kb_mask_cc")]
     maskcc_traffic = sum(mc) if all(t is not None for t in mc) and args.workload == "batch" else None
 
     def maskcc(ph):
@@ -426,9 +431,7 @@ def main():
     dom_map = {"kb_copy": ["k_asm_copy"], "kb_walk": ["k_asm_walk"], "kb_lpt": ["k_part_lpt"],
                "kb_walk_small": ["k_asm_walk"],
                "kb_induce": ["k_ind_local", "k_ind_rows"],
-               "kb_induce_small": ["k_ind_local", "k_ind_rows"], "kb_mask_list": ["k_mask"],
-               "kb_cc_local": ["k_cc_hook", "k_cc_compress"],
-               "kb_fill<T>": ["k_ind_fill"],
+               "kb_induce_small": ["k_ind_local", "k_ind_rows"],
                "kb_offsets": ["k_asm_offsets"]}
     dom_bytes = sum(algo_bytes(k, st) or 0 for k in dom_map.get(dom, [kname(dom)]))
     dom_bytes_per_launch = (dom_bytes or 0) / dom_launches
@@ -478,8 +481,10 @@ def main():
                     "hbm_frac": maskcc_bytes / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
                     if maskcc_ms else None,
                     "cold_median": maskcc(cold_ph), "warm_median": maskcc(warm_ph),
-                    "kernels": "kb_mask_list + kb_cc_prep + kb_cc_local (the last also builds the component "
-                               "table and groups members)",
+                    "kernels": "kb_mask_tiles (degrees, bitmaps and the reads of degree 1-2 "
+                               "with their columns, over the whole chip) + kb_mask_cc (one "
+                               "workgroup per graph: kept entries, union-find in LDS, labels, the "
+                               "component table and its members, label_comp of every read)",
                     # what the phase's kernels move in all (the calibrated
                     # counters of the committed profile): random lines and the
                     # arrays the later steps need, far above the fused minimum

@@ -367,7 +367,9 @@ int cg_contig_generation_noalloc(const cg_graph *g, int32_t P, int32_t min_reads
 /* ---- batched form -------------------------------------------------------- */
 
 /* One graph of a batch: its inputs, its parameters and the same output
- * buffers the single-graph calls fill (same sizes and meaning). */
+ * buffers the single-graph calls fill (same sizes and meaning).  The batched
+ * kernels move reads with 16-byte accesses: g.row_ptr, flags, label and
+ * parts.label_comp must be 16-byte aligned. */
 typedef struct {
   cg_graph g;
   int32_t P;          /* bins, 1..65536 */

@@ -1,19 +1,18 @@
 // Batched form: the five steps of Algorithm 2 for many independent string
 // graphs ("jobs") with one launch per phase for the whole batch.
 //
+//  mask + comps    one workgroup per job, largest first: branch flags,
+//                  components and the component table from LDS bitmaps
 //  vertex passes   each job is cut into tiles of T vertices; a launch covers
 //                  the tiles of every job (tile -> job table)
-//  compaction      reduce-then-scan per job: tiles count, then each tile adds
-//                  up the counts of the tiles before it in its job
 //  component and   persistent grids over the batch-wide item ranges
 //  piece passes    (components, pieces) whose per-job bases the last LPT
 //                  workgroup computes on the device; the per-component passes
 //                  take a work queue of every component of the batch in
 //                  decreasing read count
 //
-// Every counter a launch uses is reset by the launch itself, and the
-// union-find forest is reset by bumping its tag, so the launches (twelve, or
-// more when one-read components are eligible or weights are bases) can be
+// Every counter a launch uses is reset by the launch itself, so the
+// launches (ten, or eleven when a job partitions by bases weights) can be
 // captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
@@ -36,15 +35,8 @@ struct BJob {
   cg_local local;
   cg_contigs out;
   Scratch s;
-  uint64_t *forest;            // [n] tagged union-find forest (batch-owned, never reused)
-  int4 *conn_list;             // [n] reads of degree 1-2, each mask tile's reads packed in id
-                               // order at the start of its slice: (id, columns or -1, degree)
-                               // from the mask pass, then (id, s0, s1, kept bits) from the
-                               // neighbour pass, s_k the list slot of neighbour k when its
-                               // entry is kept and its id is smaller, else -1
-  int32_t *conn_map;           // [n] slot of a listed read in conn_list
   int32_t vt_first, vt_count;  // the job's vertex tiles (covering 0..n)
-  int32_t mt_first, mt_count;  // the job's mask tiles
+  int32_t mt_first, mt_count;  // the job's mask tiles (kb_mask_tiles)
   int32_t external;            // 1: the job runs through the single-graph kernels before the
                                // batched launches, which then leave it alone
   int32_t pad_;
@@ -68,30 +60,9 @@ __device__ __forceinline__ int32_t ld_const(const int32_t *a, int64_t i) {
   return ((const CG_CONST int32_t *)a)[i];
 }
 
-// One tile of the mask pass: kMaskTile consecutive reads of one job.
-struct MaskTile {
-  const int32_t *row_ptr;
-  const int32_t *col;
-  uint8_t *flags;
-  int32_t *label;
-  int32_t *label_comp;
-  int4 *conn_list;
-  int32_t *conn_map;
-  int2 *tile_cnt;   // (listed reads, branch reads) of this tile
-  int32_t n, v0;
-  int32_t lc_init;  // first value of label_comp: -1, or 4 (one-read count) when
-                    // one-read components can be eligible
-  int32_t pad_;
-};
-static_assert(sizeof(MaskTile) % 8 == 0, "tile descriptors are copied in 8-byte words");
-constexpr int kMaskThreads = 256;
-constexpr int kMaskGroups = 2;  // groups of 4 consecutive reads per thread
-constexpr int kMaskTile = 4 * kMaskThreads * kMaskGroups;
-
 struct BatchDev {
   BJob *jobs;                       // [n_jobs]
   int32_t *tile_job;                // [n_vtiles]
-  int32_t *tile_cnt;                // [n_vtiles] eligible roots per tile
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
   int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
@@ -105,10 +76,9 @@ struct BatchDev {
                                     // reads, 2: above kIndSmallCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
   int32_t *chunk_job;               // [sum of ceil(n / kChunkPieces)] job of each copy chunk
-  unsigned int *counters;           // [8] 2: LPT ticket, 3: runs so far (forest tag - 1)
-  int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
+  unsigned int *counters;           // [8] 2: LPT ticket
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
-  const MaskTile *mtiles;           // [n_mtiles]
+  int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
   Fixed *fixed;
   int32_t n_jobs, n_vtiles, n_mtiles;
 };
@@ -126,60 +96,109 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 }
 
 // ---------------------------------------------------------------------------
-// 1. mask (eight reads per thread as two 16-byte row_ptr sweeps): branch
-// flags, labels and label_comp initialised, and every read of degree 1-2
-// listed with its columns, packed per tile in id order by a block scan.
-// Whether an entry is kept needs the other end's branch bit, which the
-// job's components workgroup reads next, from the job's flags.
+// 1a. The reads of every job in tiles of kMaskTile, over the whole chip
+// (one workgroup's share of a job would get a sliver of the memory
+// bandwidth while all jobs stream at once): degree from row_ptr, the
+// "listed" (degree 1 or 2, the only reads that can keep an entry) and
+// "branch" (degree >= 3) bitmaps of the job, and every listed read with its
+// columns, packed per tile in id order by a block scan.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t forest_tag(const BatchDev &B) { return B.counters[3] + 1u; }
+struct MaskTile {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  int4 *list;        // the job's listed reads: tile t's at list[t * kMaskTile], as
+                     // (id, first column, second column or -1, degree)
+  uint32_t *bits;    // the job's bitmaps: W listed words, then W branch words
+  int2 *tile_cnt;    // (listed reads, branch reads) of this tile
+  int32_t n, v0, W, pad_;
+};
+static_assert(sizeof(MaskTile) % 8 == 0, "tile descriptors are copied in 8-byte words");
+constexpr int kMaskThreads = 256;
+constexpr int kMaskGroups = 2;  // groups of 4 consecutive reads per thread
+constexpr int kMaskTile = 4 * kMaskThreads * kMaskGroups;
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__restrict__ tiles) {
+__global__ __launch_bounds__(kMaskThreads) void kb_mask_tiles(const MaskTile *__restrict__ tiles) {
   __shared__ int64_t sh[kMaskThreads / kWave + 1];
-  const MaskTile D = tiles[blockIdx.x];
+  MaskTile D;
+  {
+    const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(tiles + blockIdx.x);
+    uint64_t *q = reinterpret_cast<uint64_t *>(&D);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(MaskTile) / 8); ++k) q[k] = p[k];
+  }
+  const CG_GLOBAL int32_t *rp = (const CG_GLOBAL int32_t *)D.row_ptr;
+  const CG_GLOBAL int32_t *col = (const CG_GLOBAL int32_t *)D.col;
+  CG_GLOBAL i32x4 *list = (CG_GLOBAL i32x4 *)D.list;
+  CG_GLOBAL uint32_t *bits = (CG_GLOBAL uint32_t *)D.bits;
   const int32_t n = D.n;
   const int lane = lane_id();
+  // every load issued before any is used: a group past the end loads the
+  // last whole group instead and is patched or ignored below
+  const int32_t last4 = n >= 3 ? (n - 3) & ~3 : 0;
   int32_t v0[kMaskGroups];
-  int4 a[kMaskGroups];
-#pragma unroll
-  for (int g = 0; g < kMaskGroups; ++g) {
-    v0[g] = D.v0 + g * 4 * kMaskThreads + 4 * (int32_t)threadIdx.x;
-    a[g] = make_int4(0, 0, 0, 0);
-    if (v0[g] + 3 <= n) {
-      a[g] = *(const int4 *)(D.row_ptr + v0[g]);
-    } else if (v0[g] <= n) {
-      a[g].x = D.row_ptr[v0[g]];
-      if (v0[g] + 1 <= n) a[g].y = D.row_ptr[v0[g] + 1];
-      if (v0[g] + 2 <= n) a[g].z = D.row_ptr[v0[g] + 2];
-    }
-  }
+  i32x4 a[kMaskGroups];
   int32_t e4[kMaskGroups];
 #pragma unroll
   for (int g = 0; g < kMaskGroups; ++g) {
-    e4[g] = __shfl_down(a[g].x, 1);
-    if (lane == kWave - 1 && v0[g] + 4 <= n) e4[g] = D.row_ptr[v0[g] + 4];
+    v0[g] = D.v0 + g * 4 * kMaskThreads + 4 * (int32_t)threadIdx.x;
+    a[g] = i32x4{0, 0, 0, 0};
+    if (n >= 3) a[g] = *(const CG_GLOBAL i32x4 *)(rp + (v0[g] + 3 <= n ? v0[g] : last4));
+    e4[g] = rp[lane == kWave - 1 && v0[g] + 4 <= n ? v0[g] + 4 : 0];
   }
-  constexpr int R = 4 * kMaskGroups;
-  int32_t dg[R], bb[R];
 #pragma unroll
   for (int g = 0; g < kMaskGroups; ++g) {
-    const int32_t rp[5] = {a[g].x, a[g].y, a[g].z, a[g].w, e4[g]};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      dg[4 * g + i] = v0[g] + i < n ? rp[i + 1] - rp[i] : 0;
-      bb[4 * g + i] = rp[i];
+    if (v0[g] + 3 > n && v0[g] <= n) {  // the job's last, partial group
+      a[g].x = rp[v0[g]];
+      if (v0[g] + 1 <= n) a[g].y = rp[v0[g] + 1];
+      if (v0[g] + 2 <= n) a[g].z = rp[v0[g] + 2];
     }
   }
+  constexpr int R = 4 * kMaskGroups;
+  int32_t dg[R], rs[R];
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    const int32_t nx = __shfl_down(a[g].x, 1);
+    const int32_t r[5] = {a[g].x, a[g].y, a[g].z, a[g].w, lane == kWave - 1 ? e4[g] : nx};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dg[4 * g + i] = v0[g] + i < n ? r[i + 1] - r[i] : 0;
+      rs[4 * g + i] = r[i];
+    }
+  }
+  // columns of the listed reads (rows of consecutive reads are consecutive)
   int32_t u0[R], u1[R];
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    u0[k] = (dg[k] == 1 || dg[k] == 2) ? D.col[bb[k]] : -1;
-    u1[k] = dg[k] == 2 ? D.col[bb[k] + 1] : -1;
+    u0[k] = (dg[k] == 1 || dg[k] == 2) ? col[rs[k]] : -1;
+    u1[k] = dg[k] == 2 ? col[rs[k] + 1] : -1;
+  }
+  // the bitmaps: a group's 4 reads are a nibble of word v0 / 32; eight lanes
+  // OR their nibbles into a word
+#pragma unroll
+  for (int g = 0; g < kMaskGroups; ++g) {
+    uint32_t ln = 0, bn = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ln |= (dg[4 * g + i] == 1 || dg[4 * g + i] == 2 ? 1u : 0u) << i;
+      bn |= (dg[4 * g + i] >= 3 ? 1u : 0u) << i;
+    }
+    uint32_t lb = ln << (4 * (lane & 7)), bb = bn << (4 * (lane & 7));
+    lb |= __shfl_xor(lb, 1);
+    bb |= __shfl_xor(bb, 1);
+    lb |= __shfl_xor(lb, 2);
+    bb |= __shfl_xor(bb, 2);
+    lb |= __shfl_xor(lb, 4);
+    bb |= __shfl_xor(bb, 4);
+    const int32_t w = v0[g] >> 5;
+    if ((lane & 7) == 0 && w < D.W) {
+      bits[w] = lb;
+      bits[D.W + w] = bb;
+    }
   }
   // listed reads packed in id order: group 0 of every thread precedes group
   // 1, so one scan of (listed, branch) counts of both groups, 16-bit fields
-  // (a tile holds fewer than 2^16 reads), gives every position.  The scan
-  // comes before any store: its barriers would wait for them.
+  // (a tile holds fewer than 2^16 reads), gives every position
   static_assert(kMaskGroups == 2, "two groups per scan");
   int64_t cnt = 0;
 #pragma unroll
@@ -195,481 +214,845 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_list(const MaskTile *__r
   int64_t tot;
   const int64_t ex = block_excl_scan<int64_t, kMaskThreads>(cnt, sh, &tot);
   const int32_t listed0 = (int32_t)(tot & 0xFFFF);
-  int32_t pos[kMaskGroups] = {D.v0 + (int32_t)(ex & 0xFFFF), D.v0 + listed0 + (int32_t)((ex >> 32) & 0xFFFF)};
+  int32_t pos[kMaskGroups] = {D.v0 + (int32_t)(ex & 0xFFFF),
+                              D.v0 + listed0 + (int32_t)((ex >> 32) & 0xFFFF)};
 #pragma unroll
-  for (int g = 0; g < kMaskGroups; ++g) {
-    uint32_t fw = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) fw |= (dg[4 * g + i] >= 3 ? 1u : 0u) << (8 * i);
-    const int32_t v = v0[g];
-    if (v + 3 < n) {
-      *(uint32_t *)(D.flags + v) = fw;
-      *(int4 *)(D.label + v) = make_int4(v, v + 1, v + 2, v + 3);
-      *(int4 *)(D.label_comp + v) = make_int4(D.lc_init, D.lc_init, D.lc_init, D.lc_init);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (v + i < n) {
-          D.flags[v + i] = (uint8_t)(fw >> (8 * i));
-          D.label[v + i] = v + i;
-          D.label_comp[v + i] = D.lc_init;
-        }
-    }
+  for (int g = 0; g < kMaskGroups; ++g)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 4 * g + i;
-      if (dg[k] == 1 || dg[k] == 2) {
-        D.conn_list[pos[g]] = make_int4(v0[g] + i, u0[k], u1[k], dg[k]);
-        D.conn_map[v0[g] + i] = pos[g];
-        ++pos[g];
-      }
+      if (dg[k] == 1 || dg[k] == 2) list[pos[g]++] = i32x4{v0[g] + i, u0[k], u1[k], dg[k]};
     }
-  }
-  if (threadIdx.x == 0)
-    *D.tile_cnt = make_int2(listed0 + (int32_t)((tot >> 32) & 0xFFFF),
-                            (int32_t)((tot >> 16) & 0xFFFF) + (int32_t)((tot >> 48) & 0xFFFF));
-}
-
-// 1b. the neighbour lookups of every listed read, spread over the whole chip
-// (done inside the components pass they would fall on one CU per job): kept
-// bits from the neighbours' branch bits, and the list slots of the kept
-// neighbours with smaller ids, written back into the read's list entry
-constexpr int kPrepChunks = kMaskTile / kMaskThreads;
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(kMaskThreads) void kb_cc_prep(const MaskTile *__restrict__ tiles) {
-  // the tile descriptor through the constant address space (scalar loads),
-  // its arrays as global memory
-  MaskTile D;
-  {
-    const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(tiles + blockIdx.x);
-    uint64_t *q = reinterpret_cast<uint64_t *>(&D);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(MaskTile) / 8); ++k) q[k] = p[k];
-  }
-  const int32_t c = ((const CG_GLOBAL int2 *)D.tile_cnt)->x;
-  if (c == 0) return;
-  CG_GLOBAL i32x4 *list = (CG_GLOBAL i32x4 *)D.conn_list + D.v0;
-  const CG_GLOBAL uint8_t *flags = (const CG_GLOBAL uint8_t *)D.flags;
-  const CG_GLOBAL int32_t *map = (const CG_GLOBAL int32_t *)D.conn_map;
-  // all loads of the thread's entries in flight before any is used; slots at
-  // or past c read slot 0 and are then treated as empty (a listed read's
-  // job has at least one read, so index 0 is in bounds)
-  i32x4 e[kPrepChunks];
-#pragma unroll
-  for (int k = 0; k < kPrepChunks; ++k) {
-    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
-    e[k] = list[i < c ? i : 0];
-  }
-  uint32_t b0[kPrepChunks], b1[kPrepChunks];
-  int32_t m0[kPrepChunks], m1[kPrepChunks];
-#pragma unroll
-  for (int k = 0; k < kPrepChunks; ++k) {
-    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
-    if (i >= c) e[k] = i32x4{-1, -1, -1, 0};
-    const int32_t u0 = e[k].y >= 0 ? e[k].y : 0, u1 = e[k].z >= 0 ? e[k].z : 0;
-    b0[k] = flags[u0];
-    b1[k] = flags[u1];
-    m0[k] = map[u0];
-    m1[k] = map[u1];
-  }
-#pragma unroll
-  for (int k = 0; k < kPrepChunks; ++k) {
-    const int32_t i = k * kMaskThreads + (int32_t)threadIdx.x;
-    if (i >= c) continue;
-    const bool k0 = e[k].y >= 0 && !(b0[k] & 1), k1 = e[k].z >= 0 && !(b1[k] & 1);
-    list[i] = i32x4{e[k].x, k0 && e[k].y < e[k].x ? m0[k] : -1, k1 && e[k].z < e[k].x ? m1[k] : -1,
-                    (k0 ? 2 : 0) | (k1 ? 4 : 0)};
+  if (threadIdx.x == 0) {
+    CG_GLOBAL int32_t *tc = (CG_GLOBAL int32_t *)D.tile_cnt;
+    tc[0] = listed0 + (int32_t)((tot >> 32) & 0xFFFF);
+    tc[1] = (int32_t)((tot >> 16) & 0xFFFF) + (int32_t)((tot >> 48) & 0xFFFF);
   }
 }
 
-// 2. components of each job in one workgroup, from its listed reads: kept
-// bits (both ends outside the branch set), union-find in LDS (roots =
-// smallest read id), labels, exact per-root counts, and, when one-read
-// components cannot be eligible (min_reads >= 2), the component table in
-// label order with each component's members grouped for the induce step.
-// A listed read's local number is its tile's offset plus its slot in the
-// tile, which orders local numbers like read ids, so the smaller local
-// number is the smaller id.  A job with more listed reads (or mask tiles)
-// than LDS holds uses the tagged global forest instead.  Largest jobs are
-// dispatched first.
-constexpr int kCcBlock = 1024;
-constexpr int kCcCap = 16384;
-constexpr int kCcPer = kCcCap / kCcBlock;
-constexpr int kCcTileCap = 1024;
-// jobs with more directed entries go through the single-graph kernels
-constexpr int64_t kExternalEntries = 2 * (int64_t)kCcCap;
+// ---------------------------------------------------------------------------
+// 1. BranchRemoval, ConnectedComponent and the component table of each job in
+// one workgroup (Sections 4.2 and 4.3), largest jobs dispatched first.
+//
+// A job's reads are cut into words of 32 consecutive reads and each thread
+// owns a contiguous run of words, so its reads, and the local numbers of its
+// listed reads (below), are contiguous and in id order.  A thread's work
+// follows what its words hold: a word without a read of degree 1-2 costs a
+// few instructions for all 32 reads.
+//  A  row_ptr of the thread's words: the bitmaps "listed" (degree 1 or 2,
+//     the only reads that can keep an entry) and "branch" (degree >= 3)
+//  B  listed reads before each word (one block scan): a listed read's local
+//     number is its rank among the job's listed reads, so local numbers
+//     follow read ids
+//  C  each listed read's entries: kept when the other end is not a branch
+//     read; the other end's local number from the bitmaps
+//  D  union-find over local numbers (larger root under smaller, so a root is
+//     its component's smallest id): a read first points at its smallest kept
+//     neighbour below it, and only an edge that leaves open is hooked
+//  E  roots and per-root counts (4 per read + 1 per path end)
+//  H  flags, labels and label_comp of every read as 16-byte stores of whole
+//     words (what a read of degree 1-2 changes is stored after)
+//  F  eligible components in label order (one scan over the threads' runs)
+//     and each component's members grouped for the induce step
+// The listed reads' state (entry, forest/counter, hook/root) is in LDS, or
+// in the job's scratch for a job with more listed reads than LDS holds.
+// ---------------------------------------------------------------------------
+constexpr int kMcBlock = 1024;
+constexpr int kMcReadCap = 131072;               // reads of a job (LDS bitmaps)
+constexpr int kMcWords = kMcReadCap / 32;
+constexpr int kMcMaxWpt = kMcWords / kMcBlock;   // words per thread at most
+constexpr int kMcListCap = 9216;                 // listed reads held in LDS
+constexpr int kMcPer = kMcListCap / kMcBlock;    // listed reads per thread at most in LDS
+// jobs with more directed entries or reads go through the single-graph
+// kernels (with at most this many entries a job's listed reads fit in LDS
+// unless most of its reads have degree 1)
+constexpr int64_t kExternalEntries = 2 * (int64_t)kMcListCap;
 constexpr int32_t kNotEligible = -(1 << 30);
+constexpr uint32_t kIdMask = (1u << 30) - 1;     // low bits of a listed read's entry: its id
 
-__device__ __forceinline__ int lds_find(int32_t *par, int x) {
-  volatile int32_t *vp = par;
-  while (true) {
-    const int p = vp[x];
-    if (p == x) return x;
-    const int gp = vp[p];
-    if (gp == p) return p;
-    vp[x] = gp;  // path halving: gp is an ancestor of x
-    x = gp;
-  }
-}
-
-// link the larger root under the smaller one
-__device__ __forceinline__ void lds_union(int32_t *par, int a, int b) {
-  while (true) {
-    a = lds_find(par, a);
-    b = lds_find(par, b);
-    if (a == b) return;
-    const int hi = a > b ? a : b;
-    const int lo = a > b ? b : a;
-    if (atomicCAS(par + hi, hi, lo) == hi) return;
-  }
+// a barrier that orders LDS accesses only (global stores stay in flight)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ uint8_t kind_of(uint32_t c4) {
   return (c4 >> 2) == 1 ? CG_KIND_SINGLE : ((c4 & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
 }
 
-__device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *tc,
-                          int64_t *sh64, int64_t *m_l_out);
+// Listed reads' state: entry (id | kept bits << 30); `a`: forest parent, then
+// per-root counter, then member cursor; `b`: hook target, then root (or
+// ~component for a numbered root).  In LDS, or in the job's scratch.
+template <bool kLds>
+struct McArr;
+template <>
+struct McArr<true> {
+  uint32_t *lid;
+  int32_t *a;
+  int32_t *b;
+  static constexpr bool lds = true;
+};
+template <>
+struct McArr<false> {
+  CG_GLOBAL uint32_t *lid;
+  CG_GLOBAL int32_t *a;
+  CG_GLOBAL int32_t *b;
+  static constexpr bool lds = false;
+};
 
-__global__ __launch_bounds__(kCcBlock) void kb_cc_local(BatchDev B) {
-  __shared__ int32_t s_par[kCcCap], s_aux[kCcCap];
-  __shared__ int32_t s_pref[kCcTileCap + 1];
-  __shared__ int64_t sh64[kCcBlock / kWave + 1];
+// relaxed atomics of the union-find: workgroup scope in LDS; device scope in
+// global memory
+__device__ __forceinline__ int32_t mc_ld(int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t mc_ld(CG_GLOBAL int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void mc_st(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void mc_st(CG_GLOBAL int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool mc_cas(int32_t *p, int32_t *expect, int32_t v) {
+  return __hip_atomic_compare_exchange_strong(p, expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool mc_cas(CG_GLOBAL int32_t *p, int32_t *expect, int32_t v) {
+  return __hip_atomic_compare_exchange_strong(p, expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t mc_add(int32_t *p, int32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int32_t mc_add(CG_GLOBAL int32_t *p, int32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename P>
+__device__ __forceinline__ int32_t mc_find(P par, int32_t x) {
+  while (true) {
+    const int32_t p = mc_ld(par + x);
+    if (p == x) return x;
+    const int32_t gp = mc_ld(par + p);
+    if (gp == p) return p;
+    mc_st(par + x, gp);  // path halving: gp is an ancestor of x
+    x = gp;
+  }
+}
+
+// link the larger root under the smaller one; a failed link climbs to the
+// parent the root got meanwhile
+template <typename P>
+__device__ __forceinline__ void mc_union(P par, int32_t a, int32_t b) {
+  a = mc_find(par, a);
+  b = mc_find(par, b);
+  while (a != b) {
+    const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    int32_t expect = hi;
+    if (mc_cas(par + hi, &expect, lo)) return;
+    if (a == hi) a = expect;
+    else b = expect;
+  }
+}
+
+// The job's outputs and scratch arrays this kernel writes, typed as global
+// memory: stores through generic pointers would be flat stores, which the
+// LDS wait counter also counts, so every later LDS wait would wait for them.
+struct McOut {
+  CG_GLOBAL uint8_t *flags;
+  CG_GLOBAL int32_t *label;
+  CG_GLOBAL int32_t *label_comp;
+  CG_GLOBAL int32_t *comp_label;
+  CG_GLOBAL int32_t *comp_size;
+  CG_GLOBAL uint8_t *comp_kind;
+  CG_GLOBAL int32_t *memb;
+  CG_GLOBAL uint64_t *comp_w;
+  CG_GLOBAL int32_t *tmp;
+};
+
+__device__ __forceinline__ McOut mc_out(const BJob &J) {
+  return McOut{(CG_GLOBAL uint8_t *)J.flags,          (CG_GLOBAL int32_t *)J.label,
+               (CG_GLOBAL int32_t *)J.parts.label_comp, (CG_GLOBAL int32_t *)J.parts.comp_label,
+               (CG_GLOBAL int32_t *)J.parts.comp_size, (CG_GLOBAL uint8_t *)J.parts.comp_kind,
+               (CG_GLOBAL int32_t *)J.s.memb,          (CG_GLOBAL uint64_t *)J.s.comp_w,
+               (CG_GLOBAL int32_t *)J.s.tmp};
+}
+
+// component record cb: label, size, kind, first member slot; bases weight 0
+__device__ __forceinline__ void mc_component(const McOut &O, int32_t cb, int32_t label,
+                                             uint32_t c4, int32_t mb) {
+  O.comp_label[cb] = label;
+  O.comp_size[cb] = (int32_t)(c4 >> 2);
+  O.comp_kind[cb] = kind_of(c4);
+  O.memb[cb] = mb;
+  O.comp_w[cb] = 0;
+}
+
+// local number of listed read v: listed reads before its word, plus those
+// below it in the word
+__device__ __forceinline__ int32_t mc_rank(const uint32_t *lw, const int32_t *wp, int32_t v) {
+  const int w = v >> 5, b = v & 31;
+  return wp[w] + __popc(lw[w] & ((1u << b) - 1u));
+}
+
+// id of the listed read of local number l (l below the number of listed
+// reads; -1 otherwise)
+__device__ __forceinline__ int32_t mc_select(const uint32_t *lw, const int32_t *wp, int W,
+                                             int32_t l) {
+  int lo = 0, hi = W - 1;  // the last word whose prefix is at most l holds it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wp[mid] <= l) lo = mid;
+    else hi = mid - 1;
+  }
+  uint32_t bits = lw[lo];
+  for (int s = l - wp[lo]; s > 0 && bits; --s) bits &= bits - 1u;
+  return bits ? (lo << 5) + __builtin_ctz(bits) : -1;
+}
+
+// State of the listed reads as the sweep over all reads sees it: entry
+// (id | kept bits << 30), root (~component once numbered) and counter
+// (per-root count, then member cursor).
+template <bool kLds>
+struct McState;
+template <>
+struct McState<true> {
+  uint32_t *lid;
+  int32_t *par;
+  int32_t *cnt;
+};
+template <>
+struct McState<false> {
+  CG_GLOBAL uint32_t *lid;
+  CG_GLOBAL int32_t *par;
+  CG_GLOBAL int32_t *cnt;
+};
+
+// The outputs of one read of a job for phase H (and, with one-read
+// components eligible, what numbering it needs): every LDS access happens
+// whatever the read is (indices stay in range), so the loads of a thread's
+// reads are issued together.
+struct McRead {
+  uint32_t fl;      // flags
+  int32_t lab;      // label
+  int32_t lcx;      // label_comp (-1 unless an eligible root already numbered)
+  int32_t loc;      // local number of a read with kept entries, else -1
+  int32_t root;     // root (local number) of a read with kept entries not yet numbered, else -1
+  uint32_t c4;      // what an unnumbered root counts (4 per read + path ends); 4 for one read
+  bool cand;        // not a branch read, not a member below a root: a component of its own
+};
+
+template <bool kLds>
+__device__ __forceinline__ McRead mc_read(int32_t v, int32_t n, uint32_t lw, uint32_t bw,
+                                          int32_t wp, const McState<kLds> &S) {
+  McRead r;
+  const int b = v & 31;
+  const bool live = v < n;
+  const bool listed = live && ((lw >> b) & 1u);
+  const uint32_t br = live ? (bw >> b) & 1u : 0u;
+  const int32_t l = listed ? wp + __popc(lw & ((1u << b) - 1u)) : 0;
+  const uint32_t x = S.lid[l];
+  const int32_t p = S.par[l];
+  const uint32_t c = (uint32_t)S.cnt[l];
+  const uint32_t y = S.lid[p >= 0 ? p : l];
+  const uint32_t kept = listed ? x >> 30 : 0u;
+  r.fl = br | (kept << 1);
+  r.lab = v;
+  r.lcx = -1;
+  r.loc = kept ? l : -1;
+  r.root = -1;
+  r.c4 = 4;
+  r.cand = live && !br;
+  if (kept) {
+    if (p >= 0 && p != l) {  // a member: its root comes earlier in id order
+      r.root = p;
+      r.lab = (int32_t)(y & kIdMask);
+      r.cand = false;
+    } else if (p < 0) {      // a root numbered by the listed scan
+      r.lcx = ~p;
+      r.cand = false;
+    } else {                 // a root not numbered yet
+      r.root = l;
+      r.c4 = c;
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ void mc_store4(const McOut &O, int32_t v4, int32_t n, const McRead *r) {
+  if (v4 + 3 < n) {
+    *(CG_GLOBAL uint32_t *)(O.flags + v4) =
+        r[0].fl | (r[1].fl << 8) | (r[2].fl << 16) | (r[3].fl << 24);
+    *(CG_GLOBAL i32x4 *)(O.label + v4) = i32x4{r[0].lab, r[1].lab, r[2].lab, r[3].lab};
+    *(CG_GLOBAL i32x4 *)(O.label_comp + v4) = i32x4{r[0].lcx, r[1].lcx, r[2].lcx, r[3].lcx};
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (v4 + i < n) {
+        O.flags[v4 + i] = (uint8_t)r[i].fl;
+        O.label[v4 + i] = r[i].lab;
+        O.label_comp[v4 + i] = r[i].lcx;
+      }
+  }
+}
+
+// F when one-read components are eligible, with H: every read in id order,
+// 4096 per round; the eligible components are numbered in label order
+// (one-read components included) and members claim their slots.
+template <bool kLds>
+__device__ __forceinline__ int32_t mc_sweep_table(int32_t n, int32_t min_reads, const McOut &O,
+                                                  const uint32_t *lw, const uint32_t *bw,
+                                                  const int32_t *wp, const McState<kLds> &S,
+                                                  int64_t *sh64) {
+  const int32_t mr = min_reads < 1 ? 1 : min_reads;
+  int32_t cbase = 0, mbase = 0;
+  for (int32_t base = 0; base < n; base += 4 * kMcBlock) {
+    const int32_t v4 = base + 4 * (int32_t)threadIdx.x;
+    const int w = v4 < n ? v4 >> 5 : 0;
+    McRead r[4];
+    int64_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      r[i] = mc_read<kLds>(v4 + i, n, lw[w], bw[w], wp[w], S);
+      if (r[i].cand && (int32_t)(r[i].c4 >> 2) >= mr)
+        cnt += ((int64_t)1 << 32) | (int64_t)(r[i].c4 >> 2);
+      else
+        r[i].cand = false;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kMcBlock>(cnt, sh64, &tot);
+    int32_t cb = cbase + (int32_t)(ex >> 32), mb = mbase + (int32_t)(ex & 0xFFFFFFFF);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!r[i].cand) continue;
+      const int32_t v = v4 + i;
+      mc_component(O, cb, v, r[i].c4, mb);
+      r[i].lcx = cb;
+      if (r[i].loc >= 0) {
+        S.par[r[i].loc] = ~cb;
+        S.cnt[r[i].loc] = mb;  // member cursor, the root's own slot included
+      } else {
+        O.tmp[mb] = v;  // a one-read component is its own member
+      }
+      ++cb;
+      mb += (int32_t)(r[i].c4 >> 2);
+    }
+    cbase += (int32_t)(tot >> 32);
+    mbase += (int32_t)(tot & 0xFFFFFFFF);
+    if (kLds) lds_barrier();
+    else __syncthreads();
+    // members (the roots of this round included) claim their slots
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (r[i].root < 0) continue;
+      int32_t at;
+      if constexpr (kLds) at = atomicAdd(S.cnt + r[i].root, 1);
+      else at = mc_add(S.cnt + r[i].root, 1);
+      if (at >= 0) O.tmp[at] = v4 + i;
+    }
+    if (v4 < n) mc_store4(O, v4, n, r);
+  }
+  return cbase;
+}
+
+// H (for jobs whose listed reads are in LDS, after F and G): flags, labels
+// and label_comp of every read, four consecutive reads per lane (16-byte
+// stores, consecutive across a wave); reads of degree 1-2 look up their
+// state: kept bits, a member's label (its root's id), a numbered root's
+// component.  All loads of the kernel are done by now: gfx9 counts stores
+// and loads in one counter, so a load behind these stores would wait for
+// them.
+__device__ __forceinline__ void mc_write_lds(int32_t n, const McOut &O, const uint32_t *lw,
+                                             const uint32_t *bw, const int32_t *wp,
+                                             const uint32_t *s_lid, const int32_t *s_b) {
+  constexpr int R = 2;  // groups of four reads per thread per round, their lookups together
+  for (int32_t base = 0; base < n; base += 4 * kMcBlock * R) {
+    int32_t v4[R];
+    uint32_t fw[R];
+    int32_t lab[R][4], lcx[R][4];
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
+      v4[g] = base + 4 * ((int32_t)threadIdx.x + g * kMcBlock);
+      const int w = v4[g] < n ? v4[g] >> 5 : 0, sh = v4[g] & 31;
+      const uint32_t lword = lw[w];
+      const uint32_t ln = v4[g] < n ? (lword >> sh) & 15u : 0u;
+      fw[g] = (((bw[w] >> sh) & 15u) * 0x00204081u) & 0x01010101u;  // branch bit i to byte i
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lab[g][i] = v4[g] + i;
+        lcx[g][i] = -1;
+      }
+      if (ln) {
+        int32_t l = wp[w] + __popc(lword & ((1u << sh) - 1u));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (!((ln >> i) & 1u)) continue;
+          const uint32_t kept = s_lid[l] >> 30;
+          const int32_t rt = s_b[l];
+          if (kept) {
+            fw[g] |= kept << (8 * i + 1);
+            if (rt < 0) lcx[g][i] = ~rt;
+            else if (rt != l) lab[g][i] = (int32_t)(s_lid[rt] & kIdMask);
+          }
+          ++l;
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
+      const int32_t v = v4[g];
+      if (v >= n) continue;
+      if (v + 3 < n) {
+        *(CG_GLOBAL uint32_t *)(O.flags + v) = fw[g];
+        *(CG_GLOBAL i32x4 *)(O.label + v) = i32x4{lab[g][0], lab[g][1], lab[g][2], lab[g][3]};
+        *(CG_GLOBAL i32x4 *)(O.label_comp + v) =
+            i32x4{lcx[g][0], lcx[g][1], lcx[g][2], lcx[g][3]};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (v + i < n) {
+            O.flags[v + i] = (uint8_t)(fw[g] >> (8 * i));
+            O.label[v + i] = lab[g][i];
+            O.label_comp[v + i] = lcx[g][i];
+          }
+      }
+    }
+  }
+}
+
+// C-H for a job with more listed reads than LDS holds: the listed reads
+// [lo, hi) of this thread (those of its words [w0, w1)) with their state in
+// the job's scratch.  Returns the job's component count.
+template <bool kLds>
+__device__ __forceinline__ int32_t mc_components(
+    const BJob &J, const McOut &O, const McArr<kLds> &A, const uint32_t *lw, const uint32_t *bw,
+    const int32_t *wp, int32_t w0, int32_t w1, int32_t lo, int32_t hi, int64_t *sh64,
+    int32_t *s_ml) {
+  const int32_t n = J.g.n;
+  const CG_GLOBAL int32_t *rp = (const CG_GLOBAL int32_t *)J.g.row_ptr;
+  const CG_GLOBAL int32_t *col = (const CG_GLOBAL int32_t *)J.g.col;
+  auto barrier = [] {
+    if (kLds) lds_barrier();
+    else __syncthreads();
+  };
+  // C. entries of each listed read: kept bits, first pointer, hook
+  {
+    int32_t m_l = 0;
+    int32_t l = lo;  // this thread's listed reads, in order, by walking its words' bits
+    for (int32_t w = w0; w < w1; ++w) {
+      for (uint32_t bits = lw[w]; bits; bits &= bits - 1u, ++l) {
+        const int32_t v = (w << 5) + __builtin_ctz(bits);
+        const int32_t ra = rp[v], d = rp[v + 1] - ra;  // d is 1 or 2
+        const int32_t c0 = col[ra], c1 = d == 2 ? col[ra + 1] : -1;
+        uint32_t kept = 0;
+        int32_t nb[2] = {-1, -1};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int32_t c = j ? c1 : c0;
+          if (c < 0) continue;
+          const int cw = c >> 5, cb = c & 31;
+          // kept: the other end is not a branch read (on a valid graph it is
+          // then listed, which its local number needs; checked all the same)
+          if (((bw[cw] >> cb) & 1u) || !((lw[cw] >> cb) & 1u)) continue;
+          kept |= 1u << j;
+          nb[j] = wp[cw] + __popc(lw[cw] & ((1u << cb) - 1u));
+        }
+        const int32_t s0 = nb[0] >= 0 && nb[0] < l ? nb[0] : l;
+        const int32_t s1 = nb[1] >= 0 && nb[1] < l ? nb[1] : l;
+        A.lid[l] = (uint32_t)v | (kept << 30);
+        A.a[l] = s0 < s1 ? s0 : s1;                                // first pointer
+        A.b[l] = (s0 < l && s1 < l) ? (s0 < s1 ? s1 : s0) : -1;  // the edge it leaves open
+        m_l += __popc(kept);
+      }
+    }
+    const int32_t wm = (int32_t)wave_sum((int64_t)m_l);
+    if (lane_id() == 0 && wm) atomicAdd(s_ml, wm);
+  }
+  barrier();
+  // D. hooks
+  for (int32_t l = lo; l < hi; ++l) {
+    const int32_t o = A.b[l];
+    if (o >= 0) mc_union(A.a, l, o);
+  }
+  barrier();
+  // E. roots, then per-root counts
+  for (int32_t l = lo; l < hi; ++l) A.b[l] = (A.lid[l] >> 30) ? mc_find(A.a, l) : l;
+  barrier();
+  for (int32_t l = lo; l < hi; ++l) A.a[l] = 0;
+  barrier();
+  for (int32_t l = lo; l < hi; ++l) {
+    const uint32_t kept = A.lid[l] >> 30;
+    if (kept) mc_add(A.a + A.b[l], 4 + (__popc(kept) == 1 ? 1 : 0));
+  }
+  barrier();
+  // H. every read of the thread's words: branch bits, label = own id,
+  // label_comp = -1 (16-byte stores; the job's last word read by read)
+  for (int32_t w = w0; w < w1; ++w) {
+    const int32_t v0 = w << 5;
+    const uint32_t br = bw[w];
+    if (v0 + 32 <= n) {
+#pragma unroll
+      for (int k = 0; k < 8; k += 4) {
+        // four reads per flag word: branch bit i of the nibble to byte i
+        const uint32_t f0 = (((br >> (4 * k)) & 15u) * 0x00204081u) & 0x01010101u;
+        const uint32_t f1 = (((br >> (4 * k + 4)) & 15u) * 0x00204081u) & 0x01010101u;
+        const uint32_t f2 = (((br >> (4 * k + 8)) & 15u) * 0x00204081u) & 0x01010101u;
+        const uint32_t f3 = (((br >> (4 * k + 12)) & 15u) * 0x00204081u) & 0x01010101u;
+        *(CG_GLOBAL i32x4 *)(O.flags + v0 + 4 * k) =
+            i32x4{(int32_t)f0, (int32_t)f1, (int32_t)f2, (int32_t)f3};
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int32_t v = v0 + 4 * k;
+        *(CG_GLOBAL i32x4 *)(O.label + v) = i32x4{v, v + 1, v + 2, v + 3};
+        *(CG_GLOBAL i32x4 *)(O.label_comp + v) = i32x4{-1, -1, -1, -1};
+      }
+    } else {
+      for (int32_t v = v0; v < n; ++v) {
+        O.flags[v] = (uint8_t)((br >> (v - v0)) & 1u);
+        O.label[v] = v;
+        O.label_comp[v] = -1;
+      }
+    }
+  }
+  // F. eligible components in label order, numbered from the threads' runs
+  // (one scan), member cursors in `a`, ~component in `b` of a numbered root
+  int32_t n_comp;
+  if (J.min_reads >= 2) {
+    int64_t cnt = 0;
+    for (int32_t l = lo; l < hi; ++l)
+      if ((A.lid[l] >> 30) && A.b[l] == l && (A.a[l] >> 2) >= J.min_reads)
+        cnt += ((int64_t)1 << 32) | (int64_t)(A.a[l] >> 2);
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kMcBlock>(cnt, sh64, &tot);
+    int32_t cb = (int32_t)(ex >> 32), mb = (int32_t)(ex & 0xFFFFFFFF);
+    for (int32_t l = lo; l < hi; ++l) {
+      if (!(A.lid[l] >> 30) || A.b[l] != l) continue;
+      const uint32_t c4 = (uint32_t)A.a[l];
+      if ((int32_t)(c4 >> 2) >= J.min_reads) {
+        mc_component(O, cb, (int32_t)(A.lid[l] & kIdMask), c4, mb);
+        A.b[l] = ~cb;
+        A.a[l] = mb;
+        ++cb;
+        mb += (int32_t)(c4 >> 2);
+      } else {
+        A.a[l] = kNotEligible;
+      }
+    }
+    n_comp = (int32_t)(tot >> 32);
+  } else {
+    // one-read components are eligible too: every read that is not a branch
+    // read and not a member below a root is a component of its own
+    const int32_t mr = J.min_reads < 1 ? 1 : J.min_reads;  // at most 1 here
+    uint32_t sm[kMcMaxWpt], rm[kMcMaxWpt];  // one-read and root masks of each word
+    int64_t cnt = 0;
+    {
+      int32_t l = lo;
+#pragma unroll
+      for (int k = 0; k < kMcMaxWpt; ++k) {
+        const int32_t w = w0 + k;
+        sm[k] = rm[k] = 0;
+        if (w >= w1) continue;
+        const int32_t v0 = w << 5;
+        const uint32_t valid = v0 + 32 <= n ? ~0u : ((1u << (n - v0)) - 1u);
+        sm[k] = valid & ~bw[w] & ~lw[w];
+        for (uint32_t bits = lw[w]; bits; bits &= bits - 1u, ++l) {
+          const uint32_t bit = bits & (0u - bits);
+          if (!(A.lid[l] >> 30)) {
+            sm[k] |= bit;
+          } else if (A.b[l] == l && (A.a[l] >> 2) >= mr) {
+            rm[k] |= bit;
+            cnt += (int64_t)(A.a[l] >> 2) - 1;  // the root's reads beyond one
+          }
+        }
+        cnt += (int64_t)__popc(sm[k] | rm[k]) * (((int64_t)1 << 32) | 1);
+      }
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kMcBlock>(cnt, sh64, &tot);
+    int32_t cb = (int32_t)(ex >> 32), mb = (int32_t)(ex & 0xFFFFFFFF);
+    int32_t l = lo;
+#pragma unroll
+    for (int k = 0; k < kMcMaxWpt; ++k) {
+      const int32_t w = w0 + k;
+      if (w >= w1) continue;
+      const int32_t v0 = w << 5;
+      const uint32_t lwk = lw[w];
+      for (uint32_t bits = sm[k] | rm[k]; bits; bits &= bits - 1u) {
+        const int b = __builtin_ctz(bits);
+        const int32_t v = v0 + b;
+        uint32_t c4 = 4;
+        if ((rm[k] >> b) & 1u) {
+          const int32_t lr = l + __popc(lwk & ((1u << b) - 1u));
+          c4 = (uint32_t)A.a[lr];
+          A.b[lr] = ~cb;
+          A.a[lr] = mb;  // member cursor, the root's own slot included
+        } else {
+          O.tmp[mb] = v;  // a one-read component is its own member
+        }
+        mc_component(O, cb, v, c4, mb);
+        O.label_comp[v] = cb;
+        ++cb;
+        mb += (int32_t)(c4 >> 2);
+      }
+      l += __popc(lwk);
+    }
+    n_comp = (int32_t)(tot >> 32);
+  }
+  barrier();
+  // G. members claim their slots; what the listed reads change in H's
+  // stores: kept bits, a member's label, a numbered root's label_comp
+  for (int32_t l = lo; l < hi; ++l) {
+    const uint32_t x = A.lid[l];
+    const uint32_t kept = x >> 30;
+    if (!kept) continue;
+    const int32_t v = (int32_t)(x & kIdMask);
+    const int32_t rt = A.b[l];
+    const int32_t r = rt < 0 ? l : rt;
+    const int32_t at = mc_add(A.a + r, 1);
+    if (at >= 0) O.tmp[at] = v;
+    O.flags[v] = (uint8_t)(kept << 1);
+    if (rt < 0) O.label_comp[v] = ~rt;
+    else if (rt != l) O.label[v] = (int32_t)(A.lid[rt] & kIdMask);
+  }
+  return n_comp;
+}
+
+// C-G for the listed reads of this thread, their state in LDS: slot k holds
+// local number tid + k * kMcBlock (below L), so that the slots' loads of the
+// tile lists are contiguous across a wave; PER is the listed reads per thread
+// rounded up to 1, 2, 4 or kMcPer, so that a job does the work of its own
+// reads.  Returns the job's component count (eligible components at
+// min_reads >= 2; otherwise they are numbered by the sweep over all reads).
+template <int PER>
+__device__ __forceinline__ int32_t mc_listed(const BJob &J, const McOut &O, int32_t L,
+                                             int32_t W, const uint32_t *lw, const uint32_t *bw,
+                                             const int32_t *wp, uint32_t *s_lid, int32_t *s_a,
+                                             int32_t *s_b, int64_t *sh64, int32_t *s_ml) {
+  const int tid = threadIdx.x;
+  int32_t ls[PER];  // local number of slot k, or -1
+#pragma unroll
+  for (int k = 0; k < PER; ++k) ls[k] = tid + k * kMcBlock < L ? tid + k * kMcBlock : -1;
+  // C. each read's id and columns from its tile's list (tile t's listed
+  // reads hold local numbers from the prefix of its first word on), then
+  // kept bits and the other ends' local numbers from the bitmaps
+  int32_t id[PER], c0[PER], c1[PER];
+  {
+    constexpr int kTileWords = kMaskTile / 32;
+    const int32_t nt = J.mt_count;
+    const CG_GLOBAL i32x4 *list = (const CG_GLOBAL i32x4 *)J.s.walk;
+    int32_t slot[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int32_t l = ls[k] >= 0 ? ls[k] : 0;
+      int32_t a = 0, b = nt - 1;  // the last tile whose first local number is at most l
+      while (a < b) {
+        const int32_t mid = (a + b + 1) >> 1;
+        if (wp[mid * kTileWords] <= l) a = mid;
+        else b = mid - 1;
+      }
+      slot[k] = a * kMaskTile + (l - wp[a * kTileWords]);
+    }
+    i32x4 e[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) e[k] = list[slot[k]];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      id[k] = ls[k] >= 0 ? e[k].x : -1;
+      c0[k] = ls[k] >= 0 ? e[k].y : -1;
+      c1[k] = ls[k] >= 0 ? e[k].z : -1;
+    }
+  }
+  uint32_t kept[PER];
+  int32_t hook[PER];
+  {
+    int32_t m_l = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int32_t l = ls[k];
+      // kept: the other end is not a branch read (on a valid graph it is
+      // then listed, which its local number needs; checked all the same)
+      const int32_t x0 = c0[k] >= 0 ? c0[k] : 0, x1 = c1[k] >= 0 ? c1[k] : 0;
+      const uint32_t b0 = bw[x0 >> 5], b1 = bw[x1 >> 5];
+      const uint32_t w0 = lw[x0 >> 5], w1 = lw[x1 >> 5];
+      const int32_t f0 = wp[x0 >> 5], f1 = wp[x1 >> 5];
+      const bool k0 = c0[k] >= 0 && !((b0 >> (x0 & 31)) & 1u) && ((w0 >> (x0 & 31)) & 1u);
+      const bool k1 = c1[k] >= 0 && !((b1 >> (x1 & 31)) & 1u) && ((w1 >> (x1 & 31)) & 1u);
+      kept[k] = (k0 ? 1u : 0u) | (k1 ? 2u : 0u);
+      const int32_t n0 = k0 ? f0 + __popc(w0 & ((1u << (x0 & 31)) - 1u)) : l;
+      const int32_t n1 = k1 ? f1 + __popc(w1 & ((1u << (x1 & 31)) - 1u)) : l;
+      const int32_t s0 = n0 < l ? n0 : l, s1 = n1 < l ? n1 : l;
+      // first pointer: the smallest kept neighbour below l; the edge to the
+      // other one, when both lie below, is the hook left open
+      hook[k] = (s0 < l && s1 < l) ? (s0 < s1 ? s1 : s0) : -1;
+      if (l < 0) continue;
+      s_lid[l] = (uint32_t)id[k] | (kept[k] << 30);
+      s_a[l] = s0 < s1 ? s0 : s1;
+      m_l += __popc(kept[k]);
+    }
+    const int32_t wm = (int32_t)wave_sum((int64_t)m_l);
+    if (lane_id() == 0 && wm) atomicAdd(s_ml, wm);
+  }
+  lds_barrier();
+  // D. hooks, one after the other
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (hook[k] >= 0) mc_union(s_a, ls[k], hook[k]);
+  lds_barrier();
+  // E. roots (lockstep climbs), then per-root counts
+  int32_t r[PER];
+  {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) r[k] = ls[k] >= 0 ? ls[k] : 0;
+    bool more = true;
+    while (more) {
+      more = false;
+      int32_t pr[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        pr[k] = mc_ld(s_a + r[k]);
+        if (!kept[k]) pr[k] = r[k];
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        if (pr[k] != r[k]) more = true;
+        r[k] = pr[k];
+      }
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (ls[k] < 0) continue;
+    s_b[ls[k]] = r[k];
+    s_a[ls[k]] = 0;
+  }
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (kept[k]) atomicAdd(s_a + r[k], 4 + (__popc(kept[k]) == 1 ? 1 : 0));
+  lds_barrier();
+  if (J.min_reads < 2) return 0;  // numbered by the sweep over all reads
+  // F. eligible roots in label order: each thread numbers a contiguous run of
+  // local numbers (which follow ids), one scan
+  const int per = (L + kMcBlock - 1) / kMcBlock;
+  const int32_t f0 = tid * per < L ? tid * per : L;
+  const int32_t f1 = f0 + per < L ? f0 + per : L;
+  int64_t c = 0;
+  for (int32_t l = f0; l < f1; ++l)
+    if ((s_lid[l] >> 30) && s_b[l] == l && (s_a[l] >> 2) >= J.min_reads)
+      c += ((int64_t)1 << 32) | (int64_t)(s_a[l] >> 2);
+  int64_t tot;
+  const int64_t ex = block_excl_scan<int64_t, kMcBlock>(c, sh64, &tot);
+  int32_t cb = (int32_t)(ex >> 32), mb = (int32_t)(ex & 0xFFFFFFFF);
+  for (int32_t l = f0; l < f1; ++l) {
+    if (!(s_lid[l] >> 30) || s_b[l] != l) continue;
+    const uint32_t c4 = (uint32_t)s_a[l];
+    if ((int32_t)(c4 >> 2) >= J.min_reads) {
+      mc_component(O, cb, (int32_t)(s_lid[l] & kIdMask), c4, mb);
+      s_b[l] = ~cb;
+      s_a[l] = mb;  // member cursor, the root's own slot included
+      ++cb;
+      mb += (int32_t)(c4 >> 2);
+    } else {
+      s_a[l] = kNotEligible;
+    }
+  }
+  lds_barrier();
+  // G. members claim their slots
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (!kept[k]) continue;
+    const int32_t at = atomicAdd(s_a + r[k], 1);
+    if (at >= 0) O.tmp[at] = id[k];
+  }
+  return (int32_t)(tot >> 32);
+}
+
+__global__ __launch_bounds__(kMcBlock) void kb_mask_cc(BatchDev B) {
+  __shared__ uint32_t s_lw[kMcWords], s_bw[kMcWords];
+  __shared__ int32_t s_wp[kMcWords];
+  __shared__ uint32_t s_lid[kMcListCap];
+  __shared__ int32_t s_a[kMcListCap], s_b[kMcListCap];
+  __shared__ int64_t sh64[kMcBlock / kWave + 1];
+  __shared__ int32_t s_ml;  // kept directed entries of the job
   const int j = ld_const(B.job_order, blockIdx.x);
   const BJob J = job_at(B.jobs, j);
   if (J.external) return;
-  const int nt = J.mt_count;
+  const int32_t n = J.g.n;
+  if (n > kMcReadCap) return;  // such a job is external (set when the batch is made)
   const int tid = threadIdx.x;
-  const bool table = J.min_reads >= 2;
-  const int2 *tc = B.mt_cnt + J.mt_first;
-  // listed reads per tile (prefix in LDS) and branch reads of the job
-  int64_t L = 0, n_branch = 0;
-  for (int base = 0; base < nt; base += kCcBlock) {
-    const int t = base + tid;
-    const int2 c = t < nt ? tc[t] : make_int2(0, 0);
-    int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t, kCcBlock>(((int64_t)c.y << 32) | c.x, sh64, &tot);
-    if (t < nt && nt <= kCcTileCap) s_pref[t] = (int32_t)(L + (ex & 0xFFFFFFFF));
-    L += tot & 0xFFFFFFFF;
-    n_branch += tot >> 32;
+  const McOut O = mc_out(J);
+  const int32_t W = (n + 31) >> 5;
+  const int32_t wpt = (W + kMcBlock - 1) / kMcBlock;  // at most kMcMaxWpt
+  const int32_t w0 = tid * wpt < W ? tid * wpt : W;
+  const int32_t w1 = w0 + wpt < W ? w0 + wpt : W;
+  if (tid == 0) s_ml = 0;
+  // A. the job's bitmaps (written by kb_mask_tiles) into LDS
+  {
+    const CG_GLOBAL uint32_t *bits = (const CG_GLOBAL uint32_t *)J.s.fill;
+    for (int32_t w = tid; w < W; w += kMcBlock) {
+      s_lw[w] = bits[w];
+      s_bw[w] = bits[W + w];
+    }
   }
-  if (tid == 0 && nt <= kCcTileCap) s_pref[nt] = (int32_t)L;
   __syncthreads();
-  int64_t m_l = 0;
-  if (L > 0 && (nt > kCcTileCap || L > kCcCap)) {
-    cc_global(B, B.jobs[j], nt, tc, sh64, &m_l);
-  } else if (L > 0) {
-    // All of this thread's loads are issued before any is used, and every
-    // global store waits for the tail: a barrier behind scattered stores
-    // waits for them to land.
-    const int per = (int)((L + kCcBlock - 1) / kCcBlock);
-    const int l0 = tid * per;
-    // 1. this thread's listed reads l0 .. l0 + per - 1: their slots in the
-    // tiles' lists, their entries, then their neighbours' branch bits and
-    // list slots
-    int32_t slot[kCcPer];
-    {
-      int lo = 0, hi = nt - 1;  // tile of local number l0
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pref[mid] <= l0) lo = mid;
-        else hi = mid - 1;
-      }
-      int t = lo;
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k) {
-        const int l = l0 + k;
-        slot[k] = -1;
-        if (k < per && l < L) {
-          while (s_pref[t + 1] <= l) ++t;
-          slot[k] = t * kMaskTile + (l - s_pref[t]);
-        }
-      }
-    }
-    int4 e[kCcPer];
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) e[k] = J.conn_list[slot[k] >= 0 ? slot[k] : 0];
-    uint32_t fk[kCcPer];
-    int32_t lu0[kCcPer], lu1[kCcPer];
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) {
-      const int l = l0 + k;
-      fk[k] = 0;
-      lu0[k] = lu1[k] = -1;
-      if (slot[k] >= 0) {
-        fk[k] = (uint32_t)e[k].w;
-        s_aux[l] = e[k].x;
-        s_par[l] = l;
-        if (e[k].y >= 0) lu0[k] = s_pref[e[k].y / kMaskTile] + e[k].y % kMaskTile;
-        if (e[k].z >= 0) lu1[k] = s_pref[e[k].z / kMaskTile] + e[k].z % kMaskTile;
-        m_l += __popc(fk[k]);
-      }
-    }
-    __syncthreads();
-    // 2. union-find over local numbers (the larger root under the smaller)
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) {
-      if (lu0[k] >= 0) lds_union(s_par, l0 + k, lu0[k]);
-      if (lu1[k] >= 0) lds_union(s_par, l0 + k, lu1[k]);
-    }
-    __syncthreads();
-    int32_t r[kCcPer];
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) r[k] = fk[k] ? lds_find(s_par, l0 + k) : l0 + k;
-    __syncthreads();
-    // 3. s_par becomes the per-root counter: 4 per read + 1 per path end
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k)
-      if (slot[k] >= 0) s_par[l0 + k] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k)
-      if (fk[k]) atomicAdd(s_par + r[k], 4 + (__popc(fk[k]) == 1 ? 1 : 0));
-    __syncthreads();
-    int32_t c4[kCcPer];  // own roots' counts (a read without kept entries: 4)
-    int32_t ne = 0, nq = 0;
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) {
-      const int l = l0 + k;
-      c4[k] = 0;
-      if (slot[k] >= 0) {
-        if (!fk[k]) c4[k] = 4;
-        else if (r[k] == l) c4[k] = s_par[l];
-        if (table && fk[k] && r[k] == l && (c4[k] >> 2) >= J.min_reads) {
-          ++ne;
-          nq += c4[k] >> 2;
-        }
-      }
-    }
-    // 4. one scan: eligible roots, their reads and the kept entries (21 bits each)
+  // B. listed reads before each word, and the branch reads of the job
+  int32_t lo, hi, L, n_branch;
+  {
+    int64_t x = 0;
+    for (int32_t w = w0; w < w1; ++w)
+      x += ((int64_t)__popc(s_lw[w]) << 32) | (int64_t)__popc(s_bw[w]);
     int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t, kCcBlock>(
-        ((int64_t)ne << 42) | ((int64_t)nq << 21) | m_l, sh64, &tot);
-    const int64_t kMask21 = (1 << 21) - 1;
-    if (table) {
-      int32_t cb = (int32_t)(ex >> 42), mb = (int32_t)((ex >> 21) & kMask21);
-      // s_par: member cursor of each eligible root, kNotEligible elsewhere
-#pragma unroll
-      for (int k = 0; k < kCcPer; ++k) {
-        const int l = l0 + k;
-        if (!fk[k] || r[k] != l) continue;
-        const int32_t id = s_aux[l];
-        if ((c4[k] >> 2) >= J.min_reads) {
-          const int32_t q = c4[k] >> 2;
-          J.parts.comp_label[cb] = id;
-          J.parts.comp_size[cb] = q;
-          J.parts.comp_kind[cb] = kind_of(c4[k]);
-          J.parts.label_comp[id] = cb;
-          J.s.memb[cb] = mb;
-          J.s.comp_w[cb] = 0;
-          s_par[l] = mb;
-          ++cb;
-          mb += q;
-        } else {
-          s_par[l] = kNotEligible;
-        }
-      }
-      __syncthreads();
+    const int64_t ex = block_excl_scan<int64_t, kMcBlock>(x, sh64, &tot);
+    lo = (int32_t)(ex >> 32);
+    hi = lo + (int32_t)(x >> 32);
+    int32_t run = lo;
+    for (int32_t w = w0; w < w1; ++w) {
+      s_wp[w] = run;
+      run += __popc(s_lw[w]);
     }
-    // 5. the tail: members, flags, labels, counts
-#pragma unroll
-    for (int k = 0; k < kCcPer; ++k) {
-      if (!fk[k]) continue;
-      const int32_t id = s_aux[l0 + k];
-      J.flags[id] = (uint8_t)fk[k];
-      J.label[id] = s_aux[r[k]];
-      if (table) {
-        const int32_t at = atomicAdd(s_par + r[k], 1);
-        if (at >= 0) J.s.tmp[at] = id;
-      } else {
-        J.parts.label_comp[id] = c4[k];  // 0 for non-roots
-      }
-    }
-    if (tid == 0) {
-      if (table) *J.parts.d_n_comp = (int32_t)(tot >> 42);
-      J.counts[0] = (int32_t)n_branch;
-      J.counts[1] = (int32_t)(tot & kMask21);
-    }
-    return;
+    L = (int32_t)(tot >> 32);
+    n_branch = (int32_t)(tot & 0xFFFFFFFF);
   }
-  if (L == 0 && table && tid == 0) *J.parts.d_n_comp = 0;
-  // BranchRemoval's counts: branch reads and kept entries
-  int64_t tm;
-  (void)block_excl_scan<int64_t, kCcBlock>(m_l, sh64, &tm);
+  lds_barrier();
+  int32_t n_comp = 0;
+  if (L <= kMcListCap) {
+    const bool table = J.min_reads < 2;
+    if (L > 0) {
+      const int per = (L + kMcBlock - 1) / kMcBlock;
+      if (per <= 1)
+        n_comp = mc_listed<1>(J, O, L, W, s_lw, s_bw, s_wp, s_lid, s_a, s_b, sh64, &s_ml);
+      else if (per <= 2)
+        n_comp = mc_listed<2>(J, O, L, W, s_lw, s_bw, s_wp, s_lid, s_a, s_b, sh64, &s_ml);
+      else if (per <= 4)
+        n_comp = mc_listed<4>(J, O, L, W, s_lw, s_bw, s_wp, s_lid, s_a, s_b, sh64, &s_ml);
+      else
+        n_comp = mc_listed<kMcPer>(J, O, L, W, s_lw, s_bw, s_wp, s_lid, s_a, s_b, sh64, &s_ml);
+    }
+    if (table)
+      n_comp = mc_sweep_table<true>(n, J.min_reads, O, s_lw, s_bw, s_wp,
+                                    McState<true>{s_lid, s_b, s_a}, sh64);
+    else
+      mc_write_lds(n, O, s_lw, s_bw, s_wp, s_lid, s_b);
+  } else {
+    n_comp = mc_components<false>(J, O,
+                                  McArr<false>{(CG_GLOBAL uint32_t *)J.s.lidx,
+                                               (CG_GLOBAL int32_t *)J.s.aux,
+                                               (CG_GLOBAL int32_t *)J.s.walk},
+                                  s_lw, s_bw, s_wp, w0, w1, lo, hi, sh64, &s_ml);
+  }
+  // BranchRemoval's counts (the kept entries were summed in LDS before the
+  // later barriers) and the number of components; no barrier waits here for
+  // the stores above
   if (tid == 0) {
-    J.counts[0] = (int32_t)n_branch;
-    J.counts[1] = (int32_t)tm;
+    CG_GLOBAL int32_t *counts = (CG_GLOBAL int32_t *)J.counts;
+    counts[0] = n_branch;
+    counts[1] = s_ml;
+    *(CG_GLOBAL int32_t *)J.parts.d_n_comp = n_comp;
   }
-}
-
-// The same for a job beyond LDS: the job's own forest in global memory (only
-// this workgroup touches it), the list walked tile by tile in id order.
-__device__ void cc_global(const BatchDev &B, const BJob &J, int nt, const int2 *tc,
-                          int64_t *sh64, int64_t *m_l_out) {
-  const int tid = threadIdx.x;
-  const uint32_t tag = forest_tag(B);
-  const bool table = J.min_reads >= 2;
-  uint32_t *lc = (uint32_t *)J.parts.label_comp;
-  int64_t m_l = 0;
-  // kept bits; counters of the reads with kept entries start at 0
-  for (int t = 0; t < nt; ++t) {
-    const int32_t c = tc[t].x;
-    for (int i = tid; i < c; i += kCcBlock) {
-      const int4 e = J.conn_list[t * kMaskTile + i];
-      const uint32_t f = (uint32_t)e.w;
-      if (f) {
-        J.flags[e.x] = (uint8_t)f;
-        lc[e.x] = 0;
-      }
-      m_l += __popc(f);
-    }
-  }
-  *m_l_out = m_l;
-  __syncthreads();
-  for (int t = 0; t < nt; ++t) {
-    const int32_t c = tc[t].x;
-    for (int i = tid; i < c; i += kCcBlock) {
-      const int4 e = J.conn_list[t * kMaskTile + i];
-      if (e.y >= 0) tf_union(J.forest, tag, e.x, J.conn_list[e.y].x);
-      if (e.z >= 0) tf_union(J.forest, tag, e.x, J.conn_list[e.z].x);
-    }
-  }
-  __syncthreads();
-  for (int t = 0; t < nt; ++t) {
-    const int32_t c = tc[t].x;
-    for (int i = tid; i < c; i += kCcBlock) {
-      const int4 e = J.conn_list[t * kMaskTile + i];
-      const uint32_t f = J.flags[e.x];
-      if (!f) continue;
-      int32_t r = e.x;
-      while (true) {
-        const int32_t p = tf_parent(J.forest, tag, r);
-        if (p == r) break;
-        r = p;
-      }
-      J.label[e.x] = r;
-      atomicAdd(lc + r, 4u + (__popc(f) == 1 ? 1u : 0u));
-    }
-  }
-  if (!table) return;
-  __syncthreads();
-  // component table in label order: the list in id order, chunk by chunk
-  int32_t cb = 0, mb = 0;
-  for (int t = 0; t < nt; ++t) {
-    const int32_t c = tc[t].x;
-    for (int base = 0; base < c; base += kCcBlock) {
-      const int i = base + tid;
-      int32_t id = -1;
-      uint32_t c4 = 0;
-      bool elig = false, root = false;
-      if (i < c) {
-        id = J.conn_list[t * kMaskTile + i].x;
-        if (J.flags[id] & 6) {
-          root = J.label[id] == id;
-          if (root) {
-            c4 = __hip_atomic_load(lc + id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            elig = (int32_t)(c4 >> 2) >= J.min_reads;
-          }
-        }
-      }
-      int64_t tot;
-      const int64_t ex = block_excl_scan<int64_t, kCcBlock>(
-          elig ? (((int64_t)1 << 32) | (c4 >> 2)) : 0, sh64, &tot);
-      if (elig) {
-        const int32_t k = cb + (int32_t)(ex >> 32);
-        J.parts.comp_label[k] = id;
-        J.parts.comp_size[k] = (int32_t)(c4 >> 2);
-        J.parts.comp_kind[k] = kind_of(c4);
-        J.s.memb[k] = mb + (int32_t)(ex & 0xFFFFFFFF);
-        J.s.fill[k] = 0;
-        J.s.comp_w[k] = 0;
-      }
-      if (i < c && (J.flags[id] & 6))
-        __hip_atomic_store((int32_t *)lc + id, elig ? cb + (int32_t)(ex >> 32) : -1,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      cb += (int32_t)(tot >> 32);
-      mb += (int32_t)(tot & 0xFFFFFFFF);
-    }
-  }
-  if (tid == 0) *J.parts.d_n_comp = cb;
-  __syncthreads();
-  // members grouped by component
-  for (int t = 0; t < nt; ++t) {
-    const int32_t c = tc[t].x;
-    for (int i = tid; i < c; i += kCcBlock) {
-      const int32_t id = J.conn_list[t * kMaskTile + i].x;
-      if (!(J.flags[id] & 6)) continue;
-      const int32_t k = __hip_atomic_load((int32_t *)lc + J.label[id], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-      if (k < 0) continue;
-      J.s.tmp[J.s.memb[k] + (int32_t)atomicAdd(J.s.fill + k, 1u)] = id;
-    }
-  }
-}
-
-// 3. eligible components in label order, reduce-then-scan: each tile counts
-// its eligible roots, then each tile adds up the counts of the tiles before
-// it in its job (plain loads, no waiting) and scatters
-template <int T>
-__device__ __forceinline__ bool eligible(const BJob &J, int64_t v, uint32_t *c_out) {
-  if (v >= J.g.n) return false;
-  const uint32_t c = (uint32_t)J.parts.label_comp[v];
-  *c_out = c;
-  const uint32_t mr = J.min_reads < 1 ? 1u : (uint32_t)J.min_reads;
-  return (c >> 2) >= mr && !(J.flags[v] & 1);
-}
-
-template <int T>
-__global__ __launch_bounds__(T) void kb_tilecount(BatchDev B) {
-  __shared__ int32_t sh[T / kWave];
-  const int t = blockIdx.x;
-  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  uint32_t c = 0;
-  const bool e = eligible<T>(J, v, &c);
-  const int cnt = __popcll(__ballot(e));
-  if (lane_id() == 0) sh[threadIdx.x / kWave] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int w = 0; w < T / kWave; ++w) s += sh[w];
-    B.tile_cnt[t] = s;
-  }
-}
-
-template <int T>
-__global__ __launch_bounds__(T) void kb_compact(BatchDev B) {
-  __shared__ int32_t sh[T / kWave + 1];
-  const int t = blockIdx.x;
-  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
-  int32_t before = 0;
-  for (int i = J.vt_first + (int)threadIdx.x; i < t; i += T) before += B.tile_cnt[i];
-  before = wave_sum(before);
-  if (lane_id() == 0) sh[threadIdx.x / kWave] = before;
-  __syncthreads();
-  int32_t base = 0;
-  for (int w = 0; w < T / kWave; ++w) base += sh[w];
-  __syncthreads();
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  uint32_t c = 0;
-  const bool e = eligible<T>(J, v, &c);
-  int32_t tot;
-  const int32_t ex = base + block_excl_scan<int32_t, T>(e ? 1 : 0, sh, &tot);
-  if (v < J.g.n) {
-    if (e) {
-      const uint32_t q = c >> 2;
-      J.parts.comp_label[ex] = (int32_t)v;
-      J.parts.comp_size[ex] = (int32_t)q;
-      J.parts.comp_kind[ex] = q == 1 ? CG_KIND_SINGLE : ((c & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
-      J.parts.label_comp[v] = ex;
-      J.s.comp_w[ex] = 0;
-    } else {
-      J.parts.label_comp[v] = -1;
-    }
-  }
-  if (t == J.vt_first + J.vt_count - 1 && threadIdx.x == 0) *J.parts.d_n_comp = base + tot;
 }
 
 // 3b. bases weight of each eligible component (jobs partitioned by bases):
@@ -738,7 +1121,6 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
       if (b < P) J.local.bin_vptr[b] = (int32_t)(carry + ex);
       carry += tot;
     }
-    for (int c = threadIdx.x; c < nc; c += kBatchLptBlock) J.s.fill[c] = 0;
   }
   __shared__ int last;
   if (threadIdx.x == 0) {
@@ -788,7 +1170,6 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
     B.piece_base[B.n_jobs] = (int32_t)(uint32_t)tcp;
     B.chunk_base[B.n_jobs] = (int32_t)th;
     B.counters[2] = 0;
-    B.counters[3] += 1u;  // the next run's forest tag
   }
   __threadfence();
 }
@@ -907,20 +1288,6 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   }
 }
 
-// 5. each eligible read claims a slot in its component's block
-template <int T>
-__global__ __launch_bounds__(T) void kb_fill(BatchDev B) {
-  const int t = blockIdx.x;
-  const BJob J = job_at(B.jobs, ld_const(B.tile_job, t));
-  if (J.min_reads >= 2 || J.external) return;  // table and members come from elsewhere
-  const int64_t v = (int64_t)(t - J.vt_first) * T + threadIdx.x;
-  if (v >= J.g.n) return;
-  const int32_t c = J.parts.label_comp[J.label[v]];
-  if (c < 0) return;
-  const uint32_t slot = atomicAdd(J.s.fill + c, 1u);
-  J.s.tmp[J.parts.comp_start[c] + slot] = (int32_t)v;
-}
-
 // The per-component passes take their part of the work queue [lo, hi) in a
 // snake order over the grid: round r gives workgroup w entry r*W + w, or
 // r*W + W-1-w on odd rounds.  The queue is in decreasing read count, so this
@@ -949,7 +1316,7 @@ __device__ __forceinline__ void induce_listed(const BatchDev &B, int4 d, int32_t
   const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
   const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
   const BJob J = job_at(B.jobs, j);
-  const int32_t *members = J.s.tmp + (J.min_reads >= 2 ? J.s.memb[c] : st);
+  const int32_t *members = J.s.tmp + J.s.memb[c];
   induce_component<BLOCK, CAP>(q, st, J.s.estart[c], members, J.flags, J.g.row_ptr, J.g.col,
                                J.local.perm, J.s.lidx, J.local.loc_row_ptr, J.local.loc_col,
                                J.local.loc_eid, a, sh_scan);
@@ -1078,7 +1445,8 @@ using namespace cg;
 struct cg_batch {
   cg_ctx *ctx;
   int32_t n_jobs, n_vtiles;
-  bool any_single;  // a job with min_reads <= 1 (one-read components eligible)
+  int32_t n_internal;  // jobs the batched launches run (the others are external)
+  const MaskTile *mtiles;  // [dev.n_mtiles] tiles of kb_mask_tiles
   bool any_bases;   // a job partitioned by bases weights
   int64_t chunk_slots;  // upper bound on the copy chunks of the batch
   // workgroups of each per-component pass that fit on the device at once:
@@ -1117,30 +1485,15 @@ static int check_job(const cg_job &J, int i) {
       !c.cflags || !c.layout_off || !c.layout_vid || !c.layout_rev || !c.d_total_words ||
       (c.cap_words > 0 && !c.bases))
     return set_error(CG_EINVAL, "job %d: a buffer is NULL", i);
-  // the mask pass moves four reads per thread with 16-byte accesses
+  // the mask and components pass moves reads with 16-byte accesses
   if (((uintptr_t)g.row_ptr & 15) || ((uintptr_t)J.label & 15) || ((uintptr_t)p.label_comp & 15) ||
-      ((uintptr_t)J.flags & 3))
+      ((uintptr_t)J.flags & 15))
     return set_error(CG_EINVAL,
-                     "job %d: row_ptr, label and label_comp must be 16-byte aligned and flags "
-                     "4-byte aligned", i);
+                     "job %d: row_ptr, flags, label and label_comp must be 16-byte aligned", i);
   return CG_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-template <int T>
-static void launch_vertex_phases(cg_batch *b, hipStream_t st) {
-  cg_ctx *ctx = b->ctx;
-  const BatchDev &B = b->dev;
-  CG_LAUNCH(ctx, kb_tilecount<T>, dim3(b->n_vtiles), dim3(T), st, B);
-  CG_LAUNCH(ctx, kb_compact<T>, dim3(b->n_vtiles), dim3(T), st, B);
-}
-
-template <int T>
-static void launch_vertex_fill(cg_batch *b, hipStream_t st) {
-  cg_ctx *ctx = b->ctx;
-  CG_LAUNCH(ctx, kb_fill<T>, dim3(b->n_vtiles), dim3(T), st, b->dev);
-}
 
 extern "C" {
 
@@ -1172,7 +1525,6 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const int T = prm.vertex_tile;
   std::vector<BJob> hj(n_jobs);
   std::vector<int32_t> tile_job;
-  std::vector<size_t> job_off(n_jobs);
   size_t at = 0;
   auto take = [&](size_t bytes) {
     size_t here = at;
@@ -1189,7 +1541,6 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     nv += cnt;
   }
   const size_t o_tiles = take(sizeof(int32_t) * nv);
-  const size_t o_tcnt = take(sizeof(int32_t) * nv);
   const size_t o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
   const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
@@ -1207,34 +1558,31 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   const size_t o_hjob = take(sizeof(int32_t) * (size_t)(sum_chunks > 0 ? sum_chunks : 1));
   const size_t o_counters = take(sizeof(unsigned int) * 8);
   const size_t o_order = take(sizeof(int32_t) * n_jobs);
-  int32_t n_mt = 0;
+  std::vector<size_t> job_off(n_jobs);
+  int32_t n_internal = 0, n_mt = 0;
   for (int i = 0; i < n_jobs; ++i) {
-    // a job whose reads of degree 1-2 (about half its entries) would not fit
-    // the components pass's LDS goes through the single-graph kernels
-    hj[i].external = jobs[i].g.m > kExternalEntries ? 1 : 0;
+    // the components pass holds a job's reads as LDS bitmaps and its reads
+    // of degree 1-2 (at most its entries) in LDS; larger jobs go through the
+    // single-graph kernels
+    hj[i].external =
+        (jobs[i].g.n > kMcReadCap || jobs[i].g.m > kExternalEntries) ? 1 : 0;
+    n_internal += hj[i].external ? 0 : 1;
     hj[i].mt_first = n_mt;
     hj[i].mt_count = hj[i].external ? 0 : (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
     n_mt += hj[i].mt_count;
+    job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
   }
   const size_t o_mtiles = take(sizeof(MaskTile) * (n_mt > 0 ? n_mt : 1));
   const size_t o_mtcnt = take(sizeof(int2) * (n_mt > 0 ? n_mt : 1));
-  std::vector<size_t> forest_off(n_jobs);
-  for (int i = 0; i < n_jobs; ++i) {
-    job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
-    forest_off[i] = take(sizeof(uint64_t) * (size_t)(jobs[i].g.n > 0 ? jobs[i].g.n : 1));
-  }
   cg_batch *b = new (std::nothrow) cg_batch();
   if (!b) return set_error(CG_EINVAL, "out of host memory");
   b->ctx = ctx;
   b->n_jobs = n_jobs;
   b->n_vtiles = nv;
   b->chunk_slots = sum_chunks;
-  b->any_single = false;
+  b->n_internal = n_internal;
   b->any_bases = false;
-  for (int i = 0; i < n_jobs; ++i) {
-    b->any_single |= jobs[i].min_reads < 2;
-    b->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
-  }
+  for (int i = 0; i < n_jobs; ++i) b->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
   b->prm = prm;
   {
     int dev = 0, cus = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
@@ -1282,32 +1630,28 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
       view.scratch = b->mem + job_off[i];
       view.scratch_bytes = layout(J.g.n, J.g.m, J.P).total;
       carve(&view, J.g.n, J.g.m, J.P, &h.s);
-      // zeroed above: tag 0 never matches a run's tag (runs use 1, 2, ...)
-      h.forest = (uint64_t *)(b->mem + forest_off[i]);
-      // the list and its index live in scratch that later steps reuse
-      h.conn_list = (int4 *)h.s.walk;
-      h.conn_map = h.s.lidx;
       if (h.external) {
         b->ext_jobs.push_back(J);
         b->ext_s.push_back(h.s);
       }
     }
+    // the mask tiles: each job's list lives in its walk scratch, its bitmaps
+    // in its fill scratch (both reused by later steps)
     std::vector<MaskTile> mt;
     mt.reserve(n_mt);
     int2 *d_mtcnt = (int2 *)(b->mem + o_mtcnt);
     for (int i = 0; i < n_jobs; ++i)
       for (int32_t v0 = 0; !hj[i].external && v0 < jobs[i].g.n; v0 += kMaskTile)
-        mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, jobs[i].flags, jobs[i].label,
-                              jobs[i].parts.label_comp, hj[i].conn_list, hj[i].conn_map,
-                              d_mtcnt + (int32_t)mt.size(), jobs[i].g.n, v0,
-                              jobs[i].min_reads >= 2 ? -1 : 4});
+        mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, (int4 *)hj[i].s.walk,
+                              (uint32_t *)hj[i].s.fill, d_mtcnt + (int32_t)mt.size(),
+                              jobs[i].g.n, v0, (jobs[i].g.n + 31) / 32, 0});
+    if (n_mt > 0)
+      rc = hip_check(hipMemcpy(b->mem + o_mtiles, mt.data(), sizeof(MaskTile) * n_mt,
+                               hipMemcpyHostToDevice), "hipMemcpy(mask tiles)");
     std::vector<int32_t> order(n_jobs);
     for (int i = 0; i < n_jobs; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return jobs[a].g.n > jobs[c].g.n; });
-    if (n_mt > 0)
-      rc = hip_check(hipMemcpy(b->mem + o_mtiles, mt.data(), sizeof(MaskTile) * n_mt,
-                               hipMemcpyHostToDevice), "hipMemcpy(mask tiles)");
     if (!rc)
       rc = hip_check(hipMemcpy(b->mem + o_order, order.data(), sizeof(int32_t) * n_jobs,
                                hipMemcpyHostToDevice), "hipMemcpy(job order)");
@@ -1328,7 +1672,6 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   BatchDev &d = b->dev;
   d.jobs = (BJob *)(b->mem + o_jobs);
   d.tile_job = (int32_t *)(b->mem + o_tiles);
-  d.tile_cnt = (int32_t *)(b->mem + o_tcnt);
   d.comp_base = (int32_t *)(b->mem + o_cbase);
   d.piece_base = (int32_t *)(b->mem + o_pbase);
   d.chunk_base = (int32_t *)(b->mem + o_hbase);
@@ -1340,10 +1683,10 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
   d.comp_job = (int32_t *)(b->mem + o_cjob);
   d.chunk_job = (int32_t *)(b->mem + o_hjob);
   d.counters = (unsigned int *)(b->mem + o_counters);
-  d.mt_cnt = (int2 *)(b->mem + o_mtcnt);
   d.job_order = (const int32_t *)(b->mem + o_order);
-  d.mtiles = (const MaskTile *)(b->mem + o_mtiles);
+  d.mt_cnt = (int2 *)(b->mem + o_mtcnt);
   d.n_mtiles = n_mt;
+  b->mtiles = (const MaskTile *)(b->mem + o_mtiles);
   d.fixed = ctx->fixed;
   d.n_jobs = n_jobs;
   d.n_vtiles = nv;
@@ -1369,18 +1712,10 @@ int cg_batch_run(cg_batch *b, void *stream) {
     if (!rc) rc = launch_assemble(ctx, J.g, s, J.parts, J.local, J.P, J.contigs, st);
     if (rc) return rc;
   }
-  if (B.n_mtiles > 0) {
-    CG_LAUNCH(ctx, kb_mask_list, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
-    CG_LAUNCH(ctx, kb_cc_prep, dim3(B.n_mtiles), dim3(kMaskThreads), st, B.mtiles);
-  }
-  CG_LAUNCH(ctx, kb_cc_local, dim3(b->n_jobs), dim3(kCcBlock), st, B);
-  // jobs where one-read components are eligible take their component table
-  // and member buckets from full vertex passes
-  if (b->any_single) {
-    if (T == 256) launch_vertex_phases<256>(b, st);
-    else if (T == 512) launch_vertex_phases<512>(b, st);
-    else launch_vertex_phases<1024>(b, st);
-  }
+  if (b->n_internal == 0) return hip_check(hipGetLastError(), "cg_batch_run");
+  if (B.n_mtiles > 0)
+    CG_LAUNCH(ctx, kb_mask_tiles, dim3(B.n_mtiles), dim3(kMaskThreads), st, b->mtiles);
+  CG_LAUNCH(ctx, kb_mask_cc, dim3(b->n_jobs), dim3(kMcBlock), st, B);
   if (b->any_bases) {
     if (T == 256) CG_LAUNCH(ctx, kb_weight<256>, dim3(b->n_vtiles), dim3(256), st, B);
     else if (T == 512) CG_LAUNCH(ctx, kb_weight<512>, dim3(b->n_vtiles), dim3(512), st, B);
@@ -1389,11 +1724,6 @@ int cg_batch_run(cg_batch *b, void *stream) {
   CG_LAUNCH(ctx, kb_lpt, dim3(b->n_jobs), dim3(kBatchLptBlock), st, B);
   CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
   CG_LAUNCH(ctx, kb_wq_place, dim3(128), dim3(kWqBlock), st, B);
-  if (b->any_single) {
-    if (T == 256) launch_vertex_fill<256>(b, st);
-    else if (T == 512) launch_vertex_fill<512>(b, st);
-    else launch_vertex_fill<1024>(b, st);
-  }
   auto capped = [](int want, int fit) { return dim3((unsigned)(fit > 0 && fit < want ? fit : want)); };
   CG_LAUNCH(ctx, kb_induce_small, capped(4 * PB, b->res_induce_small), dim3(kIndSmallBlock), st, B);
   CG_LAUNCH(ctx, kb_induce, capped(PB, b->res_induce), dim3(kIndBlock), st, B);

@@ -42,29 +42,30 @@ def _mixed_graphs():
     gs.append(synth.with_alignment_ends(synth.config_graph(1), np.random.default_rng(8), 3))
     ra = np.random.default_rng(18)
     gs += [_random_pre_post(synth.adversarial(ra), ra) for _ in range(6)]
-    # more than 32768 entries: run through the single-graph kernels inside
-    # the batch, with and without one-read components
+    # more entries than the batched components pass takes: run through the
+    # single-graph kernels inside the batch, with and without one-read
+    # components
     gs.append(_chain_graph(r, [6000, 6000, 5000, 2]))
     gs[-1].meta["min_reads"] = 2
     gs.append(_chain_graph(r, [7000, 5000, 1], cycles=[4000, 600]))
     gs[-1].meta["min_reads"] = 1
     # explicit coordinates through every batched walk form: one-wave walks
     # (up to 128 reads), the LDS walk (129-1024) and the global-array walk
-    # (above 1024), chains and cycles, clipped and arbitrary; and a job of
-    # more than 32768 entries with coordinates (single-graph route)
+    # (above 1024), chains and cycles, clipped and arbitrary; and a job with
+    # coordinates above the batched entry bound (single-graph route)
     rc = np.random.default_rng(33)
-    long_g = _chain_graph(rc, [200, 900, 1500, 3000, 60], cycles=[200, 900, 1500, 3000],
-                          len_lo=30, len_hi=80)
-    gs.append(synth.with_alignment_ends(long_g, rc, 3))
+    gs.append(synth.with_alignment_ends(
+        _chain_graph(rc, [200, 900, 3000, 60], cycles=[1500], len_lo=30, len_hi=80), rc, 3))
     gs[-1].meta = dict(gs[-1].meta, min_reads=2)
-    gs.append(_random_pre_post(long_g, rc))
+    gs.append(_random_pre_post(
+        _chain_graph(rc, [1500, 2], cycles=[200, 900, 3000], len_lo=30, len_hi=80), rc))
     gs[-1].meta = dict(min_reads=1)
     gs.append(synth.with_alignment_ends(_chain_graph(rc, [6000, 5000, 4000, 2000, 500, 2],
                                                      cycles=[1200], len_lo=30, len_hi=80),
                                         rc, 3))
     gs[-1].meta = dict(gs[-1].meta, min_reads=2)
     # more listed reads than the components pass holds in LDS, but few
-    # entries: the tagged global forest of the batched components pass
+    # entries: the components pass keeps their state in the job's scratch
     gs.append(_chain_graph(r, [2] * 9000))
     gs[-1].meta["min_reads"] = 2
     gs.append(_chain_graph(r, [2] * 8800 + [3] * 50))
