@@ -385,6 +385,17 @@ typedef struct {
 
 /* Launch shapes of the batched kernels (0 = default).  They change speed,
  * never results. */
+/* Every output buffer of one job carved from one device buffer: with base
+ * NULL, *bytes [host] receives the bytes needed; with base [device, 256-byte
+ * aligned, at least that many bytes] the output pointers of *job [host]
+ * (flags, d_counts, label, parts, local, contigs with cap_words) are set to
+ * buffers inside it, each at a 256-byte boundary, at the capacities the
+ * five calls state for a graph of n reads and P bins (as cg_footprint's
+ * outputs, plus the alignment).  The graph, P, min_reads and weight of *job
+ * are left alone.  Errors: CG_EINVAL. */
+int cg_job_outputs(int32_t n, int32_t P, uint64_t cap_words, void *base, uint64_t *bytes,
+                   cg_job *job);
+
 typedef struct {
   int32_t vertex_tile;     /* vertices per workgroup in vertex passes: 256 (default), 512, 1024 */
   int32_t copy_block;      /* threads per workgroup of the base copy, multiple of 64 (256);
@@ -407,8 +418,49 @@ typedef struct cg_batch cg_batch;
 int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
                     const cg_batch_params *params, cg_batch **out);
 
+/* Device bytes a batch of these jobs needs (as cg_batch_create allocates;
+ * vertex_tile of params counts, NULL params means the defaults).  Only each
+ * job's g.n, g.m, P and weight are read: its pointers may be NULL, so a
+ * caller can size a batch before it allocates the jobs' outputs.  bytes is
+ * [host]. */
+int cg_batch_bytes(int32_t n_jobs, const cg_job *jobs, const cg_batch_params *params,
+                   uint64_t *bytes);
+
+/* A batch with `bytes` of device memory and no jobs yet, for a caller that
+ * plans batch after batch into the same memory (a serving loop): give it
+ * jobs with cg_batch_plan. */
+int cg_batch_create_empty(cg_ctx *ctx, uint64_t bytes, const cg_batch_params *params,
+                          cg_batch **out);
+
+/* Replace the batch's jobs (same checks as cg_batch_create), within its
+ * memory: CG_ECAPACITY when they need more than it has (cg_batch_bytes), and
+ * nothing changes.  The job tables are uploaded on `stream`; the batch's
+ * earlier work must be complete (the new jobs reuse its memory).  A captured
+ * graph of the batch is dropped. */
+int cg_batch_plan(cg_batch *b, int32_t n_jobs, const cg_job *jobs, void *stream);
+
 /* Enqueue the whole path for every job of the batch on `stream`. */
 int cg_batch_run(cg_batch *b, void *stream);
+
+/* Results of the batch, for a caller that downloads them (enqueue after
+ * cg_batch_run or cg_batch_launch, on the same stream).
+ *
+ * cg_batch_counts writes d_counts [device, 4 n_jobs + 1 int64]: for job j
+ * (plan order) 4j: contigs nc (*d_n_comp), 4j+1: layout entries ne
+ * (d_sizes[0]), 4j+2: base words tw (*d_total_words, at most cap_words),
+ * 4j+3: the byte offset of the job's packed results; 4 n_jobs: their total
+ * bytes.
+ *
+ * cg_batch_pack copies every job's results, trimmed to those counts, into
+ * d_dst [device, 16-byte aligned] at the job's offset, as one packed record:
+ *   len u64[nc], base_off u64[nc], label, bin, start, n_reads, cflags,
+ *   layout_off (4 bytes each)[nc], layout_vid i32[ne], bases u32[tw],
+ *   layout_rev u8[ne], zero bytes up to a multiple of 16.
+ * Nothing is written past dst_bytes: a caller that read the total first
+ * (d_counts[4 n_jobs]) passes at least that.  Errors: CG_EINVAL. */
+int cg_batch_counts(cg_batch *b, int64_t *d_counts, void *stream);
+int cg_batch_pack(cg_batch *b, const int64_t *d_counts, void *d_dst, uint64_t dst_bytes,
+                  void *stream);
 
 /* Capture cg_batch_run into a HIP graph on `stream` (must not be the NULL
  * stream) and instantiate it; cg_batch_launch then replays it. */

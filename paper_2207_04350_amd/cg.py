@@ -105,10 +105,20 @@ def lib():
                                                    P(CgLocal), P(CgContigs), _vp, _vp]
         L.cg_batch_create.argtypes = [_vp, ctypes.c_int32, P(CgJob), P(CgBatchParams), P(_vp)]
         L.cg_batch_run.argtypes = [_vp, _vp]
+        L.cg_batch_bytes.argtypes = [ctypes.c_int32, P(CgJob), P(CgBatchParams),
+                                     P(ctypes.c_uint64)]
+        L.cg_batch_create_empty.argtypes = [_vp, ctypes.c_uint64, P(CgBatchParams), P(_vp)]
+        L.cg_batch_plan.argtypes = [_vp, ctypes.c_int32, P(CgJob), _vp]
+        L.cg_job_outputs.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _vp,
+                                     P(ctypes.c_uint64), P(CgJob)]
+        L.cg_batch_counts.argtypes = [_vp, _vp, _vp]
+        L.cg_batch_pack.argtypes = [_vp, _vp, _vp, ctypes.c_uint64, _vp]
         L.cg_batch_capture.argtypes = [_vp, _vp]
         L.cg_batch_launch.argtypes = [_vp, _vp]
         L.cg_batch_destroy.argtypes = [_vp]
-        for name in ("cg_batch_create", "cg_batch_run", "cg_batch_capture", "cg_batch_launch",
+        for name in ("cg_batch_create", "cg_batch_run", "cg_batch_bytes", "cg_batch_create_empty",
+                     "cg_batch_plan", "cg_batch_capture", "cg_batch_launch", "cg_job_outputs",
+                     "cg_batch_counts", "cg_batch_pack",
                      "cg_batch_destroy", "cg_ctx_profile", "cg_ctx_profile_read",
                      "cg_ctx_create", "cg_ctx_destroy", "cg_footprint", "cg_ctx_status",
                      "cg_validate", "cg_mask_branches", "cg_components", "cg_partition",
@@ -425,35 +435,133 @@ def to_host(out, n):
                 parts=parts, local=local, contigs=contigs)
 
 
+def job_outputs_bytes(n, P, cap_words):
+    """cg_job_outputs: bytes of one job's outputs carved from one buffer."""
+    b = ctypes.c_uint64(0)
+    _check(lib().cg_job_outputs(int(n), int(P), int(cap_words), None, ctypes.byref(b), None))
+    return int(b.value)
+
+
+class CarvedOutputs:
+    """One job's output buffers inside a larger device buffer (cg_job_outputs):
+    only the C pointers, no tensor per buffer."""
+
+    def __init__(self, buf, offset, n, P, cap_words):
+        self.buf = buf          # keeps the device buffer alive
+        self.n, self.P, self.cap_words = int(n), int(P), int(cap_words)
+        self.cjob = CgJob()
+        b = ctypes.c_uint64(0)
+        _check(lib().cg_job_outputs(self.n, self.P, self.cap_words,
+                                    _vp(buf.data_ptr() + int(offset)), ctypes.byref(b),
+                                    ctypes.byref(self.cjob)))
+        self.nbytes = int(b.value)
+
+
+# fields of one job's packed results (cg_batch_pack), in order
+_PACK_NC = (("len", np.uint64), ("base_off", np.uint64), ("label", np.int32),
+            ("bin", np.int32), ("start", np.int32), ("n_reads", np.int32),
+            ("cflags", np.uint32), ("layout_off", np.int32))
+
+
+def unpack_results(packed, row):
+    """One job's results from the packed bytes of cg_batch_pack (a uint8
+    numpy array) and its row of cg_batch_counts (nc, ne, tw, offset): a dict
+    of numpy views."""
+    nc, ne, tw, off = (int(x) for x in row)
+    out, at = {}, off
+    for name, dt in _PACK_NC:
+        w = np.dtype(dt).itemsize
+        out[name] = packed[at:at + w * nc].view(dt)
+        at += w * nc
+    out["layout_vid"] = packed[at:at + 4 * ne].view(np.int32)
+    at += 4 * ne
+    out["bases"] = packed[at:at + 4 * tw].view(np.uint32)
+    at += 4 * tw
+    out["layout_rev"] = packed[at:at + ne]
+    return out
+
+
+def _job_array(jobs):
+    arr = (CgJob * len(jobs))()
+    for i, job in enumerate(jobs):
+        dg, out, P, mr = job[:4]
+        if isinstance(out, CarvedOutputs):
+            arr[i] = out.cjob
+        arr[i].g = dg.struct
+        arr[i].P = int(P)
+        arr[i].min_reads = int(mr)
+        arr[i].weight = int(_weight(job[4] if len(job) > 4 else "reads"))
+        if isinstance(out, CarvedOutputs):
+            continue
+        arr[i].flags = _ptr(out.flags)
+        arr[i].d_counts = _ptr(out.counts)
+        arr[i].label = _ptr(out.label)
+        arr[i].parts = out.parts
+        arr[i].local = out.local
+        arr[i].contigs = out.contigs
+    return arr
+
+
+def batch_bytes(jobs, vertex_tile=0):
+    """cg_batch_bytes: device bytes a batch of these jobs needs.  A job is a
+    (DeviceGraph, Outputs, P, min_reads[, weight]) tuple or, before anything
+    is allocated, a (n, m, P[, weight]) tuple of sizes."""
+    if jobs and not isinstance(jobs[0][0], DeviceGraph):
+        arr = (CgJob * len(jobs))()
+        for i, job in enumerate(jobs):
+            arr[i].g.n, arr[i].g.m, arr[i].P = int(job[0]), int(job[1]), int(job[2])
+            arr[i].weight = int(_weight(job[3] if len(job) > 3 else "reads"))
+    else:
+        arr = _job_array(jobs)
+    out = ctypes.c_uint64(0)
+    prm = CgBatchParams(int(vertex_tile), 0, 0)
+    _check(lib().cg_batch_bytes(len(jobs), arr, ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
 class Batch:
     """A cg_batch over resident graphs: `jobs` is a list of (DeviceGraph,
     Outputs, P, min_reads[, weight]).  Keeps the tensors alive while it
-    exists."""
+    exists.  Batch.empty(ctx, bytes) makes one without jobs, for plan()."""
 
     def __init__(self, ctx, jobs, vertex_tile=0, copy_block=0, persist_blocks=0):
         self.ctx = ctx
         self._keep = jobs
-        arr = (CgJob * len(jobs))()
-        for i, job in enumerate(jobs):
-            dg, out, P, mr = job[:4]
-            arr[i].g = dg.struct
-            arr[i].P = int(P)
-            arr[i].min_reads = int(mr)
-            arr[i].weight = int(_weight(job[4] if len(job) > 4 else "reads"))
-            arr[i].flags = _ptr(out.flags)
-            arr[i].d_counts = _ptr(out.counts)
-            arr[i].label = _ptr(out.label)
-            arr[i].parts = out.parts
-            arr[i].local = out.local
-            arr[i].contigs = out.contigs
         prm = CgBatchParams(int(vertex_tile), int(copy_block), int(persist_blocks))
         self.handle = _vp(0)
-        _check(lib().cg_batch_create(ctx.handle, len(jobs), arr, ctypes.byref(prm),
+        if jobs is None:
+            return
+        _check(lib().cg_batch_create(ctx.handle, len(jobs), _job_array(jobs), ctypes.byref(prm),
                                      ctypes.byref(self.handle)))
         self.params = (vertex_tile, copy_block, persist_blocks)
 
+    @classmethod
+    def empty(cls, ctx, nbytes, vertex_tile=0, copy_block=0, persist_blocks=0):
+        self = cls(ctx, None)
+        prm = CgBatchParams(int(vertex_tile), int(copy_block), int(persist_blocks))
+        _check(lib().cg_batch_create_empty(ctx.handle, int(nbytes), ctypes.byref(prm),
+                                           ctypes.byref(self.handle)))
+        self.params = (vertex_tile, copy_block, persist_blocks)
+        self._keep = []
+        return self
+
+    def plan(self, jobs, stream=None):
+        """cg_batch_plan: replace the jobs (the batch's earlier work must be
+        complete)."""
+        _check(lib().cg_batch_plan(self.handle, len(jobs), _job_array(jobs), _stream(stream)))
+        self._keep = jobs
+
     def run(self, stream=None):
         _check(lib().cg_batch_run(self.handle, _stream(stream)))
+
+    def counts(self, d_counts, stream=None):
+        """cg_batch_counts into d_counts (int64 tensor of 4 n_jobs + 1)."""
+        _check(lib().cg_batch_counts(self.handle, _ptr(d_counts), _stream(stream)))
+
+    def pack(self, d_counts, dst, stream=None):
+        """cg_batch_pack into dst (a 16-byte aligned device tensor)."""
+        _check(lib().cg_batch_pack(self.handle, _ptr(d_counts), _ptr(dst),
+                                   dst.numel() * dst.element_size(), _stream(stream)))
 
     def capture(self, stream):
         _check(lib().cg_batch_capture(self.handle, _stream(stream)))

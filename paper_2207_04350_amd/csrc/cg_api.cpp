@@ -183,6 +183,66 @@ int cg_footprint(int32_t n, int32_t m, uint64_t seq_words, int32_t P, int32_t co
   return CG_OK;
 }
 
+int cg_job_outputs(int32_t n, int32_t P, uint64_t cap_words, void *base, uint64_t *bytes,
+                   cg_job *job) {
+  if (!bytes || n < 0 || P < 1 || P > 65536 || cap_words >= (1ull << 62) ||
+      (base && (!job || ((uintptr_t)base & 255))))
+    return set_error(CG_EINVAL, "bad arguments (n=%d P=%d, base 256-byte aligned with a job)",
+                     n, P);
+  const uint64_t k = n > 0 ? (uint64_t)n : 1, Pb = (uint64_t)P;
+  const uint64_t words = cap_words > 0 ? cap_words : 1;
+  char *b = (char *)base;
+  uint64_t at = 0;
+  // each buffer at the next 256-byte boundary
+  auto take = [&](uint64_t size) -> void * {
+    void *p = b ? (void *)(b + at) : nullptr;
+    at += (size + 255) & ~(uint64_t)255;
+    return p;
+  };
+  cg_job j{};
+  j.flags = (uint8_t *)take(k);
+  j.d_counts = (int32_t *)take(8);
+  j.label = (int32_t *)take(4 * k);
+  j.parts.comp_label = (int32_t *)take(4 * k);
+  j.parts.comp_size = (int32_t *)take(4 * k);
+  j.parts.comp_kind = (uint8_t *)take(k);
+  j.parts.comp_bin = (int32_t *)take(4 * k);
+  j.parts.comp_rank = (int32_t *)take(4 * k);
+  j.parts.comp_start = (int32_t *)take(4 * k);
+  j.parts.bin_load = (uint64_t *)take(8 * Pb);
+  j.parts.label_comp = (int32_t *)take(4 * k);
+  j.parts.d_n_comp = (int32_t *)take(4);
+  j.local.perm = (int32_t *)take(4 * k);
+  j.local.bin_vptr = (int32_t *)take(4 * (Pb + 1));
+  j.local.loc_row_ptr = (int32_t *)take(4 * (k + 1));
+  j.local.loc_col = (int32_t *)take(8 * k);
+  j.local.loc_eid = (int32_t *)take(8 * k);
+  j.local.d_sizes = (int32_t *)take(8);
+  j.contigs.label = (int32_t *)take(4 * k);
+  j.contigs.bin = (int32_t *)take(4 * k);
+  j.contigs.start = (int32_t *)take(4 * k);
+  j.contigs.n_reads = (int32_t *)take(4 * k);
+  j.contigs.len = (uint64_t *)take(8 * k);
+  j.contigs.base_off = (uint64_t *)take(8 * k);
+  j.contigs.cflags = (uint32_t *)take(4 * k);
+  j.contigs.layout_off = (int32_t *)take(4 * k);
+  j.contigs.layout_vid = (int32_t *)take(4 * k);
+  j.contigs.layout_rev = (uint8_t *)take(k);
+  j.contigs.bases = (uint32_t *)take(4 * words);
+  j.contigs.cap_words = cap_words;
+  j.contigs.d_total_words = (uint64_t *)take(8);
+  *bytes = at;
+  if (b) {
+    job->flags = j.flags;
+    job->d_counts = j.d_counts;
+    job->label = j.label;
+    job->parts = j.parts;
+    job->local = j.local;
+    job->contigs = j.contigs;
+  }
+  return CG_OK;
+}
+
 int cg_ctx_create(int device, size_t scratch_bytes, cg_ctx **out) {
   if (!out) return set_error(CG_EINVAL, "out is NULL");
   *out = nullptr;

@@ -1435,6 +1435,113 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Results of a batch in one packed buffer (for a caller that downloads them)
+// ---------------------------------------------------------------------------
+// Packed record of one job, from its 16-byte aligned start (sizes in
+// entries: nc contigs, ne layout entries, tw base words):
+//   len u64[nc] | base_off u64[nc] | label, bin, start, n_reads, cflags,
+//   layout_off i32[nc] each | layout_vid i32[ne] | bases u32[tw] |
+//   layout_rev u8[ne] | zero padding to 16 bytes
+constexpr int kCountsBlock = 1024;
+constexpr int kPackBlock = 256;
+
+__device__ __forceinline__ int64_t pack_bytes(int64_t nc, int64_t ne, int64_t tw) {
+  return (40 * nc + 5 * ne + 4 * tw + 15) & ~(int64_t)15;
+}
+
+// out[4j..4j+3] = n_comp, n_e, packed base words, packed offset of job j;
+// out[4 n_jobs] = packed bytes of the batch.  One workgroup: a scan over the
+// jobs in chunks of its size.
+__global__ void __launch_bounds__(kCountsBlock) kb_counts(const BJob *jobs, int n_jobs,
+                                                          int64_t *out) {
+  __shared__ int64_t part[kCountsBlock / kWave];
+  __shared__ int64_t carry;
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < n_jobs; j0 += kCountsBlock) {
+    const int j = j0 + t;
+    int64_t nc = 0, ne = 0, tw = 0, sz = 0;
+    if (j < n_jobs) {
+      const BJob *J = jobs + j;
+      nc = *J->parts.d_n_comp;
+      ne = J->local.d_sizes[0];
+      tw = (int64_t)*J->out.d_total_words;
+      if ((uint64_t)tw > J->out.cap_words) tw = (int64_t)J->out.cap_words;  // not written
+      sz = pack_bytes(nc, ne, tw);
+    }
+    // inclusive scan of sz over the workgroup
+    int64_t x = sz;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int64_t y = __shfl_up(x, d, kWave);
+      if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) part[w] = x;
+    __syncthreads();
+    int64_t before = carry;
+    for (int k = 0; k < w; ++k) before += part[k];
+    if (j < n_jobs) {
+      out[4 * (int64_t)j + 0] = nc;
+      out[4 * (int64_t)j + 1] = ne;
+      out[4 * (int64_t)j + 2] = tw;
+      out[4 * (int64_t)j + 3] = before + x - sz;
+    }
+    __syncthreads();
+    if (t == kCountsBlock - 1) carry = before + x;
+    __syncthreads();
+  }
+  if (t == 0) out[4 * (int64_t)n_jobs] = carry;
+}
+
+// one 4-byte word of the packed results per thread (grid-stride); the job by
+// a binary search over the packed offsets, then the segment within it
+__global__ void __launch_bounds__(kPackBlock) kb_pack(const BJob *jobs, int n_jobs,
+                                                      const int64_t *counts, uint32_t *dst,
+                                                      int64_t dst_words) {
+  const int64_t total_words = counts[4 * (int64_t)n_jobs] / 4;
+  const int64_t lim = total_words < dst_words ? total_words : dst_words;
+  for (int64_t wd = (int64_t)blockIdx.x * kPackBlock + threadIdx.x; wd < lim;
+       wd += (int64_t)gridDim.x * kPackBlock) {
+    const int64_t byte = wd * 4;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (counts[4 * (int64_t)mid + 3] <= byte) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t nc = counts[4 * (int64_t)lo], ne = counts[4 * (int64_t)lo + 1];
+    const int64_t tw = counts[4 * (int64_t)lo + 2];
+    int64_t o = byte - counts[4 * (int64_t)lo + 3];
+    const BJob *J = jobs + lo;
+    uint32_t v = 0;
+    if (o < 16 * nc) {
+      const uint32_t *src = (const uint32_t *)(o < 8 * nc ? (const void *)J->out.len
+                                                          : (const void *)J->out.base_off);
+      v = src[(o < 8 * nc ? o : o - 8 * nc) / 4];
+    } else if (o < 40 * nc) {
+      const int64_t r = o - 16 * nc, a = r / (4 * nc), i = (r - a * 4 * nc) / 4;
+      const uint32_t *src = a == 0 ? (const uint32_t *)J->out.label
+                          : a == 1 ? (const uint32_t *)J->out.bin
+                          : a == 2 ? (const uint32_t *)J->out.start
+                          : a == 3 ? (const uint32_t *)J->out.n_reads
+                          : a == 4 ? J->out.cflags
+                                   : (const uint32_t *)J->out.layout_off;
+      v = src[i];
+    } else if ((o -= 40 * nc) < 4 * ne) {
+      v = (uint32_t)J->out.layout_vid[o / 4];
+    } else if ((o -= 4 * ne) < 4 * tw) {
+      v = J->out.bases[o / 4];
+    } else {
+      o -= 4 * tw;
+      for (int k = 0; k < 4; ++k)
+        if (o + k < ne) v |= (uint32_t)J->out.layout_rev[o + k] << (8 * k);
+    }
+    dst[wd] = v;
+  }
+}
+
 }  // namespace cg
 
 // ---------------------------------------------------------------------------
@@ -1464,17 +1571,31 @@ struct cg_batch {
   size_t mem_bytes;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  // host copies of the tables of the current plan (kept until the next plan:
+  // a plan's uploads may still read them)
+  std::vector<BJob> h_jobs;
+  std::vector<int32_t> h_tiles, h_order;
+  std::vector<MaskTile> h_mtiles;
 };
 
-static int check_job(const cg_job &J, int i) {
-  const cg_graph &g = J.g;
-  if (g.n < 0 || g.n >= (1 << 30) || g.m < 0 || !g.row_ptr ||
-      (g.m > 0 && (!g.col || !g.ovl || !g.strand)) ||
-      (g.n > 0 && (!g.read_len || !g.read_off || !g.seq)) || ((g.pre == nullptr) != (g.post == nullptr)))
-    return set_error(CG_EINVAL, "job %d: bad graph", i);
+// sizes and parameters of a job (all that its share of the batch memory
+// depends on)
+static int check_job_sizes(const cg_job &J, int i) {
+  if (J.g.n < 0 || J.g.n >= (1 << 30) || J.g.m < 0)
+    return set_error(CG_EINVAL, "job %d: n=%d m=%d", i, J.g.n, J.g.m);
   if (J.P < 1 || J.P > 65536) return set_error(CG_EINVAL, "job %d: P=%d outside [1, 65536]", i, J.P);
   if (J.weight != CG_WEIGHT_READS && J.weight != CG_WEIGHT_BASES)
     return set_error(CG_EINVAL, "job %d: weight=%d", i, J.weight);
+  return CG_OK;
+}
+
+static int check_job(const cg_job &J, int i) {
+  const cg_graph &g = J.g;
+  int rc = check_job_sizes(J, i);
+  if (rc) return rc;
+  if (!g.row_ptr || (g.m > 0 && (!g.col || !g.ovl || !g.strand)) ||
+      (g.n > 0 && (!g.read_len || !g.read_off || !g.seq)) || ((g.pre == nullptr) != (g.post == nullptr)))
+    return set_error(CG_EINVAL, "job %d: bad graph", i);
   const cg_parts &p = J.parts;
   const cg_local &l = J.local;
   const cg_contigs &c = J.contigs;
@@ -1495,12 +1616,18 @@ static int check_job(const cg_job &J, int i) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-extern "C" {
+// Where every table of a batch lives in its device memory, for one set of
+// jobs (sizes only; plan_fill writes the tables).
+struct Plan {
+  int32_t n_jobs = 0, nv = 0, n_mt = 0, n_internal = 0;
+  int64_t sum_chunks = 0;
+  bool any_bases = false;
+  size_t o_jobs, o_tiles, o_cbase, o_pbase, o_hbase, o_jcnt, o_cjob, o_wq, o_wqh, o_wqc, o_wqm,
+      o_hjob, o_counters, o_order, o_mtiles, o_mtcnt, total = 0;
+  std::vector<size_t> job_off;
+};
 
-int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
-                    const cg_batch_params *params, cg_batch **out) {
-  if (!ctx || !jobs || !out || n_jobs < 1) return set_error(CG_EINVAL, "bad batch arguments");
-  *out = nullptr;
+static int check_params(cg_ctx *ctx, const cg_batch_params *params, cg_batch_params *out) {
   cg_batch_params prm = params ? *params : cg_batch_params{0, 0, 0};
   if (prm.vertex_tile == 0) prm.vertex_tile = 256;
   if (prm.vertex_tile != 256 && prm.vertex_tile != 512 && prm.vertex_tile != 1024)
@@ -1515,75 +1642,207 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     prm.persist_blocks = 4 * prop.multiProcessorCount;
   }
   if (prm.persist_blocks < 1) return set_error(CG_EINVAL, "persist_blocks must be positive");
+  *out = prm;
+  return CG_OK;
+}
+
+// sizes and offsets of a plan for these jobs (checks every job: all of it,
+// or with sizes_only its sizes and parameters)
+static int plan_sizes(int32_t n_jobs, const cg_job *jobs, int vertex_tile, Plan *P,
+                      bool sizes_only = false) {
+  if (!jobs || n_jobs < 1) return set_error(CG_EINVAL, "a batch needs at least one job");
   int64_t total_n = 0;
   for (int i = 0; i < n_jobs; ++i) {
-    int rc = check_job(jobs[i], i);
+    int rc = sizes_only ? check_job_sizes(jobs[i], i) : check_job(jobs[i], i);
     if (rc) return rc;
     total_n += jobs[i].g.n + 1;
   }
   if (total_n >= (1ll << 31)) return set_error(CG_EUNSUPPORTED, "batch holds 2^31 or more reads");
-  const int T = prm.vertex_tile;
-  std::vector<BJob> hj(n_jobs);
-  std::vector<int32_t> tile_job;
+  const int T = vertex_tile;
   size_t at = 0;
   auto take = [&](size_t bytes) {
     size_t here = at;
     at += align256(bytes);
     return here;
   };
-  const size_t o_jobs = take(sizeof(BJob) * n_jobs);
-  int32_t nv = 0;
-  for (int i = 0; i < n_jobs; ++i) {
-    const int32_t cnt = (int32_t)((jobs[i].g.n + 1 + T - 1) / T);
-    hj[i].vt_first = nv;
-    hj[i].vt_count = cnt;
-    for (int32_t t = 0; t < cnt; ++t) tile_job.push_back(i);
-    nv += cnt;
-  }
-  const size_t o_tiles = take(sizeof(int32_t) * nv);
-  const size_t o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
-  const size_t o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
-  const size_t o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
-  const size_t o_jcnt = take(sizeof(int2) * (n_jobs > 0 ? n_jobs : 1));
-  int64_t sum_n = 0, sum_chunks = 0;
+  P->n_jobs = n_jobs;
+  P->o_jobs = take(sizeof(BJob) * n_jobs);
+  P->nv = 0;
+  for (int i = 0; i < n_jobs; ++i) P->nv += (int32_t)((jobs[i].g.n + 1 + T - 1) / T);
+  P->o_tiles = take(sizeof(int32_t) * P->nv);
+  P->o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
+  P->o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
+  P->o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
+  P->o_jcnt = take(sizeof(int2) * n_jobs);
+  int64_t sum_n = 0;
+  P->sum_chunks = 0;
+  P->any_bases = false;
   for (int i = 0; i < n_jobs; ++i) {
     sum_n += jobs[i].g.n;
-    sum_chunks += (jobs[i].g.n + kChunkPieces - 1) / kChunkPieces;
+    P->sum_chunks += (jobs[i].g.n + kChunkPieces - 1) / kChunkPieces;
+    P->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
   }
-  const size_t o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
-  const size_t o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
-  const size_t o_wqh = take(sizeof(int32_t) * kWqBuckets);
-  const size_t o_wqc = take(sizeof(int32_t) * kWqBuckets);
-  const size_t o_wqm = take(sizeof(int32_t) * 8);
-  const size_t o_hjob = take(sizeof(int32_t) * (size_t)(sum_chunks > 0 ? sum_chunks : 1));
-  const size_t o_counters = take(sizeof(unsigned int) * 8);
-  const size_t o_order = take(sizeof(int32_t) * n_jobs);
-  std::vector<size_t> job_off(n_jobs);
-  int32_t n_internal = 0, n_mt = 0;
+  P->o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
+  P->o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
+  P->o_wqh = take(sizeof(int32_t) * kWqBuckets);
+  P->o_wqc = take(sizeof(int32_t) * kWqBuckets);
+  P->o_wqm = take(sizeof(int32_t) * 8);
+  P->o_hjob = take(sizeof(int32_t) * (size_t)(P->sum_chunks > 0 ? P->sum_chunks : 1));
+  P->o_counters = take(sizeof(unsigned int) * 8);
+  P->o_order = take(sizeof(int32_t) * n_jobs);
+  P->job_off.resize(n_jobs);
+  P->n_internal = P->n_mt = 0;
   for (int i = 0; i < n_jobs; ++i) {
     // the components pass holds a job's reads as LDS bitmaps and its reads
     // of degree 1-2 (at most its entries) in LDS; larger jobs go through the
     // single-graph kernels
-    hj[i].external =
-        (jobs[i].g.n > kMcReadCap || jobs[i].g.m > kExternalEntries) ? 1 : 0;
-    n_internal += hj[i].external ? 0 : 1;
-    hj[i].mt_first = n_mt;
-    hj[i].mt_count = hj[i].external ? 0 : (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
-    n_mt += hj[i].mt_count;
-    job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
+    const bool ext = jobs[i].g.n > kMcReadCap || jobs[i].g.m > kExternalEntries;
+    P->n_internal += ext ? 0 : 1;
+    P->n_mt += ext ? 0 : (jobs[i].g.n + kMaskTile - 1) / kMaskTile;
+    P->job_off[i] = take(layout(jobs[i].g.n, jobs[i].g.m, jobs[i].P).total);
   }
-  const size_t o_mtiles = take(sizeof(MaskTile) * (n_mt > 0 ? n_mt : 1));
-  const size_t o_mtcnt = take(sizeof(int2) * (n_mt > 0 ? n_mt : 1));
+  P->o_mtiles = take(sizeof(MaskTile) * (P->n_mt > 0 ? P->n_mt : 1));
+  P->o_mtcnt = take(sizeof(int2) * (P->n_mt > 0 ? P->n_mt : 1));
+  P->total = at;
+  return CG_OK;
+}
+
+// the plan's tables for the batch memory at b->mem, in b's host copies, and
+// b's fields and device pointers; the tables still have to be uploaded
+static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
+  const int n_jobs = P.n_jobs;
+  const int T = b->prm.vertex_tile;
+  char *mem = b->mem;
+  b->h_jobs.assign(n_jobs, BJob{});
+  b->h_tiles.clear();
+  b->h_mtiles.clear();
+  b->h_order.resize(n_jobs);
+  b->ext_jobs.clear();
+  b->ext_s.clear();
+  int2 *d_mtcnt = (int2 *)(mem + P.o_mtcnt);
+  int32_t nv = 0, n_mt = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    const cg_job &J = jobs[i];
+    BJob &h = b->h_jobs[i];
+    h.g = J.g;
+    h.P = J.P;
+    h.min_reads = J.min_reads;
+    h.weight = J.weight;
+    h.flags = J.flags;
+    h.counts = J.d_counts;
+    h.label = J.label;
+    h.parts = J.parts;
+    h.local = J.local;
+    h.out = J.contigs;
+    const int32_t cnt = (int32_t)((J.g.n + 1 + T - 1) / T);
+    h.vt_first = nv;
+    h.vt_count = cnt;
+    for (int32_t t = 0; t < cnt; ++t) b->h_tiles.push_back(i);
+    nv += cnt;
+    h.external = (J.g.n > kMcReadCap || J.g.m > kExternalEntries) ? 1 : 0;
+    // carve this job's scratch slice the way a context carves its scratch
+    cg_ctx view{};
+    view.scratch = mem + P.job_off[i];
+    view.scratch_bytes = layout(J.g.n, J.g.m, J.P).total;
+    carve(&view, J.g.n, J.g.m, J.P, &h.s);
+    h.mt_first = n_mt;
+    h.mt_count = h.external ? 0 : (J.g.n + kMaskTile - 1) / kMaskTile;
+    // the mask tiles: the job's list lives in its walk scratch, its bitmaps
+    // in its fill scratch (both reused by later steps)
+    for (int32_t v0 = 0; !h.external && v0 < J.g.n; v0 += kMaskTile)
+      b->h_mtiles.push_back(MaskTile{J.g.row_ptr, J.g.col, (int4 *)h.s.walk,
+                                     (uint32_t *)h.s.fill, d_mtcnt + n_mt++, J.g.n, v0,
+                                     (J.g.n + 31) / 32, 0});
+    if (h.external) {
+      b->ext_jobs.push_back(J);
+      b->ext_s.push_back(h.s);
+    }
+  }
+  for (int i = 0; i < n_jobs; ++i) b->h_order[i] = i;
+  std::stable_sort(b->h_order.begin(), b->h_order.end(),
+                   [&](int a, int c) { return jobs[a].g.n > jobs[c].g.n; });
+  b->n_jobs = n_jobs;
+  b->n_vtiles = nv;
+  b->chunk_slots = P.sum_chunks;
+  b->n_internal = P.n_internal;
+  b->any_bases = P.any_bases;
+  b->mtiles = (const MaskTile *)(mem + P.o_mtiles);
+  BatchDev &d = b->dev;
+  d.jobs = (BJob *)(mem + P.o_jobs);
+  d.tile_job = (int32_t *)(mem + P.o_tiles);
+  d.comp_base = (int32_t *)(mem + P.o_cbase);
+  d.piece_base = (int32_t *)(mem + P.o_pbase);
+  d.chunk_base = (int32_t *)(mem + P.o_hbase);
+  d.job_cnt = (int2 *)(mem + P.o_jcnt);
+  d.wq = (int4 *)(mem + P.o_wq);
+  d.wq_hist = (int32_t *)(mem + P.o_wqh);
+  d.wq_cur = (int32_t *)(mem + P.o_wqc);
+  d.wq_meta = (int32_t *)(mem + P.o_wqm);
+  d.comp_job = (int32_t *)(mem + P.o_cjob);
+  d.chunk_job = (int32_t *)(mem + P.o_hjob);
+  d.counters = (unsigned int *)(mem + P.o_counters);
+  d.job_order = (const int32_t *)(mem + P.o_order);
+  d.mt_cnt = d_mtcnt;
+  d.n_mtiles = n_mt;
+  d.fixed = b->ctx->fixed;
+  d.n_jobs = n_jobs;
+  d.n_vtiles = nv;
+}
+
+// enqueue the plan's uploads on st (tables from b's host copies); the
+// launch counters are cleared by a small kernel (no memset node, so the
+// sequence can sit in a captured graph)
+__global__ void kb_clear_counters(unsigned int *c) {
+  if (threadIdx.x < 8) c[threadIdx.x] = 0;
+}
+
+// the look-back status words of a job that runs through the single-graph
+// kernels start at zero (its slice of the batch memory may hold anything
+// from an earlier plan)
+__global__ void kb_clear_status(unsigned long long *p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+static int plan_upload(cg_batch *b, const Plan &P, hipStream_t st) {
+  char *mem = b->mem;
+  int rc = hip_check(hipMemcpyAsync(mem + P.o_jobs, b->h_jobs.data(), sizeof(BJob) * P.n_jobs,
+                                    hipMemcpyHostToDevice, st), "hipMemcpyAsync(jobs)");
+  if (!rc && P.nv > 0)
+    rc = hip_check(hipMemcpyAsync(mem + P.o_tiles, b->h_tiles.data(), sizeof(int32_t) * P.nv,
+                                  hipMemcpyHostToDevice, st), "hipMemcpyAsync(tiles)");
+  if (!rc)
+    rc = hip_check(hipMemcpyAsync(mem + P.o_order, b->h_order.data(), sizeof(int32_t) * P.n_jobs,
+                                  hipMemcpyHostToDevice, st), "hipMemcpyAsync(job order)");
+  if (!rc && P.n_mt > 0)
+    rc = hip_check(hipMemcpyAsync(mem + P.o_mtiles, b->h_mtiles.data(),
+                                  sizeof(MaskTile) * P.n_mt, hipMemcpyHostToDevice, st),
+                   "hipMemcpyAsync(mask tiles)");
+  if (!rc) {
+    hipLaunchKernelGGL(kb_clear_counters, dim3(1), dim3(64), 0, st, b->dev.counters);
+    rc = hip_check(hipGetLastError(), "kb_clear_counters");
+  }
+  for (size_t e = 0; !rc && e < b->ext_jobs.size(); ++e) {
+    const int words = scan_blocks((int64_t)(b->ext_jobs[e].g.n > 0 ? b->ext_jobs[e].g.n : 1) + 1) + 1;
+    hipLaunchKernelGGL(kb_clear_status, dim3((words + 255) / 256), dim3(256), 0, st,
+                       b->ext_s[e].scan_status, words);
+    rc = hip_check(hipGetLastError(), "kb_clear_status");
+  }
+  return rc;
+}
+
+static int batch_alloc(cg_ctx *ctx, const cg_batch_params &prm, size_t bytes, cg_batch **out) {
   cg_batch *b = new (std::nothrow) cg_batch();
   if (!b) return set_error(CG_EINVAL, "out of host memory");
   b->ctx = ctx;
-  b->n_jobs = n_jobs;
-  b->n_vtiles = nv;
-  b->chunk_slots = sum_chunks;
-  b->n_internal = n_internal;
-  b->any_bases = false;
-  for (int i = 0; i < n_jobs; ++i) b->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
   b->prm = prm;
+  b->n_jobs = b->n_vtiles = b->n_internal = 0;
+  b->any_bases = false;
+  b->chunk_slots = 0;
+  b->mtiles = nullptr;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->mem = nullptr;
+  b->mem_bytes = bytes > 0 ? bytes : 256;
   {
     int dev = 0, cus = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1602,100 +1861,97 @@ int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
     b->res_walk_small = k3 * cus;
     b->res_walk = k4 * cus;
   }
-  b->mem_bytes = at;
-  b->mem = nullptr;
-  b->graph = nullptr;
-  b->exec = nullptr;
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
-  int rc = hip_check(hipMalloc((void **)&b->mem, at), "hipMalloc(batch)");
-  if (!rc) rc = hip_check(hipMemset(b->mem, 0, at), "hipMemset(batch)");
-  if (!rc) {
-    for (int i = 0; i < n_jobs; ++i) {
-      const cg_job &J = jobs[i];
-      BJob &h = hj[i];
-      h.g = J.g;
-      h.P = J.P;
-      h.min_reads = J.min_reads;
-      h.weight = J.weight;
-      h.flags = J.flags;
-      h.counts = J.d_counts;
-      h.label = J.label;
-      h.parts = J.parts;
-      h.local = J.local;
-      h.out = J.contigs;
-      // carve this job's scratch slice the way a context carves its scratch
-      cg_ctx view{};
-      view.scratch = b->mem + job_off[i];
-      view.scratch_bytes = layout(J.g.n, J.g.m, J.P).total;
-      carve(&view, J.g.n, J.g.m, J.P, &h.s);
-      if (h.external) {
-        b->ext_jobs.push_back(J);
-        b->ext_s.push_back(h.s);
-      }
-    }
-    // the mask tiles: each job's list lives in its walk scratch, its bitmaps
-    // in its fill scratch (both reused by later steps)
-    std::vector<MaskTile> mt;
-    mt.reserve(n_mt);
-    int2 *d_mtcnt = (int2 *)(b->mem + o_mtcnt);
-    for (int i = 0; i < n_jobs; ++i)
-      for (int32_t v0 = 0; !hj[i].external && v0 < jobs[i].g.n; v0 += kMaskTile)
-        mt.push_back(MaskTile{jobs[i].g.row_ptr, jobs[i].g.col, (int4 *)hj[i].s.walk,
-                              (uint32_t *)hj[i].s.fill, d_mtcnt + (int32_t)mt.size(),
-                              jobs[i].g.n, v0, (jobs[i].g.n + 31) / 32, 0});
-    if (n_mt > 0)
-      rc = hip_check(hipMemcpy(b->mem + o_mtiles, mt.data(), sizeof(MaskTile) * n_mt,
-                               hipMemcpyHostToDevice), "hipMemcpy(mask tiles)");
-    std::vector<int32_t> order(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return jobs[a].g.n > jobs[c].g.n; });
-    if (!rc)
-      rc = hip_check(hipMemcpy(b->mem + o_order, order.data(), sizeof(int32_t) * n_jobs,
-                               hipMemcpyHostToDevice), "hipMemcpy(job order)");
-  }
-  if (!rc) {
-    rc = hip_check(hipMemcpy(b->mem + o_jobs, hj.data(), sizeof(BJob) * n_jobs,
-                             hipMemcpyHostToDevice), "hipMemcpy(jobs)");
-  }
-  if (!rc)
-    rc = hip_check(hipMemcpy(b->mem + o_tiles, tile_job.data(), sizeof(int32_t) * nv,
-                             hipMemcpyHostToDevice), "hipMemcpy(tiles)");
+  int rc = hip_check(hipMalloc((void **)&b->mem, b->mem_bytes), "hipMalloc(batch)");
+  if (!rc) rc = hip_check(hipMemset(b->mem, 0, b->mem_bytes), "hipMemset(batch)");
   (void)hipSetDevice(prev);
   if (rc) {
     if (b->mem) (void)hipFree(b->mem);
     delete b;
     return rc;
   }
-  BatchDev &d = b->dev;
-  d.jobs = (BJob *)(b->mem + o_jobs);
-  d.tile_job = (int32_t *)(b->mem + o_tiles);
-  d.comp_base = (int32_t *)(b->mem + o_cbase);
-  d.piece_base = (int32_t *)(b->mem + o_pbase);
-  d.chunk_base = (int32_t *)(b->mem + o_hbase);
-  d.job_cnt = (int2 *)(b->mem + o_jcnt);
-  d.wq = (int4 *)(b->mem + o_wq);
-  d.wq_hist = (int32_t *)(b->mem + o_wqh);
-  d.wq_cur = (int32_t *)(b->mem + o_wqc);
-  d.wq_meta = (int32_t *)(b->mem + o_wqm);
-  d.comp_job = (int32_t *)(b->mem + o_cjob);
-  d.chunk_job = (int32_t *)(b->mem + o_hjob);
-  d.counters = (unsigned int *)(b->mem + o_counters);
-  d.job_order = (const int32_t *)(b->mem + o_order);
-  d.mt_cnt = (int2 *)(b->mem + o_mtcnt);
-  d.n_mtiles = n_mt;
-  b->mtiles = (const MaskTile *)(b->mem + o_mtiles);
-  d.fixed = ctx->fixed;
-  d.n_jobs = n_jobs;
-  d.n_vtiles = nv;
   *out = b;
   return CG_OK;
 }
 
+extern "C" {
+
+int cg_batch_bytes(int32_t n_jobs, const cg_job *jobs, const cg_batch_params *params,
+                   uint64_t *bytes) {
+  if (!bytes) return set_error(CG_EINVAL, "bytes is NULL");
+  const int T = params && params->vertex_tile ? params->vertex_tile : 256;
+  if (T != 256 && T != 512 && T != 1024)
+    return set_error(CG_EINVAL, "vertex_tile must be 256, 512 or 1024");
+  Plan P;
+  int rc = plan_sizes(n_jobs, jobs, T, &P, true);
+  if (rc) return rc;
+  *bytes = (uint64_t)P.total;
+  return CG_OK;
+}
+
+int cg_batch_create(cg_ctx *ctx, int32_t n_jobs, const cg_job *jobs,
+                    const cg_batch_params *params, cg_batch **out) {
+  if (!ctx || !jobs || !out || n_jobs < 1) return set_error(CG_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  cg_batch_params prm;
+  int rc = check_params(ctx, params, &prm);
+  if (rc) return rc;
+  Plan P;
+  if ((rc = plan_sizes(n_jobs, jobs, prm.vertex_tile, &P))) return rc;
+  cg_batch *b = nullptr;
+  if ((rc = batch_alloc(ctx, prm, P.total, &b))) return rc;
+  plan_fill(b, P, jobs);
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  rc = plan_upload(b, P, nullptr);
+  if (!rc) rc = hip_check(hipStreamSynchronize(nullptr), "hipStreamSynchronize");
+  (void)hipSetDevice(prev);
+  if (rc) {
+    (void)hipFree(b->mem);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CG_OK;
+}
+
+int cg_batch_create_empty(cg_ctx *ctx, uint64_t bytes, const cg_batch_params *params,
+                          cg_batch **out) {
+  if (!ctx || !out) return set_error(CG_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  cg_batch_params prm;
+  int rc = check_params(ctx, params, &prm);
+  if (rc) return rc;
+  return batch_alloc(ctx, prm, (size_t)bytes, out);
+}
+
+int cg_batch_plan(cg_batch *b, int32_t n_jobs, const cg_job *jobs, void *stream) {
+  if (!b) return set_error(CG_EINVAL, "batch is NULL");
+  Plan P;
+  int rc = plan_sizes(n_jobs, jobs, b->prm.vertex_tile, &P);
+  if (rc) return rc;
+  if (P.total > b->mem_bytes)
+    return set_error(CG_ECAPACITY, "the jobs need %zu bytes of batch memory, the batch has %zu",
+                     P.total, b->mem_bytes);
+  // a captured graph holds the previous plan's launch shapes
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  plan_fill(b, P, jobs);
+  return plan_upload(b, P, (hipStream_t)stream);
+}
+
 int cg_batch_run(cg_batch *b, void *stream) {
   if (!b) return set_error(CG_EINVAL, "batch is NULL");
+  if (b->n_jobs < 1) return set_error(CG_EINVAL, "batch has no jobs (cg_batch_plan)");
   hipStream_t st = (hipStream_t)stream;
   cg_ctx *ctx = b->ctx;
   const BatchDev &B = b->dev;
@@ -1737,6 +1993,33 @@ int cg_batch_run(cg_batch *b, void *stream) {
   const int64_t cgrid = (b->chunk_slots + wpb - 1) / wpb;
   CG_LAUNCH(ctx, kb_copy, dim3((unsigned)(cgrid > 0 ? cgrid : 1)), dim3(b->prm.copy_block), st, B);
   return hip_check(hipGetLastError(), "cg_batch_run");
+}
+
+int cg_batch_counts(cg_batch *b, int64_t *d_counts, void *stream) {
+  if (!b || !d_counts) return set_error(CG_EINVAL, "bad arguments");
+  if (b->n_jobs < 1) return set_error(CG_EINVAL, "batch has no jobs (cg_batch_plan)");
+  CG_LAUNCH(b->ctx, kb_counts, dim3(1), dim3(kCountsBlock), (hipStream_t)stream, b->dev.jobs,
+            b->n_jobs, d_counts);
+  return hip_check(hipGetLastError(), "cg_batch_counts");
+}
+
+int cg_batch_pack(cg_batch *b, const int64_t *d_counts, void *d_dst, uint64_t dst_bytes,
+                  void *stream) {
+  if (!b || !d_counts || (dst_bytes > 0 && !d_dst)) return set_error(CG_EINVAL, "bad arguments");
+  if (b->n_jobs < 1) return set_error(CG_EINVAL, "batch has no jobs (cg_batch_plan)");
+  if ((uintptr_t)d_dst & 15) return set_error(CG_EINVAL, "d_dst must be 16-byte aligned");
+  if (dst_bytes < 4) return CG_OK;
+  int dev = 0, cus = 0;
+  int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (!rc) rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev),
+                          "hipDeviceGetAttribute");
+  if (rc) return rc;
+  const int64_t words = (int64_t)(dst_bytes / 4);
+  int64_t grid = (words + kPackBlock - 1) / kPackBlock;
+  if (grid > 8 * (int64_t)cus) grid = 8 * (int64_t)cus;
+  CG_LAUNCH(b->ctx, kb_pack, dim3((unsigned)grid), dim3(kPackBlock), (hipStream_t)stream,
+            b->dev.jobs, b->n_jobs, d_counts, (uint32_t *)d_dst, words);
+  return hip_check(hipGetLastError(), "cg_batch_pack");
 }
 
 int cg_batch_capture(cg_batch *b, void *stream) {

@@ -214,3 +214,115 @@ def test_batch_lpt_equal_runs(cg):
     _check_all(cg, graphs, params, outs, wants, "equal runs")
     b.close()
     ctx.close()
+
+
+def test_batch_replan(cg):
+    """One batch's memory planned with one job set after another (as a
+    serving loop does): each run equals the oracle, and a plan beyond the
+    batch's memory is refused without touching it."""
+    import torch
+    graphs = _mixed_graphs()
+    sets = [list(range(0, 20)), list(range(40, 52)), list(range(20, 45)), list(range(0, 20))]
+    params = [_params(i, g) for i, g in enumerate(graphs)]
+    wants = {}
+    dev = torch.device("cuda")
+    big = max(range(len(graphs)), key=lambda i: cg.footprint(graphs[i].n, graphs[i].m,
+                                                             params[i][0]))
+    ctx = cg.Context.for_graph(graphs[big].n, graphs[big].m, params[big][0])
+    dgs = {}
+    jobs_of = {}
+    for sel in sets:
+        for i in sel:
+            if i not in dgs:
+                dgs[i] = cg.DeviceGraph(graphs[i], dev)
+    cap = 0
+    for k, sel in enumerate(sets):
+        outs = [cg.Outputs(graphs[i].n, params[i][0], graphs[i].seq_words, dev) for i in sel]
+        jobs_of[k] = [(dgs[i], o) + tuple(params[i]) for i, o in zip(sel, outs)]
+        cap = max(cap, cg.batch_bytes(jobs_of[k]))
+    b = cg.Batch.empty(ctx, cap)
+    s = torch.cuda.Stream()
+    for k, sel in enumerate(sets):
+        _say("replan", k, "jobs", len(sel))
+        with torch.cuda.stream(s):
+            b.plan(jobs_of[k], s)
+            b.run(s)
+        s.synchronize()
+        assert ctx.status(s) == 0
+        for i, job in zip(sel, jobs_of[k]):
+            if i not in wants:
+                P, mr, w = params[i]
+                wants[i] = oracle.run(graphs[i], P=P, min_reads=mr, weight=w)
+            got = cg.to_host(job[1], graphs[i].n)
+            bad = mismatches(got, wants[i])
+            assert bad == [], ("replan", k, i, bad)
+    small = cg.Batch.empty(ctx, 4096)
+    with pytest.raises(cg.CgError) as e:
+        small.plan(jobs_of[1], s)
+    assert e.value.code == cg.CG_ECAPACITY
+    small.close()
+    b.close()
+    ctx.close()
+
+
+def test_batch_carved_outputs_and_packed_results(cg):
+    """Outputs carved from one buffer per batch (cg_job_outputs), results
+    counted (cg_batch_counts) and packed (cg_batch_pack) into one buffer:
+    every job's unpacked records, layout and bases equal the oracle, the
+    offsets tile the packed buffer, and nothing is written past dst_bytes."""
+    import torch
+    graphs = _mixed_graphs()
+    params = [_params(i, g) for i, g in enumerate(graphs)]
+    dev = torch.device("cuda")
+    ctx = cg.Context(0, 0)
+    dgs = [cg.DeviceGraph(g, dev) for g in graphs]
+    sizes = [cg.job_outputs_bytes(g.n, p[0], g.seq_words) for g, p in zip(graphs, params)]
+    buf = torch.full((sum(sizes),), 0xA5, dtype=torch.uint8, device=dev)
+    outs, at = [], 0
+    for g, p, nb in zip(graphs, params, sizes):
+        outs.append(cg.CarvedOutputs(buf, at, g.n, p[0], g.seq_words))
+        at += nb
+    jobs = [(dg, o) + tuple(p) for dg, o, p in zip(dgs, outs, params)]
+    b = cg.Batch.empty(ctx, cg.batch_bytes(jobs))
+    s = torch.cuda.Stream()
+    _say("carved batch", len(jobs))
+    with torch.cuda.stream(s):
+        b.plan(jobs, s)
+        b.run(s)
+        d_counts = torch.empty(4 * len(jobs) + 1, dtype=torch.int64, device=dev)
+        b.counts(d_counts, s)
+    s.synchronize()
+    assert ctx.status(s) == 0
+    counts = d_counts.cpu().numpy()
+    rows = counts[:-1].reshape(-1, 4)
+    total = int(counts[-1])
+    assert total % 16 == 0 and rows[0, 3] == 0
+    assert np.all(rows[:, 3] % 16 == 0)
+    ends = rows[:, 3] + ((40 * rows[:, 0] + 5 * rows[:, 1] + 4 * rows[:, 2] + 15) // 16) * 16
+    assert np.array_equal(ends[:-1], rows[1:, 3]) and ends[-1] == total
+    # packed into a buffer with a guard band that must stay untouched
+    dst = torch.full((total + 4096,), 0x5A, dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(s):
+        b.pack(d_counts, dst[:total], s)
+    s.synchronize()
+    packed = dst.cpu().numpy()
+    assert np.all(packed[total:] == 0x5A)
+    for i, (g, p) in enumerate(zip(graphs, params)):
+        want = oracle.run(g, P=p[0], min_reads=p[1], weight=p[2])["contigs"]
+        got = cg.unpack_results(packed, rows[i])
+        assert rows[i][0] == want["label"].shape[0], i
+        assert rows[i][2] == want["total_words"], i
+        for name in ("label", "bin", "start", "n_reads", "len", "base_off", "cflags",
+                     "layout_off", "layout_vid", "layout_rev", "bases"):
+            assert np.array_equal(got[name].astype(np.int64), want[name].astype(np.int64)), \
+                (i, name)
+    # a short destination: the copy stops at dst_bytes
+    half = (total // 2) & ~15
+    dst.fill_(0x5A)
+    with torch.cuda.stream(s):
+        b.pack(d_counts, dst[:half], s)
+    s.synchronize()
+    short = dst.cpu().numpy()
+    assert np.array_equal(short[:half], packed[:half]) and np.all(short[half:] == 0x5A)
+    b.close()
+    ctx.close()
