@@ -211,7 +211,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batch", choices=["batch", "plain50", "large1g", "serve", "reduce"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: measured requests")
-    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent requests on the GPU")
+    ap.add_argument("--max-wave", type=int, default=64, help="serve: requests per wave at most")
+    ap.add_argument("--lane-bytes", type=int, default=2 << 30,
+                    help="serve: batch memory of each of the two lanes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="bound on the oracle's CPU baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -642,14 +644,19 @@ def reduce_bench(args):
 def serve_bench(args):
     """Continuous-batching serving of contig-generation requests: a pool of
     synthetic request graphs (genome 1-100 Mbp log-uniform, 15-30x, reads
-    LN(12k, 4k), 1-2% branch edges, P = 64), a seeded Poisson stream sampling
-    the pool at the rate that keeps the GPU busy about 80% of the time, and
-    p50 / p99 latency from arrival to the result in host memory.  Measured
-    with the pool resident in HBM (the reported value) and with every
-    request uploading its graph (with_upload)."""
+    LN(12k, 4k), 1-2% branch edges, P = 64) and a seeded Poisson stream
+    sampling the pool.  Admitted requests are served in waves, each wave one
+    batched launch sequence (cg_batch_plan + cg_batch_run) on one of two
+    lanes.  The arrival rate is searched for a device-busy fraction of about
+    0.8, device busy measured from GPU events around each wave's launches;
+    p50 / p99 latency runs from arrival to the result in host memory.
+    Measured with the pool resident in HBM (the reported value) and with
+    every request uploading its graph (with_upload).  Every measured
+    request's contigs are compared with the oracle's for its graph."""
     import numpy as np
     import torch
 
+    import oracle
     import synth
     from paper_2207_04350_amd import cg, serve
 
@@ -661,51 +668,79 @@ def serve_bench(args):
     log("request pool: %d graphs (%.1f M reads, %.1f GB packed reads) in %.1fs" % (
         n_pool, sum(h.n for h in pool) / 1e6, sum(h.seq_words for h in pool) * 4 / 1e9,
         time.time() - t0))
+    # the oracle's contigs of every pool graph (parity), timed (cpu_baseline)
+    wants, spent = [], 0.0
+    for h in pool:
+        tm = {}
+        wants.append(oracle.run(h.graph, P=64, min_reads=2, timings=tm)["contigs"])
+        spent += tm["total"]
+    log("oracle over the pool: %.1fs" % spent)
+    fields = ("label", "bin", "start", "n_reads", "len", "base_off", "cflags", "layout_off",
+              "layout_vid", "layout_rev", "bases")
+
+    def identical(q):
+        k = q.pool_index
+        r = q.result
+        return r is not None and r["status"] == 0 and all(
+            np.array_equal(r[f].astype(np.int64), wants[k][f].astype(np.int64)) for f in fields)
+
     def measure(resident):
-        """Alone service times, then the arrival rate for a device-busy
-        fraction of about 0.8 and the latency and throughput of that stream.
-        resident: the pool is uploaded once and requests hold only outputs;
-        else every request uploads its graph when admitted."""
-        mk = lambda slots: serve.Server(max(h.n for h in pool), max(h.m for h in pool), 64,
-                                        slots=slots)
+        """Alone service, then the arrival rate for a device-busy fraction of
+        about 0.8 and the latency and throughput of that stream.  resident:
+        the pool is uploaded once and requests hold only outputs; else every
+        request uploads its graph when admitted."""
+        tag = "resident" if resident else "upload"
+
+        def mk(lanes, max_wave):
+            srv = serve.Server(serve.Device(lanes=lanes, lane_bytes=args.lane_bytes,
+                                            max_wave=max_wave))
+            if resident:
+                for h in pool:
+                    srv.make_resident(h)
+            return srv
 
         def stream(n, rate, seed):
             r = np.random.default_rng(seed)
             pick = r.integers(0, n_pool, size=n)
             arr = serve.poisson_arrivals(n, rate, seed + 1) if rate else np.zeros(n)
-            return [serve.Request(i, pool[k], 64, 2, float(t), resident=resident)
-                    for i, (k, t) in enumerate(zip(pick, arr))]
+            out = []
+            for i, (k, t) in enumerate(zip(pick, arr)):
+                q = serve.Request(i, pool[k], 64, 2, float(t), resident=resident)
+                q.pool_index = int(k)
+                out.append(q)
+            return out
 
-        # service time of each pool graph alone (also the warm-up)
-        srv1 = mk(1)
-        if resident:
-            for h in pool:
-                srv1.make_resident(h)
-        alone, _, _ = srv1.run([serve.Request(i, h, 64, 2, 0.0, resident=resident)
-                                for i, h in enumerate(pool)])
+        # each pool graph alone (one lane, waves of one; also the warm-up)
+        srv1 = mk(1, 1)
+        alone_reqs = []
+        for i, h in enumerate(pool):
+            q = serve.Request(i, h, 64, 2, 0.0, resident=resident)
+            q.pool_index = i
+            alone_reqs.append(q)
+        alone, _, _, iv = srv1.run(alone_reqs)
         srv1.close()
         del srv1
         svc = np.array([q.t_done - q.t_admit for q in alone])
-        rate = 0.8 / svc.mean()
-        tag = "resident" if resident else "upload"
-        log("%s, alone: mean service %.2f ms -> arrival rate %.1f requests/s"
-            % (tag, 1e3 * svc.mean(), rate))
-        srv = mk(args.slots)
-        if resident:
-            for h in pool:
-                srv.make_resident(h)
+        dev_alone = sum(e - s for s, e in iv) / len(alone)
+        rate = 0.8 / dev_alone
+        log("%s, alone: mean service %.2f ms, device %.3f ms per request -> start rate %.0f/s"
+            % (tag, 1e3 * svc.mean(), 1e3 * dev_alone, rate))
+        srv = mk(2, args.max_wave)
         n_warm = max(args.requests // 10, 10)
-        # bisection on the arrival rate for a device-busy fraction of about
-        # 0.8 (proportional steps until the target is bracketed); the run
-        # closest to it is the one reported
+        # search on the arrival rate for a device-busy fraction of about 0.8
+        # (proportional steps until the target is bracketed, then bisection);
+        # the run closest to it is the one reported
         lo = hi = None
         best = None
-        for attempt in range(5):
-            reqs, span, peak = srv.run(stream(n_warm + args.requests, rate, 20220709 + attempt))
-            busy = serve.busy_fraction(reqs, span)
-            log("%s, rate %.1f/s: busy %.2f over %.2fs" % (tag, rate, busy, span))
+        for attempt in range(6):
+            reqs, span, peak, iv = srv.run(stream(n_warm + args.requests, rate,
+                                                  20220709 + attempt))
+            busy = serve.busy_fraction(iv, span)
+            waves = len({q.wave for q in reqs if q.wave is not None})
+            log("%s, rate %.0f/s: device busy %.2f over %.2fs, %d waves"
+                % (tag, rate, busy, span, waves))
             if best is None or abs(busy - 0.8) < abs(best[0] - 0.8):
-                best = (busy, rate, reqs, span, peak)
+                best = (busy, rate, reqs, span, peak, waves)
             if abs(busy - 0.8) <= 0.03:
                 break
             if busy < 0.8:
@@ -714,20 +749,28 @@ def serve_bench(args):
                 hi = rate
             rate = 0.5 * (lo + hi) if lo is not None and hi is not None \
                 else rate * 0.8 / max(busy, 0.05)
-        busy, rate, reqs, span, peak = best
+        busy, rate, reqs, span, peak, waves = best
         meas = sorted(reqs, key=lambda q: q.rid)[n_warm:]
-        lat = np.array([q.t_done - q.arrival for q in meas])
-        bases = sum(int(q.result["len"].sum()) for q in meas)
+        failed = [q for q in meas if q.result is None]
+        ok = [q for q in meas if q.result is not None]
+        lat = np.array([q.t_done - q.arrival for q in ok])
+        bases = sum(int(q.result["len"].sum()) for q in ok)
         t_span = max(q.t_done for q in meas) - min(q.arrival for q in meas)
-        bad = sum(q.result["status"] != 0 for q in meas)
+        same = sum(identical(q) for q in meas)
+        log("%s: parity %d / %d identical to the oracle" % (tag, same, len(meas)))
         out = {"value": bases / t_span, "unit": "contig bases/s",
                "p50_ms": float(np.percentile(lat, 50) * 1e3),
                "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "busy_fraction": busy, "rate_per_s": rate, "requests": len(meas),
-               "warmup_requests": n_warm, "slots": args.slots, "budget_bytes": srv.budget,
-               "peak_admitted_bytes": int(peak), "device_status_errors": int(bad),
+               "device_busy_fraction": busy, "rate_per_s": rate, "requests": len(meas),
+               "failed_requests": len(failed), "waves": waves,
+               "mean_wave_requests": (n_warm + args.requests) / max(waves, 1),
+               "warmup_requests": n_warm, "lanes": 2, "max_wave": args.max_wave,
+               "lane_bytes": args.lane_bytes, "budget_bytes": srv.budget,
+               "peak_admitted_bytes": int(peak),
+               "parity": {"identical": int(same), "total": len(meas)},
                "alone_service_ms": {"mean": float(svc.mean() * 1e3),
-                                    "max": float(svc.max() * 1e3)}}
+                                    "max": float(svc.max() * 1e3)},
+               "alone_device_ms_per_request": dev_alone * 1e3}
         srv.close()
         return out
 
@@ -749,15 +792,19 @@ def serve_bench(args):
                                "1-100 Mbp log-uniform, 15-30x, reads LN(12k, 4k), 1-2%% branch "
                                "edges, P = 64)" % n_pool,
                    "resident": "the pool's graphs are resident in HBM (uploaded once, before "
-                               "the stream); each request allocates its outputs, runs the five "
-                               "steps and downloads its contigs",
+                               "the stream); each wave of admitted requests is planned into a "
+                               "lane's batch and run as one batched launch sequence, and its "
+                               "contigs are packed by the library and downloaded in one copy",
                    "latency": "arrival to contigs in pinned host memory (all five steps and "
-                              "the download; with_upload: the graph's upload as well)"},
+                              "the download; with_upload: the graph's upload and check as "
+                              "well)",
+                   "device_busy": "union of the GPU-event intervals of every wave's launches "
+                                  "and result packing, over the run's span"},
     })
     if not args.no_cpu:
-        import oracle
         graphs = [h.graph for h in pool]
-        spent, cbases, passes = 0.0, 0, 0
+        cbases = sum(int(w["len"].sum()) for w in wants)
+        passes = 1
         while spent < min(MIN_CPU_SECONDS, args.cpu_seconds):
             for g in graphs:
                 tm = {}
