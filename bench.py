@@ -721,35 +721,44 @@ def serve_bench(args):
         srv1.close()
         del srv1
         svc = np.array([q.t_done - q.t_admit for q in alone])
-        dev_alone = sum(e - s for s, e in iv) / len(alone)
+        dev_alone = sum(i[1] - i[0] for i in iv) / len(alone)
         rate = 0.8 / dev_alone
         log("%s, alone: mean service %.2f ms, device %.3f ms per request -> start rate %.0f/s"
             % (tag, 1e3 * svc.mean(), 1e3 * dev_alone, rate))
         srv = mk(2, args.max_wave)
         n_warm = max(args.requests // 10, 10)
-        # search on the arrival rate for a device-busy fraction of about 0.8
-        # (proportional steps until the target is bracketed, then bisection);
-        # the run closest to it is the one reported
+        # search on the arrival rate for a device-busy fraction of about 0.8:
+        # proportional steps (at most x4) until the target is bracketed, then
+        # bisection; when busy stops rising with the rate the loop is
+        # saturated (the host, not the device, sets the pace) and the
+        # saturated run is reported.  Otherwise the run closest to 0.8 is.
         lo = hi = None
         best = None
-        for attempt in range(6):
+        saturated = False
+        trail = []
+        for attempt in range(8):
             reqs, span, peak, iv = srv.run(stream(n_warm + args.requests, rate,
                                                   20220709 + attempt))
             busy = serve.busy_fraction(iv, span)
+            kbusy = serve.busy_fraction(iv, span, ("kernels",))
             waves = len({q.wave for q in reqs if q.wave is not None})
-            log("%s, rate %.0f/s: device busy %.2f over %.2fs, %d waves"
-                % (tag, rate, busy, span, waves))
+            log("%s, rate %.0f/s: device busy %.2f (kernels %.2f) over %.2fs, %d waves"
+                % (tag, rate, busy, kbusy, span, waves))
+            trail.append((rate, busy))
             if best is None or abs(busy - 0.8) < abs(best[0] - 0.8):
-                best = (busy, rate, reqs, span, peak, waves)
+                best = (busy, rate, reqs, span, peak, waves, kbusy)
             if abs(busy - 0.8) <= 0.03:
                 break
             if busy < 0.8:
-                lo = rate
+                if lo is not None and rate >= 4 * lo and busy < 1.1 * lo_busy:
+                    saturated = True
+                    break
+                lo, lo_busy = rate, busy
             else:
                 hi = rate
             rate = 0.5 * (lo + hi) if lo is not None and hi is not None \
-                else rate * 0.8 / max(busy, 0.05)
-        busy, rate, reqs, span, peak, waves = best
+                else rate * min(4.0, 0.8 / max(busy, 0.05))
+        busy, rate, reqs, span, peak, waves, kbusy = best
         meas = sorted(reqs, key=lambda q: q.rid)[n_warm:]
         failed = [q for q in meas if q.result is None]
         ok = [q for q in meas if q.result is not None]
@@ -761,7 +770,10 @@ def serve_bench(args):
         out = {"value": bases / t_span, "unit": "contig bases/s",
                "p50_ms": float(np.percentile(lat, 50) * 1e3),
                "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "device_busy_fraction": busy, "rate_per_s": rate, "requests": len(meas),
+               "device_busy_fraction": busy, "kernel_busy_fraction": kbusy,
+               "rate_per_s": rate, "requests": len(meas),
+               "saturated": saturated,
+               "rate_search": [[float(r), float(b)] for r, b in trail],
                "failed_requests": len(failed), "waves": waves,
                "mean_wave_requests": (n_warm + args.requests) / max(waves, 1),
                "warmup_requests": n_warm, "lanes": 2, "max_wave": args.max_wave,
@@ -798,8 +810,9 @@ def serve_bench(args):
                    "latency": "arrival to contigs in pinned host memory (all five steps and "
                               "the download; with_upload: the graph's upload and check as "
                               "well)",
-                   "device_busy": "union of the GPU-event intervals of every wave's launches "
-                                  "and result packing, over the run's span"},
+                   "device_busy": "union of the GPU-event intervals of every wave's kernels "
+                                  "(batched path, result packing) and result download, over "
+                                  "the run's span; kernel_busy_fraction: the kernels alone"},
     })
     if not args.no_cpu:
         graphs = [h.graph for h in pool]

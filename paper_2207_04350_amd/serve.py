@@ -114,9 +114,11 @@ def take_wave(ready, fits):
     return wave
 
 
-def busy_fraction(intervals, span):
-    """Fraction of `span` covered by the union of (start, end) intervals."""
-    iv = sorted(intervals)
+def busy_fraction(intervals, span, kinds=None):
+    """Fraction of `span` covered by the union of (start, end[, kind])
+    intervals (only those of the given kinds, if any are named)."""
+    iv = sorted((i[0], i[1]) for i in intervals
+                if kinds is None or (len(i) > 2 and i[2] in kinds))
     tot, cur_s, cur_e = 0.0, None, None
     for s, e in iv:
         if cur_e is None or s > cur_e:
@@ -391,8 +393,10 @@ class Device:
         time.sleep(s)
 
     def busy_intervals(self):
-        """(start, end) of every wave's launches, in seconds from the start,
-        measured by events on the device."""
+        """(start, end, kind) of the device's work, in seconds from the
+        start, measured by events on the device: kind "kernels" for a wave's
+        batched path and its result packing, "copy" for the download of its
+        packed results, "intake" for a graph's upload and check."""
         return list(self.intervals)
 
     # -- graphs ----------------------------------------------------------------
@@ -410,7 +414,7 @@ class Device:
             cg.validate(self.intake_ctx, dg, bad, stream)
             h = torch.empty(2, dtype=torch.int64, pin_memory=True)
             h.copy_(bad, non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
         return ev, h
 
@@ -433,9 +437,13 @@ class Device:
         if q.resident:
             self.graphs[q.rid] = self.resident[id(q.host)]
             return
+        torch = self.torch
+        ev_a = torch.cuda.Event(enable_timing=True)
+        ev_a.record(self.intake_stream)
         dg = self._upload(q.host, self.intake_stream)
         self.graphs[q.rid] = dg
-        self.checks[q.rid] = self._check_async(dg, self.intake_stream)
+        ev, h = self._check_async(dg, self.intake_stream)
+        self.checks[q.rid] = (ev, h, ev_a)
 
     def intake_done(self, q):
         c = self.checks.get(q.rid)
@@ -445,6 +453,8 @@ class Device:
         c = self.checks.pop(q.rid, None)
         if c is None:
             return None
+        self.intervals.append((self.ref.elapsed_time(c[2]) * 1e-3,
+                               self.ref.elapsed_time(c[0]) * 1e-3, "intake"))
         bad = (int(c[1][0]), int(c[1][1]))
         if bad[0] != -1:
             self.graphs.pop(q.rid, None)
@@ -497,7 +507,7 @@ class Device:
         torch = self.torch
         ev0, ev1, _ = w.events
         self.intervals.append((self.ref.elapsed_time(ev0) * 1e-3,
-                               self.ref.elapsed_time(ev1) * 1e-3))
+                               self.ref.elapsed_time(ev1) * 1e-3, "kernels"))
         s = self.streams[w.lane]
         w.status = self.ctxs[w.lane].status(s)
         total = int(w.counts[-1])
@@ -508,19 +518,25 @@ class Device:
             ev2.record(s)
             self.batches[w.lane].pack(w.d_counts, dst, s)
             ev3.record(s)
+            # the wave's own pinned buffer (torch's pinned-memory cache): the
+            # requests' results are views of it, no copy on the host
             w.packed = torch.empty(max(total, 16), dtype=torch.uint8, pin_memory=True)
             w.packed.copy_(dst, non_blocking=True)
+            ev4 = torch.cuda.Event(enable_timing=True)
+            ev4.record(s)
             w.ev_down = torch.cuda.Event()
             w.ev_down.record(s)
         w.dst = dst
-        w.pack_events = (ev2, ev3)
+        w.pack_events = (ev2, ev3, ev4)
 
     def download_done(self, w):
         if not w.ev_down.query():
             return False
-        ev2, ev3 = w.pack_events
+        ev2, ev3, ev4 = w.pack_events
         self.intervals.append((self.ref.elapsed_time(ev2) * 1e-3,
-                               self.ref.elapsed_time(ev3) * 1e-3))
+                               self.ref.elapsed_time(ev3) * 1e-3, "kernels"))
+        self.intervals.append((self.ref.elapsed_time(ev3) * 1e-3,
+                               self.ref.elapsed_time(ev4) * 1e-3, "copy"))
         return True
 
     def finish(self, w):
@@ -528,7 +544,7 @@ class Device:
         rows = w.counts.numpy()[:-1].reshape(-1, 4)
         out = {}
         for q, row in zip(w.reqs, rows):
-            res = {k: v.copy() for k, v in cg.unpack_results(packed, row).items()}
+            res = cg.unpack_results(packed, row)
             res["status"] = w.status
             out[q.rid] = res
             self.graphs.pop(q.rid, None)

@@ -103,6 +103,9 @@ def test_batch_bytes_from_sizes():
 def test_busy_fraction_and_arrivals():
     assert serve.busy_fraction([(0, 1), (0.5, 2), (3, 4)], 5.0) == pytest.approx(3.0 / 5.0)
     assert serve.busy_fraction([], 5.0) == 0.0
+    iv = [(0, 1, "kernels"), (0.5, 2, "copy"), (3, 3.5, "kernels")]
+    assert serve.busy_fraction(iv, 4.0) == pytest.approx(2.5 / 4.0)
+    assert serve.busy_fraction(iv, 4.0, ("kernels",)) == pytest.approx(1.5 / 4.0)
     a = serve.poisson_arrivals(2000, 100.0, seed=3)
     assert np.all(np.diff(a) > 0)
     assert np.array_equal(a, serve.poisson_arrivals(2000, 100.0, seed=3))
