@@ -37,7 +37,7 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
     return here;
   };
   L.scan_status = take(sizeof(unsigned long long) * (size_t)(scan_blocks(nn + 1) + 1));
-  L.tmp = take(4 * (size_t)nn);
+  L.tmp = take(8 * (size_t)nn);
   L.lidx = take(4 * (size_t)nn);
   L.fill = take(4 * (size_t)nn);
   L.piece_off = take(8 * (size_t)nn);

@@ -621,14 +621,11 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
 constexpr int kIndBlock = 256;
 constexpr int kIndLocalCap = 1024;
 
-// one-wave form for the small components of the batched path
-constexpr int kIndSmallBlock = 64;
-constexpr int kIndSmallCap = 256;
-
 // lidx (the local number of each read) is written for every component when
 // lidx_always, else only for components above CAP reads (the ones whose
-// neighbours are then numbered through it instead of the sorted block)
-template <int BLOCK, int CAP>
+// neighbours are then numbered through it instead of the sorted block).
+// Member i's id is members[MS * i].
+template <int BLOCK, int CAP, int MS = 1>
 __device__ __forceinline__ void sort_component_block(int q, int st,
                                                      const int32_t *__restrict__ members,
                                                      int32_t *__restrict__ perm,
@@ -637,7 +634,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
   if (q <= CAP) {
     int N2 = 1;
     while (N2 < q) N2 <<= 1;
-    for (int i = threadIdx.x; i < N2; i += BLOCK) a[i] = i < q ? members[i] : 0x7FFFFFFF;
+    for (int i = threadIdx.x; i < N2; i += BLOCK) a[i] = i < q ? members[MS * i] : 0x7FFFFFFF;
     __syncthreads();
     for (int k = 2; k <= N2; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
@@ -663,9 +660,9 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
     // large component: the rank of a read is the number of smaller ids in
     // its block (ids are distinct)
     for (int i = threadIdx.x; i < q; i += BLOCK) {
-      const int32_t x = members[i];
+      const int32_t x = members[MS * i];
       int r = 0;
-      for (int t = 0; t < q; ++t) r += members[t] < x;
+      for (int t = 0; t < q; ++t) r += members[MS * t] < x;
       perm[st + r] = x;
       lidx[x] = st + r;
     }
@@ -679,7 +676,7 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
 // entry index kept)
 // starting at entry estart.  Neighbours of a kept entry lie in the same
 // component, so their local numbers come from the sorted block itself.
-template <int BLOCK, int CAP>
+template <int BLOCK, int CAP, int MS = 1>
 __device__ __forceinline__ void induce_component(
     int q, int st, int estart, const int32_t *__restrict__ members,
     const uint8_t *__restrict__ flags,
@@ -687,7 +684,7 @@ __device__ __forceinline__ void induce_component(
     int32_t *__restrict__ perm, int32_t *__restrict__ lidx, int32_t *__restrict__ loc_row_ptr,
     int32_t *__restrict__ loc_col, int32_t *__restrict__ loc_eid, int32_t *a,
     int32_t *sh_scan) {
-  sort_component_block<BLOCK, CAP>(q, st, members, perm, lidx, a, false);  // ends with a barrier
+  sort_component_block<BLOCK, CAP, MS>(q, st, members, perm, lidx, a, false);  // ends with a barrier
   const bool in_lds = q <= CAP;
   int carry = 0;
   for (int base = 0; base < q; base += BLOCK) {
@@ -758,16 +755,24 @@ __device__ __forceinline__ void walk_component(
     int c, int q, int st, WalkArrays w, const cg_graph &g, const cg_parts &parts,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ loc_row_ptr,
     const int32_t *__restrict__ loc_col, const int32_t *__restrict__ loc_eid,
+    const cg_contigs &out, const Scratch &s, int32_t *sh_small, uint32_t *sh_scan);
+
+// Steps 2-5 of the walk, from the component's rows in w (nb, eid; and in the
+// LDS form vid, rlen, es, eo, ep).
+template <int BLOCK, int CAP, bool kLds>
+__device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, const cg_graph &g,
+                                           const cg_parts &parts,
+                                           const int32_t *__restrict__ perm,
+                                           const cg_contigs &out, const Scratch &s,
+                                           uint32_t *sh_scan);
+
+template <int BLOCK, int CAP, bool kLds>
+__device__ __forceinline__ void walk_component(
+    int c, int q, int st, WalkArrays w, const cg_graph &g, const cg_parts &parts,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ loc_row_ptr,
+    const int32_t *__restrict__ loc_col, const int32_t *__restrict__ loc_eid,
     const cg_contigs &out, const Scratch &s, int32_t *sh_small, uint32_t *sh_scan) {
   const int tid = threadIdx.x;
-  __shared__ int s_start, s_cyc, s_sej;
-  __shared__ uint64_t s_carry;
-  if (tid == 0) {
-    s_start = 0x7FFFFFFF;
-    s_cyc = 0;
-    s_sej = 0;
-    s_carry = 0;
-  }
   // 1. local rows of the component's block
   if constexpr (kLds) {
     // and, in three rounds of loads issued together, the read ids and
@@ -854,12 +859,39 @@ __device__ __forceinline__ void walk_component(
     }
   }
   __syncthreads();
+  walk_chain<BLOCK, CAP, kLds>(c, q, st, w, g, parts, perm, out, s, sh_scan);
+  (void)sh_small;
+}
+
+template <int BLOCK, int CAP, bool kLds>
+__device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, const cg_graph &g,
+                                           const cg_parts &parts,
+                                           const int32_t *__restrict__ perm,
+                                           const cg_contigs &out, const Scratch &s,
+                                           uint32_t *sh_scan) {
+  const int tid = threadIdx.x;
+  // the LDS form orders LDS only at its barriers (its global stores stay in
+  // flight; nothing it reads back from global memory was written here); the
+  // global form's arrays are global memory
+  auto wbar = [] {
+    if constexpr (kLds) lds_barrier();
+    else __syncthreads();
+  };
+  __shared__ int s_start, s_cyc, s_sej;
+  __shared__ uint64_t s_carry;
+  if (tid == 0) {
+    s_start = 0x7FFFFFFF;
+    s_cyc = 0;
+    s_sej = 0;
+    s_carry = 0;
+  }
+  wbar();
   // 2. start: the first read of local degree 1 (the smaller-id root, since
   // the block is in id order); a cycle starts at its first read and loses
   // the edge to the larger-numbered neighbour of it
   for (int i = tid; i < q; i += BLOCK)
     if ((w.nb[2 * i] >= 0) != (w.nb[2 * i + 1] >= 0)) atomicMin(&s_start, i);
-  __syncthreads();
+  wbar();
   if (tid == 0) {
     if (s_start == 0x7FFFFFFF) {
       s_start = 0;
@@ -872,7 +904,7 @@ __device__ __forceinline__ void walk_component(
       }
     }
   }
-  __syncthreads();
+  wbar();
   const int s0 = s_start;
   // 3. rays (i, k): leave read i through slot k.  A ray jumps along the
   // chain; after ceil(log2 q) doublings it knows the chain end it reaches and
@@ -892,7 +924,7 @@ __device__ __forceinline__ void walk_component(
       w.endv[r] = y;
     }
   }
-  __syncthreads();
+  wbar();
   for (int span = 1; span < q; span <<= 1) {
     if (kLds) {
       int rn[(2 * CAP / BLOCK)], rd[(2 * CAP / BLOCK)], re[(2 * CAP / BLOCK)];
@@ -909,7 +941,7 @@ __device__ __forceinline__ void walk_component(
           }
         }
       }
-      __syncthreads();
+      wbar();
 #pragma unroll
       for (int u = 0; u < (2 * CAP / BLOCK); ++u) {
         const int r = tid + u * BLOCK;
@@ -919,7 +951,7 @@ __device__ __forceinline__ void walk_component(
           w.endv[r] = re[u];
         }
       }
-      __syncthreads();
+      wbar();
     } else {
       // large component (global arrays): ray r's successor x is only
       // rewritten by its own owner, so read all then write all in two passes
@@ -935,7 +967,7 @@ __device__ __forceinline__ void walk_component(
           w.nxt[2 * q + r] = -2;
         }
       }
-      __syncthreads();
+      wbar();
       for (int r = tid; r < 2 * q; r += BLOCK) {
         const int x = w.nxt[2 * q + r];
         if (x != -2) {
@@ -944,7 +976,7 @@ __device__ __forceinline__ void walk_component(
           w.endv[r] = w.endv[2 * q + r];
         }
       }
-      __syncthreads();
+      wbar();
     }
   }
   // 4. rank, predecessor, successor, orientation and piece of every read
@@ -1004,34 +1036,34 @@ __device__ __forceinline__ void walk_component(
     R_vid[rank] = v;
     R_rev[rank] = (uint8_t)orient;
     R_len[rank] = plen;
+    if constexpr (kLds) w.nxt[rank] = (int32_t)plen;  // nxt is free after the rays
     R_skip[rank] = skip;
     s.lay_contig[st + rank] = rank_c;
     (void)succ;
   }
-  __syncthreads();
+  wbar();
   // 5. piece offsets in walk order
   for (int base = 0; base < q; base += BLOCK) {
     const int i = base + tid;
-    const uint32_t x = i < q ? R_len[i] : 0u;
+    const uint32_t x = i < q ? (kLds ? (uint32_t)w.nxt[i] : R_len[i]) : 0u;
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<uint32_t, BLOCK>(x, sh_scan, &tot);
+    const uint32_t ex = block_excl_scan<uint32_t, BLOCK, kLds>(x, sh_scan, &tot);
     if (i < q) s.piece_off[st + i] = s_carry + ex;
-    __syncthreads();
+    wbar();
     if (tid == 0) s_carry += tot;
-    __syncthreads();
+    wbar();
   }
   if (tid == 0) {
     out.label[rank_c] = parts.comp_label[c];
     out.bin[rank_c] = parts.comp_bin[c];
-    out.start[rank_c] = perm[st + s0];
+    out.start[rank_c] = kLds ? w.vid[s0] : perm[st + s0];
     out.n_reads[rank_c] = q;
     out.len[rank_c] = s_carry;
     out.cflags[rank_c] = (q == 1 ? CG_CONTIG_SINGLE : 0u) | (s_cyc ? CG_CONTIG_CIRCULAR : 0u) |
                          (s_sej ? CG_CONTIG_SAME_END_JOIN : 0u);
     out.layout_off[rank_c] = st;
   }
-  (void)sh_small;
-  __syncthreads();
+  wbar();
 }
 
 // ---------------------------------------------------------------------------

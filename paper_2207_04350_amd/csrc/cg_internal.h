@@ -36,7 +36,8 @@ constexpr int kScanBlock = 1024;
 
 struct Scratch {
   unsigned long long *scan_status;  // [scan_blocks]
-  int32_t *tmp;        // [n] induce: reads bucketed by component
+  int32_t *tmp;        // [2n] induce: reads bucketed by component (the batched form:
+                       // (id, tile-list slot) pairs)
   int32_t *lidx;       // [n] induce: local number of each read
   uint32_t *fill;      // [n] induce: bucket cursors
   uint64_t *piece_off; // [n] assemble: base offset of each piece in its contig
@@ -130,25 +131,46 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+// A workgroup barrier that orders LDS accesses only: global loads and
+// stores stay in flight across it (a full barrier also waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block-wide exclusive scan; returns the exclusive prefix, *total the block
 // sum.  `sh` needs BLOCK/64 + 1 entries of T.  All threads must call it.
-template <typename T, int BLOCK>
+// kLdsOnly: its barriers order LDS only (the caller's global accesses stay
+// in flight); a one-wave block needs neither LDS nor barriers.
+template <typename T, int BLOCK, bool kLdsOnly = false>
 __device__ __forceinline__ T block_excl_scan(T x, T *sh, T *total) {
   constexpr int NW = BLOCK / kWave;
   const int w = threadIdx.x / kWave, l = lane_id();
   T inc = wave_incl_scan(x);
+  if constexpr (kLdsOnly && BLOCK == kWave) {
+    *total = __shfl(inc, kWave - 1);
+    (void)sh;
+    (void)w;
+    (void)l;
+    return inc - x;
+  }
+  auto bar = [] {
+    if constexpr (kLdsOnly) lds_barrier();
+    else __syncthreads();
+  };
   if (l == kWave - 1) sh[w] = inc;
-  __syncthreads();
+  bar();
   if (w == 0) {
     T v = l < NW ? sh[l] : T(0);
     T vi = wave_incl_scan(v);
     if (l < NW) sh[l] = vi - v;
     if (l == NW - 1) sh[NW] = vi;
   }
-  __syncthreads();
+  bar();
   T r = sh[w] + inc - x;
   *total = sh[NW];
-  __syncthreads();
+  bar();
   return r;
 }
 

@@ -73,7 +73,7 @@ struct BatchDev {
   int32_t *wq_hist;                 // [kWqBuckets] components per read count (capped)
   int32_t *wq_cur;                  // [kWqBuckets] placement cursors
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
-                                    // reads, 2: above kIndSmallCap
+                                    // reads, 2: above kWalkCap, 3: above kWalkTinyCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
   int32_t *chunk_job;               // [sum of ceil(n / kChunkPieces)] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket
@@ -107,12 +107,13 @@ struct MaskTile {
   const int32_t *row_ptr;
   const int32_t *col;
   int4 *list;        // the job's listed reads: tile t's at list[t * kMaskTile], as
-                     // (id, first column, second column or -1, degree)
+                     // (id, first column, second column or -1, first entry)
   uint32_t *bits;    // the job's bitmaps: W listed words, then W branch words
   int2 *tile_cnt;    // (listed reads, branch reads) of this tile
   int32_t n, v0, W, pad_;
 };
 static_assert(sizeof(MaskTile) % 8 == 0, "tile descriptors are copied in 8-byte words");
+
 constexpr int kMaskThreads = 256;
 constexpr int kMaskGroups = 2;  // groups of 4 consecutive reads per thread
 constexpr int kMaskTile = 4 * kMaskThreads * kMaskGroups;
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_tiles(const MaskTile *__
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 4 * g + i;
-      if (dg[k] == 1 || dg[k] == 2) list[pos[g]++] = i32x4{v0[g] + i, u0[k], u1[k], dg[k]};
+      if (dg[k] == 1 || dg[k] == 2) list[pos[g]++] = i32x4{v0[g] + i, u0[k], u1[k], rs[k]};
     }
   if (threadIdx.x == 0) {
     CG_GLOBAL int32_t *tc = (CG_GLOBAL int32_t *)D.tile_cnt;
@@ -269,13 +270,6 @@ constexpr int kMcPer = kMcListCap / kMcBlock;    // listed reads per thread at m
 constexpr int64_t kExternalEntries = 2 * (int64_t)kMcListCap;
 constexpr int32_t kNotEligible = -(1 << 30);
 constexpr uint32_t kIdMask = (1u << 30) - 1;     // low bits of a listed read's entry: its id
-
-// a barrier that orders LDS accesses only (global stores stay in flight)
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 __device__ __forceinline__ uint8_t kind_of(uint32_t c4) {
   return (c4 >> 2) == 1 ? CG_KIND_SINGLE : ((c4 & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
@@ -378,6 +372,22 @@ __device__ __forceinline__ McOut mc_out(const BJob &J) {
                (CG_GLOBAL int32_t *)J.parts.comp_size, (CG_GLOBAL uint8_t *)J.parts.comp_kind,
                (CG_GLOBAL int32_t *)J.s.memb,          (CG_GLOBAL uint64_t *)J.s.comp_w,
                (CG_GLOBAL int32_t *)J.s.tmp};
+}
+
+// Member slot `at` of a component: the read's id and where the tile list
+// holds it (its slot | kept bits << 30), or kNoSlot where the list does not
+// (a read without kept entries, or a job whose listed reads' state is in
+// scratch, which reuses the list's memory).  One 8-byte store.
+constexpr int32_t kNoSlot = (1 << 30) - 1;
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void mc_member(const McOut &O, int32_t at, int32_t v, int32_t rec) {
+  *(CG_GLOBAL i32x2 *)(O.tmp + 2 * (int64_t)at) = i32x2{v, rec};
+}
+
+// the tile-list slot of listed read v of local number l
+__device__ __forceinline__ int32_t mc_list_slot(int32_t v, int32_t l, const int32_t *wp) {
+  const int32_t t = v / kMaskTile;
+  return t * kMaskTile + (l - wp[t * (kMaskTile / 32)]);
 }
 
 // component record cb: label, size, kind, first member slot; bases weight 0
@@ -534,7 +544,7 @@ __device__ __forceinline__ int32_t mc_sweep_table(int32_t n, int32_t min_reads, 
         S.par[r[i].loc] = ~cb;
         S.cnt[r[i].loc] = mb;  // member cursor, the root's own slot included
       } else {
-        O.tmp[mb] = v;  // a one-read component is its own member
+        mc_member(O, mb, v, kNoSlot);  // a one-read component is its own member
       }
       ++cb;
       mb += (int32_t)(r[i].c4 >> 2);
@@ -550,7 +560,10 @@ __device__ __forceinline__ int32_t mc_sweep_table(int32_t n, int32_t min_reads, 
       int32_t at;
       if constexpr (kLds) at = atomicAdd(S.cnt + r[i].root, 1);
       else at = mc_add(S.cnt + r[i].root, 1);
-      if (at >= 0) O.tmp[at] = v4 + i;
+      if (at >= 0)
+        mc_member(O, at, v4 + i,
+                  kLds ? mc_list_slot(v4 + i, r[i].loc, wp) | (int32_t)((r[i].fl >> 1) << 30)
+                       : kNoSlot);
     }
     if (v4 < n) mc_store4(O, v4, n, r);
   }
@@ -790,7 +803,7 @@ __device__ __forceinline__ int32_t mc_components(
           A.b[lr] = ~cb;
           A.a[lr] = mb;  // member cursor, the root's own slot included
         } else {
-          O.tmp[mb] = v;  // a one-read component is its own member
+          mc_member(O, mb, v, kNoSlot);  // a one-read component is its own member
         }
         mc_component(O, cb, v, c4, mb);
         O.label_comp[v] = cb;
@@ -812,7 +825,7 @@ __device__ __forceinline__ int32_t mc_components(
     const int32_t rt = A.b[l];
     const int32_t r = rt < 0 ? l : rt;
     const int32_t at = mc_add(A.a + r, 1);
-    if (at >= 0) O.tmp[at] = v;
+    if (at >= 0) mc_member(O, at, v, kNoSlot);
     O.flags[v] = (uint8_t)(kept << 1);
     if (rt < 0) O.label_comp[v] = ~rt;
     else if (rt != l) O.label[v] = (int32_t)(A.lid[rt] & kIdMask);
@@ -839,11 +852,11 @@ __device__ __forceinline__ int32_t mc_listed(const BJob &J, const McOut &O, int3
   // reads hold local numbers from the prefix of its first word on), then
   // kept bits and the other ends' local numbers from the bitmaps
   int32_t id[PER], c0[PER], c1[PER];
+  int32_t slot[PER];
   {
     constexpr int kTileWords = kMaskTile / 32;
     const int32_t nt = J.mt_count;
     const CG_GLOBAL i32x4 *list = (const CG_GLOBAL i32x4 *)J.s.walk;
-    int32_t slot[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int32_t l = ls[k] >= 0 ? ls[k] : 0;
@@ -966,7 +979,7 @@ __device__ __forceinline__ int32_t mc_listed(const BJob &J, const McOut &O, int3
   for (int k = 0; k < PER; ++k) {
     if (!kept[k]) continue;
     const int32_t at = atomicAdd(s_a + r[k], 1);
-    if (at >= 0) O.tmp[at] = id[k];
+    if (at >= 0) mc_member(O, at, id[k], slot[k] | (int32_t)(kept[k] << 30));
   }
   return (int32_t)(tot >> 32);
 }
@@ -1215,12 +1228,13 @@ __global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
 
 // 4c. the work queue: every component of the batch in decreasing read count
 // (within a bucket in any order), as (job, component, reads, first local
-// number), and the queue heads of the four per-component passes.  Handing
-// the largest components out first to whichever workgroup is free is LPT
-// list scheduling of the whole batch's components onto the workgroups.
-// Components of at most kWalkSmallCap (kIndSmallCap) reads form the queue's
-// tail, which the one-wave passes take.
+// number), and the queue heads of the per-component passes.  Handing the
+// largest components out first to whichever workgroup is free is LPT list
+// scheduling of the whole batch's components onto the workgroups.
+// Components above kWalkCap reads form the queue's head (two passes, arrays
+// in scratch), those of at most kWalkSmallCap its tail (one wave each).
 constexpr int kWqBlock = 256;
+constexpr int kWalkTinyCap = 32;  // reads of the components the tiny pass takes
 constexpr int kWqPer = kWqBuckets / kWqBlock;
 
 __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
@@ -1246,7 +1260,8 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.wq_meta[0] = tot;
     B.wq_meta[1] = s_start[kWalkSmallCap];  // components above kWalkSmallCap reads
-    B.wq_meta[2] = s_start[kIndSmallCap];   // above kIndSmallCap
+    B.wq_meta[2] = s_start[kWalkCap];       // above kWalkCap
+    B.wq_meta[3] = s_start[kWalkTinyCap];   // above kWalkTinyCap
   }
   // this workgroup's components: a contiguous range; counted per bucket in
   // LDS, one reservation per bucket in the queue, placed by LDS cursors
@@ -1316,22 +1331,273 @@ __device__ __forceinline__ void induce_listed(const BatchDev &B, int4 d, int32_t
   const int j = __builtin_amdgcn_readfirstlane(d.x), c = __builtin_amdgcn_readfirstlane(d.y);
   const int q = __builtin_amdgcn_readfirstlane(d.z), st = __builtin_amdgcn_readfirstlane(d.w);
   const BJob J = job_at(B.jobs, j);
-  const int32_t *members = J.s.tmp + J.s.memb[c];
-  induce_component<BLOCK, CAP>(q, st, J.s.estart[c], members, J.flags, J.g.row_ptr, J.g.col,
+  // member records are (id, list slot) pairs
+  const int32_t *members = J.s.tmp + 2 * (int64_t)J.s.memb[c];
+  induce_component<BLOCK, CAP, 2>(q, st, J.s.estart[c], members, J.flags, J.g.row_ptr, J.g.col,
                                J.local.perm, J.s.lidx, J.local.loc_row_ptr, J.local.loc_col,
                                J.local.loc_eid, a, sh_scan);
 }
 
-// 6a. components of at most kIndSmallCap reads (the queue's tail): one wave each
-__global__ __launch_bounds__(kIndSmallBlock) void kb_induce_small(BatchDev B) {
-  __shared__ int32_t a[kIndSmallCap];
-  __shared__ int32_t sh_scan[kIndSmallBlock / kWave + 1];
-  const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 0);
-  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r)
-    induce_listed<kIndSmallBlock, kIndSmallCap>(B, wq_at(B, x), a, sh_scan);
+// 6-7. InducedSubgraph and LocalAssembly of one component of at most CAP
+// reads in one pass.  Each member's id, kept entries and neighbours come
+// from its member record and the tile list, which gathered them in id
+// order (a record without a list slot takes them from the graph), then its
+// read length and its entries' strand bits and overlaps (or coordinates)
+// from the graph.  The local numbers follow
+// the ids; every field goes into the walk's LDS arrays at its local number
+// while perm and the local CSR rows are written out, so the walk reads
+// nothing back.
+__device__ __forceinline__ int32_t lds_lower_bound(const int32_t *a, int q, int32_t x) {
+  int lo = 0, hi = q;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
 
-// 6b. the larger components (the queue's head, largest first)
+template <int BLOCK, int CAP>
+__device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st, WalkArrays w,
+                                             uint32_t *sh_scan) {
+  constexpr int R = CAP >= BLOCK ? CAP / BLOCK : 1;  // members per thread
+  const int tid = threadIdx.x;
+  const CG_GLOBAL i32x2 *mem = (const CG_GLOBAL i32x2 *)(J.s.tmp + 2 * (int64_t)J.s.memb[c]);
+  const CG_GLOBAL i32x4 *la = (const CG_GLOBAL i32x4 *)J.s.walk;
+  const CG_GLOBAL uint32_t *glen = (const CG_GLOBAL uint32_t *)J.g.read_len;
+  const CG_GLOBAL uint8_t *gstr = (const CG_GLOBAL uint8_t *)J.g.strand;
+  const CG_GLOBAL uint32_t *gov = (const CG_GLOBAL uint32_t *)(J.g.pre ? J.g.pre : J.g.ovl);
+  const CG_GLOBAL uint32_t *gpost = (const CG_GLOBAL uint32_t *)J.g.post;
+  const bool coords = J.g.post != nullptr;
+  // 1. member records, then their list entries A = (id, first column,
+  // second column, first entry) and kept bits kb; a record without a list
+  // slot takes them from the graph (flags give the kept entries)
+  int32_t v[R], rec[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = tid + u * BLOCK;
+    v[u] = 0x7FFFFFFF;
+    rec[u] = kNoSlot;
+    if (i < q) {
+      const i32x2 m = mem[i];
+      v[u] = m.x;
+      rec[u] = m.y;
+    }
+  }
+  i32x4 A[R];
+  uint32_t kb[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    A[u] = i32x4{v[u], -1, -1, 0};
+    kb[u] = (uint32_t)rec[u] >> 30;
+    if (rec[u] != kNoSlot) A[u] = la[rec[u] & kNoSlot];
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = tid + u * BLOCK;
+    if (i < q && rec[u] == kNoSlot) {
+      const int32_t x = v[u];
+      kb[u] = ((uint32_t)J.flags[x] >> 1) & 3u;
+      const int32_t b = J.g.row_ptr[x];
+      A[u].w = b;
+      if (kb[u] & 1u) A[u].y = J.g.col[b];
+      if (kb[u] & 2u) A[u].z = J.g.col[b + 1];
+    }
+  }
+  // then the read lengths and the kept entries' strand bits, overlaps (or
+  // pre) and post: Bq = (length, ov of entry 0, ov of entry 1, strands), Cq =
+  // post of both
+  i32x4 Bq[R];
+  i32x2 Cq[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    Bq[u] = i32x4{0, 0, 0, 0};
+    Cq[u] = i32x2{0, 0};
+    if (tid + u * BLOCK >= q) continue;
+    const int32_t b = A[u].w;
+    Bq[u].x = (int32_t)glen[v[u]];
+    if (kb[u] & 1u) {
+      Bq[u].y = (int32_t)gov[b];
+      Bq[u].w = gstr[b];
+      if (coords) Cq[u].x = (int32_t)gpost[b];
+    }
+    if (kb[u] & 2u) {
+      Bq[u].z = (int32_t)gov[b + 1];
+      Bq[u].w |= (int32_t)gstr[b + 1] << 8;
+      if (coords) Cq[u].y = (int32_t)gpost[b + 1];
+    }
+  }
+  // 2. local numbers: the ids in order in a (the walk's nxt array, unused
+  // until its rays), each member's rank among them
+  int32_t *a = w.nxt;
+  int32_t rk[R];
+  if constexpr (BLOCK == kWave) {
+    // one wave: a rank is the number of smaller ids, counted over the lanes
+#pragma unroll
+    for (int u = 0; u < R; ++u) rk[u] = 0;
+#pragma unroll
+    for (int u2 = 0; u2 < R; ++u2) {
+      const int cnt = q - u2 * kWave < kWave ? q - u2 * kWave : kWave;
+      for (int l2 = 0; l2 < cnt; ++l2) {
+        const int32_t x = __builtin_amdgcn_readlane(v[u2], l2);
+#pragma unroll
+        for (int u = 0; u < R; ++u) rk[u] += x < v[u] ? 1 : 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+      if (tid + u * BLOCK < q) a[rk[u]] = v[u];
+    lds_barrier();
+  } else {
+    int N2 = 1;
+    while (N2 < q) N2 <<= 1;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = tid + u * BLOCK;
+      if (i < N2) a[i] = i < q ? v[u] : 0x7FFFFFFF;
+    }
+    lds_barrier();
+    for (int k = 2; k <= N2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < N2; i += BLOCK) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const int32_t x = a[i], y = a[ixj];
+            if ((x > y) == ((i & k) == 0)) {
+              a[i] = y;
+              a[ixj] = x;
+            }
+          }
+        }
+        lds_barrier();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) rk[u] = tid + u * BLOCK < q ? lds_lower_bound(a, q, v[u]) : 0;
+  }
+  // 3. every member's fields at its local number: its kept entries in row
+  // order (slot 0, then slot 1), neighbours as local numbers
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (tid + u * BLOCK >= q) continue;
+    const int r = rk[u];
+    // slot 0: the first kept entry (entry 0, else entry 1); slot 1: entry 1
+    // when both are kept (selects, no indexed arrays)
+    const bool k0 = kb[u] & 1u, k1 = (kb[u] & 2u) != 0u;
+    const bool s0 = k0 || k1, s1 = k0 && k1;
+    const uint32_t sw = (uint32_t)Bq[u].w;
+    const int32_t e0 = k0 ? A[u].w : A[u].w + 1, n0 = k0 ? A[u].y : A[u].z;
+    const uint32_t es0 = k0 ? (sw & 0xFFu) : ((sw >> 8) & 0xFFu);
+    const uint32_t eo0 = (uint32_t)(k0 ? Bq[u].y : Bq[u].z);
+    const uint32_t ep0 = (uint32_t)(k0 ? Cq[u].x : Cq[u].y);
+    w.nb[2 * r] = s0 ? lds_lower_bound(a, q, n0) : -1;
+    w.eid[2 * r] = s0 ? e0 : -1;
+    w.es[2 * r] = (uint8_t)(s0 ? es0 : 0u);
+    w.eo[2 * r] = s0 ? eo0 : 0u;
+    w.ep[2 * r] = s0 ? ep0 : 0u;
+    w.nb[2 * r + 1] = s1 ? lds_lower_bound(a, q, A[u].z) : -1;
+    w.eid[2 * r + 1] = s1 ? A[u].w + 1 : -1;
+    w.es[2 * r + 1] = (uint8_t)(s1 ? (sw >> 8) & 0xFFu : 0u);
+    w.eo[2 * r + 1] = s1 ? (uint32_t)Bq[u].z : 0u;
+    w.ep[2 * r + 1] = s1 ? (uint32_t)Cq[u].y : 0u;
+    w.vid[r] = v[u];
+    w.rlen[r] = (uint32_t)Bq[u].x;
+  }
+  lds_barrier();
+  // 4. perm and the local CSR rows, in local order
+  CG_GLOBAL int32_t *perm = (CG_GLOBAL int32_t *)J.local.perm;
+  CG_GLOBAL int32_t *lrp = (CG_GLOBAL int32_t *)J.local.loc_row_ptr;
+  CG_GLOBAL int32_t *lcol = (CG_GLOBAL int32_t *)J.local.loc_col;
+  CG_GLOBAL int32_t *leid = (CG_GLOBAL int32_t *)J.local.loc_eid;
+  const int32_t estart = J.s.estart[c];
+  int32_t carry = 0;
+  for (int base = 0; base < q; base += BLOCK) {
+    const int i = base + tid;
+    int32_t n0 = -1, n1 = -1;
+    if (i < q) {
+      n0 = w.nb[2 * i];
+      n1 = w.nb[2 * i + 1];
+    }
+    const int32_t deg = (n0 >= 0 ? 1 : 0) + (n1 >= 0 ? 1 : 0);
+    int32_t tot;
+    const int32_t ex = block_excl_scan<int32_t, BLOCK, true>(deg, (int32_t *)sh_scan, &tot);
+    if (i < q) {
+      const int32_t r0 = estart + carry + ex;
+      perm[st + i] = a[i];
+      lrp[st + i] = r0;
+      if (n0 >= 0) {
+        lcol[r0] = st + n0;
+        leid[r0] = w.eid[2 * i];
+      }
+      if (n1 >= 0) {
+        lcol[r0 + 1] = st + n1;
+        leid[r0 + 1] = w.eid[2 * i + 1];
+      }
+    }
+    carry += tot;
+  }
+  walk_chain<BLOCK, CAP, true>(c, q, st, w, J.g, J.parts, J.local.perm, J.out, J.s, sh_scan);
+}
+
+// 6a. components of at most kWalkTinyCap reads (the queue's tail): one wave
+// each, both steps in one pass, with small LDS arrays so that many waves run
+// at once
+__global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_tiny(BatchDev B) {
+  __shared__ int32_t s_nb[2 * kWalkTinyCap], s_eid[2 * kWalkTinyCap], s_nxt[2 * kWalkTinyCap],
+      s_dist[2 * kWalkTinyCap], s_endv[2 * kWalkTinyCap], s_vid[kWalkTinyCap];
+  __shared__ uint32_t s_rlen[kWalkTinyCap], s_eo[2 * kWalkTinyCap], s_ep[2 * kWalkTinyCap];
+  __shared__ uint8_t s_es[2 * kWalkTinyCap];
+  __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
+  const int32_t lo = ld_const(B.wq_meta, 3), hi = ld_const(B.wq_meta, 0);
+  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
+    const int4 d = wq_at(B, x);
+    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
+    const int st = __builtin_amdgcn_readfirstlane(d.w);
+    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    iw_component<kWalkSmallBlock, kWalkTinyCap>(J, c, q, st, w, sh_scan);
+  }
+}
+
+// 6b. components of kWalkTinyCap + 1 .. kWalkSmallCap reads: one wave each
+__global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev B) {
+  __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
+      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
+  __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
+  __shared__ uint8_t s_es[2 * kWalkSmallCap];
+  __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
+  const int32_t lo = ld_const(B.wq_meta, 1), hi = ld_const(B.wq_meta, 3);
+  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
+    const int4 d = wq_at(B, x);
+    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
+    const int st = __builtin_amdgcn_readfirstlane(d.w);
+    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    iw_component<kWalkSmallBlock, kWalkSmallCap>(J, c, q, st, w, sh_scan);
+  }
+}
+
+// 6c. components of kWalkSmallCap + 1 .. kWalkCap reads: one workgroup each,
+// both steps in one pass
+__global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
+  __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
+      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
+  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
+  __shared__ uint8_t s_es[2 * kWalkCap];
+  __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
+  const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 1);
+  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
+    const int4 d = wq_at(B, x);
+    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
+    const int st = __builtin_amdgcn_readfirstlane(d.w);
+    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    iw_component<kWalkBlock, kWalkCap>(J, c, q, st, w, sh_scan);
+  }
+}
+
+// 6d. components above kWalkCap reads (the queue's head, largest first):
+// induced subgraph with the block sort in scratch
 __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
   __shared__ int32_t a[kIndLocalCap];
   __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
@@ -1340,52 +1606,22 @@ __global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
     induce_listed<kIndBlock, kIndLocalCap>(B, wq_at(B, x), a, sh_scan);
 }
 
-// 7. walk every component
-// 7a. components of at most kWalkSmallCap reads (the queue's tail): one wave each
-__global__ __launch_bounds__(kWalkSmallBlock) void kb_walk_small(BatchDev B) {
-  __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
-      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
-  __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
-  __shared__ uint8_t s_es[2 * kWalkSmallCap];
-  __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
-  const int32_t lo = ld_const(B.wq_meta, 1), hi = ld_const(B.wq_meta, 0);
-  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
-    const int4 d = wq_at(B, x);
-    const BJob J = job_at(B.jobs, d.x);
-    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
-    walk_component<kWalkSmallBlock, kWalkSmallCap, true>(
-        d.y, d.z, d.w, w, J.g, J.parts, J.local.perm, J.local.loc_row_ptr, J.local.loc_col,
-        J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-  }
-}
-
-// 7b. the larger components (the queue's head, largest first)
+// 7. their walks, with the walk's arrays in scratch
 __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
-  __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
-      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
-  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
-  __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
-  const int32_t hi = ld_const(B.wq_meta, 1);
+  const int32_t hi = ld_const(B.wq_meta, 2);
   for (int32_t r = 0, x; (x = wq_entry(0, hi, r)) >= 0; ++r) {
     const int4 d = wq_at(B, x);
     const int c = d.y, q = d.z, st = d.w;
     const BJob J = job_at(B.jobs, d.x);
-    if (q <= kWalkCap) {
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
-      walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, J.g, J.parts, J.local.perm,
-                                                 J.local.loc_row_ptr, J.local.loc_col,
-                                                 J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-    } else {
-      const int64_t n = J.g.n;
-      int32_t *gb = J.s.walk;
-      WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st,
-                   gb + 4 * n + 4 * (int64_t)st, gb + 8 * n + 4 * (int64_t)st,
-                   gb + 12 * n + 4 * (int64_t)st};
-      walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, J.g, J.parts, J.local.perm,
-                                                  J.local.loc_row_ptr, J.local.loc_col,
-                                                  J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
-    }
+    const int64_t n = J.g.n;
+    int32_t *gb = J.s.walk;
+    WalkArrays w{gb + 2 * (int64_t)st, gb + 2 * n + 2 * (int64_t)st,
+                 gb + 4 * n + 4 * (int64_t)st, gb + 8 * n + 4 * (int64_t)st,
+                 gb + 12 * n + 4 * (int64_t)st};
+    walk_component<kWalkBlock, kWalkCap, false>(c, q, st, w, J.g, J.parts, J.local.perm,
+                                                J.local.loc_row_ptr, J.local.loc_col,
+                                                J.local.loc_eid, J.out, J.s, nullptr, sh_scan);
   }
 }
 
@@ -1560,7 +1796,7 @@ struct cg_batch {
   // their grids stay within it, so every workgroup of the snake order runs
   // from the start (a workgroup that waits for a free slot starts its whole
   // share late)
-  int res_induce_small, res_induce, res_walk_small, res_walk;
+  int res_iw_tiny, res_iw_small, res_iw, res_induce, res_walk;
   // jobs too large for one workgroup's components pass: they run through the
   // single-graph kernels (grid-wide) ahead of the batched launches
   std::vector<cg_job> ext_jobs;
@@ -1747,7 +1983,7 @@ static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
     carve(&view, J.g.n, J.g.m, J.P, &h.s);
     h.mt_first = n_mt;
     h.mt_count = h.external ? 0 : (J.g.n + kMaskTile - 1) / kMaskTile;
-    // the mask tiles: the job's list lives in its walk scratch, its bitmaps
+    // the mask tiles: the job's lists live in its walk scratch, its bitmaps
     // in its fill scratch (both reused by later steps)
     for (int32_t v0 = 0; !h.external && v0 < J.g.n; v0 += kMaskTile)
       b->h_mtiles.push_back(MaskTile{J.g.row_ptr, J.g.col, (int4 *)h.s.walk,
@@ -1844,21 +2080,24 @@ static int batch_alloc(cg_ctx *ctx, const cg_batch_params &prm, size_t bytes, cg
   b->mem = nullptr;
   b->mem_bytes = bytes > 0 ? bytes : 256;
   {
-    int dev = 0, cus = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
+    int dev = 0, cus = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k1, kb_induce_small, kIndSmallBlock, 0) !=
-            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k0, kb_induce_walk_tiny, kWalkSmallBlock,
+                                                     0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k1, kb_induce_walk_small, kWalkSmallBlock,
+                                                     0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k2, kb_induce, kIndBlock, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k3, kb_walk_small, kWalkSmallBlock, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k3, kb_induce_walk, kWalkBlock, 0) !=
             hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k4, kb_walk, kWalkBlock, 0) != hipSuccess) {
       delete b;
       return set_error(CG_EHIP, "occupancy query failed");
     }
-    b->res_induce_small = k1 * cus;
+    b->res_iw_tiny = k0 * cus;
+    b->res_iw_small = k1 * cus;
     b->res_induce = k2 * cus;
-    b->res_walk_small = k3 * cus;
+    b->res_iw = k3 * cus;
     b->res_walk = k4 * cus;
   }
   int prev = 0;
@@ -1981,9 +2220,14 @@ int cg_batch_run(cg_batch *b, void *stream) {
   CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
   CG_LAUNCH(ctx, kb_wq_place, dim3(128), dim3(kWqBlock), st, B);
   auto capped = [](int want, int fit) { return dim3((unsigned)(fit > 0 && fit < want ? fit : want)); };
-  CG_LAUNCH(ctx, kb_induce_small, capped(4 * PB, b->res_induce_small), dim3(kIndSmallBlock), st, B);
+  // components above kWalkCap reads in two passes (sort and walk arrays in
+  // scratch), the others in one
   CG_LAUNCH(ctx, kb_induce, capped(PB, b->res_induce), dim3(kIndBlock), st, B);
-  CG_LAUNCH(ctx, kb_walk_small, capped(4 * PB, b->res_walk_small), dim3(kWalkSmallBlock), st, B);
+  CG_LAUNCH(ctx, kb_induce_walk, capped(PB, b->res_iw), dim3(kWalkBlock), st, B);
+  CG_LAUNCH(ctx, kb_induce_walk_small, capped(4 * PB, b->res_iw_small), dim3(kWalkSmallBlock), st,
+            B);
+  CG_LAUNCH(ctx, kb_induce_walk_tiny, capped(8 * PB, b->res_iw_tiny), dim3(kWalkSmallBlock), st,
+            B);
   CG_LAUNCH(ctx, kb_walk, capped(PB, b->res_walk), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_offsets, dim3(b->n_jobs), dim3(kScanBlock), st, B);
   // one wave per copy chunk slot: the hardware hands chunks to waves as
