@@ -65,7 +65,8 @@ struct BatchDev {
   int32_t *tile_job;                // [n_vtiles]
   int32_t *comp_base;               // [n_jobs + 1] first component item of each job
   int32_t *piece_base;              // [n_jobs + 1] first piece item of each job
-  int32_t *chunk_base;              // [n_jobs + 1] first 64-piece copy chunk of each job
+  int32_t *chunk_base;              // [n_jobs + 1] first copy chunk of each job
+  int32_t *chunk_cp;                // [n_jobs] pieces per copy chunk of each job
   int2 *job_cnt;                    // [n_jobs] (components, component reads) of each job
   // work queue of the per-component passes: every component of the batch as
   // (job, component, reads, first local number), in decreasing read count
@@ -75,7 +76,7 @@ struct BatchDev {
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
                                     // reads, 2: above kWalkCap, 3: above kWalkTinyCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
-  int32_t *chunk_job;               // [sum of ceil(n / kChunkPieces)] job of each copy chunk
+  int32_t *chunk_job;               // [bound on the chunks] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
   int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
@@ -1089,8 +1090,11 @@ constexpr int kBatchLptBlock = 256;
 // pieces per copy chunk (one wave each).  Chunks are handed to waves as
 // slots free up, so the copy ends with a tail of the last chunks: 64 pieces
 // (about 75 us of one wave's work on 3 kbp pieces) left it long, 16 paid the
-// per-chunk setup too often.
+// per-chunk setup too often.  The jobs holding the last sixteenth of the
+// batch's pieces (the last chunks handed out, about one per wave slot) take
+// chunks of kTailChunkPieces, so the waves that start last finish sooner.
 constexpr int kChunkPieces = 32;
+constexpr int kTailChunkPieces = 8;
 constexpr int kWqBuckets = 4096;  // read counts from kWqBuckets - 1 up share the top bucket
 constexpr int kBatchSortCap = 2048;
 constexpr int kBatchBinCap = 256;
@@ -1163,20 +1167,36 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
                                          __HIP_MEMORY_SCOPE_AGENT);
     const int64_t xc = (int32_t)(uint32_t)w, xp = (int32_t)(uint32_t)(w >> 32);
     xcp += (xc << 32) | xp;
-    xh += (xp + kChunkPieces - 1) / kChunkPieces;
   }
   int64_t tcp, th;
   int64_t ecp = block_excl_scan<int64_t, kBatchLptBlock>(xcp, sh, &tcp);
+  // chunks: a job whose pieces reach into the last sixteenth of the
+  // batch's takes the tail chunk size
+  const int64_t np = (int64_t)(uint32_t)tcp;
+  const int64_t tail_at = np - (np >> 4);
+  {
+    int64_t pc = (int64_t)(uint32_t)ecp;
+    for (int i = i0; i < i1; ++i) {
+      const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      const int64_t xp = (int32_t)(uint32_t)(w >> 32);
+      const int cp = pc + xp > tail_at ? kTailChunkPieces : kChunkPieces;
+      xh += (xp + cp - 1) / cp;
+      pc += xp;
+    }
+  }
   int64_t eh = block_excl_scan<int64_t, kBatchLptBlock>(xh, sh, &th);
   for (int i = i0; i < i1; ++i) {
     const uint64_t w = __hip_atomic_load((uint64_t *)(B.job_cnt + i), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     const int64_t xc = (int32_t)(uint32_t)w, xp = (int32_t)(uint32_t)(w >> 32);
+    const int cp = (int64_t)(uint32_t)ecp + xp > tail_at ? kTailChunkPieces : kChunkPieces;
     B.comp_base[i] = (int32_t)(ecp >> 32);
     B.piece_base[i] = (int32_t)(uint32_t)ecp;
     B.chunk_base[i] = (int32_t)eh;
+    B.chunk_cp[i] = cp;
     ecp += (xc << 32) | xp;
-    eh += (xp + kChunkPieces - 1) / kChunkPieces;
+    eh += (xp + cp - 1) / cp;
   }
   if (threadIdx.x == 0) {
     B.comp_base[B.n_jobs] = (int32_t)(tcp >> 32);
@@ -1665,8 +1685,9 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
     const BJob J = job_at(B.jobs, j);
     if (*J.out.d_total_words > J.out.cap_words) continue;
     const int32_t n_e = ld_const(B.piece_base, j + 1) - ld_const(B.piece_base, j);
-    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * kChunkPieces;
-    const int cnt = n_e - c0 < kChunkPieces ? n_e - c0 : kChunkPieces;
+    const int cp = ld_const(B.chunk_cp, j);
+    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * cp;
+    const int cnt = n_e - c0 < cp ? n_e - c0 : cp;
     copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), c0, cnt, n_e, lane_id());
   }
 }
@@ -1859,7 +1880,7 @@ struct Plan {
   int64_t sum_chunks = 0;
   bool any_bases = false;
   size_t o_jobs, o_tiles, o_cbase, o_pbase, o_hbase, o_jcnt, o_cjob, o_wq, o_wqh, o_wqc, o_wqm,
-      o_hjob, o_counters, o_order, o_mtiles, o_mtcnt, total = 0;
+      o_hjob, o_counters, o_order, o_mtiles, o_mtcnt, o_ccp, total = 0;
   std::vector<size_t> job_off;
 };
 
@@ -1909,15 +1930,22 @@ static int plan_sizes(int32_t n_jobs, const cg_job *jobs, int vertex_tile, Plan 
   P->o_cbase = take(sizeof(int32_t) * (n_jobs + 1));
   P->o_pbase = take(sizeof(int32_t) * (n_jobs + 1));
   P->o_hbase = take(sizeof(int32_t) * (n_jobs + 1));
+  P->o_ccp = take(sizeof(int32_t) * n_jobs);
   P->o_jcnt = take(sizeof(int2) * n_jobs);
   int64_t sum_n = 0;
   P->sum_chunks = 0;
   P->any_bases = false;
+  int64_t max_n = 0;
   for (int i = 0; i < n_jobs; ++i) {
     sum_n += jobs[i].g.n;
+    max_n = jobs[i].g.n > max_n ? jobs[i].g.n : max_n;
     P->sum_chunks += (jobs[i].g.n + kChunkPieces - 1) / kChunkPieces;
     P->any_bases |= jobs[i].weight == CG_WEIGHT_BASES;
   }
+  // the tail chunks: the jobs in the last sixteenth of the pieces hold at
+  // most a sixteenth of all reads plus one job's, in chunks of
+  // kTailChunkPieces (one partial chunk per job)
+  P->sum_chunks += (sum_n / 16 + max_n) / kTailChunkPieces + n_jobs + 1;
   P->o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
   P->o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
   P->o_wqh = take(sizeof(int32_t) * kWqBuckets);
@@ -2009,6 +2037,7 @@ static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
   d.comp_base = (int32_t *)(mem + P.o_cbase);
   d.piece_base = (int32_t *)(mem + P.o_pbase);
   d.chunk_base = (int32_t *)(mem + P.o_hbase);
+  d.chunk_cp = (int32_t *)(mem + P.o_ccp);
   d.job_cnt = (int2 *)(mem + P.o_jcnt);
   d.wq = (int4 *)(mem + P.o_wq);
   d.wq_hist = (int32_t *)(mem + P.o_wqh);
