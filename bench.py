@@ -353,6 +353,23 @@ def main():
             batch.launch(side)
         b_wall, b_gpu = timed(lambda: batch.launch(side), side, args.steps)
     log("batched: %.3f ms/step wall, %.3f ms/step between events" % (b_wall, b_gpu))
+
+    def graph_cold(reps):
+        """Median over reps of one HIP-graph launch after a 1 GiB write (the
+        Infinity Cache then holds none of the path's data), between events."""
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        with torch.cuda.stream(side):
+            for r in range(reps):
+                flush.fill_(r)
+                e0.record(side)
+                batch.launch(side)
+                e1.record(side)
+                side.synchronize()
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    b_cold = graph_cold(args.reps)
+    log("batched, HIP graph after a cache flush: %.3f ms/step (median of %d)" % (b_cold, args.reps))
     with torch.cuda.stream(side):
         batch_kern = kernel_profile(lambda: batch.run(side), args.steps, 16)
         # medians of per-kernel times, warm and cold (the primary mask+CC
@@ -450,6 +467,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": step_ms,
+        # the same step with the cache flushed before each HIP-graph launch
+        "cold_ms_per_step": None if use_plain else b_cold,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
