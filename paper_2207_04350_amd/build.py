@@ -50,7 +50,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         msg = "\n".join("== %s ==\n%s" % f for f in failed)
         raise RuntimeError("libcg build failed:\n" + msg)
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, SO)
     for o in objs:

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include "../../include/cg.h"
@@ -311,6 +312,16 @@ __device__ __forceinline__ unsigned long long lookback_block_scan(ScanCtx sc, in
 // per-kernel timing is on.
 int prof_begin(cg_ctx *ctx, hipStream_t st, const char *name);
 void prof_end(cg_ctx *ctx, hipStream_t st, int slot);
+
+// A roctx range over a scope: the host-side enqueue of one step of
+// Algorithm 2 (a tracer such as rocprofv3 --marker-trace shows it beside the
+// step's kernels).  Costs a call when no tracer is attached.
+struct PhaseRange {
+  explicit PhaseRange(const char *name) { roctxRangePushA(name); }
+  ~PhaseRange() { roctxRangePop(); }
+  PhaseRange(const PhaseRange &) = delete;
+  PhaseRange &operator=(const PhaseRange &) = delete;
+};
 
 #define CG_LAUNCH(ctx, kern, grid, block, st, ...)                 \
   do {                                                             \

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
 
 int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_parts &parts,
                     const cg_local &local, int32_t P, const cg_contigs &out, hipStream_t st) {
+  const PhaseRange range("cg: LocalAssembly");
   const int32_t n = g.n;
   if (n == 0) {
     CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,

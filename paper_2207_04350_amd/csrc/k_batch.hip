@@ -2237,9 +2237,13 @@ int cg_batch_run(cg_batch *b, void *stream) {
     if (rc) return rc;
   }
   if (b->n_internal == 0) return hip_check(hipGetLastError(), "cg_batch_run");
-  if (B.n_mtiles > 0)
-    CG_LAUNCH(ctx, kb_mask_tiles, dim3(B.n_mtiles), dim3(kMaskThreads), st, b->mtiles);
-  CG_LAUNCH(ctx, kb_mask_cc, dim3(b->n_jobs), dim3(kMcBlock), st, B);
+  {
+    const PhaseRange range("cg_batch: BranchRemoval + ConnectedComponent");
+    if (B.n_mtiles > 0)
+      CG_LAUNCH(ctx, kb_mask_tiles, dim3(B.n_mtiles), dim3(kMaskThreads), st, b->mtiles);
+    CG_LAUNCH(ctx, kb_mask_cc, dim3(b->n_jobs), dim3(kMcBlock), st, B);
+  }
+  const PhaseRange range_p("cg_batch: GreedyPartitioning, InducedSubgraph, LocalAssembly");
   if (b->any_bases) {
     if (T == 256) CG_LAUNCH(ctx, kb_weight<256>, dim3(b->n_vtiles), dim3(256), st, B);
     else if (T == 512) CG_LAUNCH(ctx, kb_weight<512>, dim3(b->n_vtiles), dim3(512), st, B);

@@ -114,6 +114,7 @@ __global__ __launch_bounds__(kScanBlock) void k_ind_rows(
 int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
                   const int32_t *label, const cg_parts &parts, int32_t P, const cg_local &out,
                   hipStream_t st) {
+  const PhaseRange range("cg: InducedSubgraph");
   const int32_t n = g.n;
   const int zgrid = n > 0 ? (int)((n + kScanBlock - 1) / kScanBlock) : 1;
   CG_LAUNCH(ctx, k_ind_zero, dim3(zgrid < 256 ? zgrid : 256), dim3(kScanBlock), st, P,

@@ -86,6 +86,7 @@ __global__ __launch_bounds__(kWave) void k_mask_sum(int nparts, const Fixed *fx,
 
 int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_counts,
                 hipStream_t st) {
+  const PhaseRange range("cg: BranchRemoval");
   int64_t grid = ((int64_t)g.n + kMaskBlock - 1) / kMaskBlock;
   if (grid < 1) grid = 1;
   if (grid > kMaskMaxBlocks) grid = kMaskMaxBlocks;
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(kCcBlock) void k_cc_compress(int32_t n, int32_t *la
 
 int launch_components(cg_ctx *ctx, const cg_graph &g, const uint8_t *flags, int32_t *label,
                       hipStream_t st) {
+  const PhaseRange range("cg: ConnectedComponent");
   (void)ctx;
   if (g.n == 0) return CG_OK;
   int grid = (int)((g.n + kCcBlock - 1) / kCcBlock);
@@ -244,6 +246,7 @@ __global__ void k_val_final(Fixed *fx, int64_t *d_bad) {
 }
 
 int launch_validate(cg_ctx *ctx, const cg_graph &g, int64_t *d_bad, hipStream_t st) {
+  const PhaseRange range("cg: validate");
   int grid = (int)((g.n + kValBlock - 1) / kValBlock);
   if (grid == 0) grid = 1;
   CG_LAUNCH(ctx, k_val_init, dim3(1), dim3(1), st, ctx->fixed);

@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kLptBlock) void k_part_lpt(int32_t P, const int32_t
 int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
                      const int32_t *label, int32_t P, int32_t min_reads, int32_t weight,
                      const cg_parts &out, hipStream_t st) {
+  const PhaseRange range("cg: GreedyPartitioning");
   const int32_t n = g.n;
   if (min_reads < 1) min_reads = 1;
   const int grid = n > 0 ? (int)((n + kPartBlock - 1) / kPartBlock) : 1;

@@ -246,6 +246,7 @@ __global__ __launch_bounds__(kRedRowBlock) void k_red_compact(
 int launch_reduce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, uint32_t fuzz,
                   uint8_t *contained, uint8_t *kept, int32_t *s_row_ptr, int32_t *s_col,
                   uint32_t *s_ovl, uint8_t *s_strand, int32_t *d_m, hipStream_t st) {
+  const PhaseRange range("cg: reduce");
   const int32_t n = g.n;
   const dim3 rows((n + kRedRowWaves - 1) / kRedRowWaves);
   if (n > 0) {
