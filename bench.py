@@ -63,11 +63,15 @@ def algo_bytes(kernel, s):
         "k_ind_fill": 4 * N + 4 * N + 8 * n_e,
         "k_ind_local": 8 * n_e + 4 * n_e,
         "k_ind_rows": 4 * n_e + n_e + 4 * (n_e + 1) + 8 * m_e + 4 * n_e,
-        "k_asm_walk": 4 * n_e + 8 * n_e + 8 * m_e + 9 * m_e + 4 * n_e + 5 * n_e + 16 * n_e,
+        # perm, local rows, entries (columns + ids, strands + overlaps), read
+        # lengths and store offsets; layout (id, strand) and pieces (length,
+        # store anchor, offset) written
+        "k_asm_walk": 4 * n_e + 8 * n_e + 8 * m_e + 9 * m_e + 12 * n_e + 5 * n_e + 20 * n_e,
         "k_asm_offsets": 16 * nc,
-        # packed source bases read + contig words written + per-piece,
-        # per-read and per-contig descriptors
-        "k_asm_copy": Cb // 4 + 4 * W + 33 * n_e + 16 * nc,
+        # packed source bases read + contig words written + per-piece
+        # descriptors (contig, offset, length, store anchor) and per-contig
+        # records (length, base offset)
+        "k_asm_copy": Cb // 4 + 4 * W + 24 * n_e + 16 * nc,
     }
     return table.get(kernel)
 

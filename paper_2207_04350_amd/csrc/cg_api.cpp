@@ -49,7 +49,7 @@ Layout layout(int64_t n, int64_t m, int64_t P) {
   L.walk = take(4 * 16 * (size_t)nn);
   L.estart = take(4 * (size_t)nn);
   L.memb = take(4 * (size_t)nn);
-  L.piece_skip = take(4 * (size_t)nn);
+  L.piece_src = take(8 * (size_t)nn);
   L.comp_w = take(8 * (size_t)nn);
   L.bin_reads = take(8 * (size_t)(P > 0 ? P : 1));
   L.total = at;
@@ -73,7 +73,7 @@ bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s) {
   s->walk = (int32_t *)(b + L.walk);
   s->estart = (int32_t *)(b + L.estart);
   s->memb = (int32_t *)(b + L.memb);
-  s->piece_skip = (uint32_t *)(b + L.piece_skip);
+  s->piece_src = (uint64_t *)(b + L.piece_src);
   s->comp_w = (uint64_t *)(b + L.comp_w);
   s->bin_reads = (uint64_t *)(b + L.bin_reads);
   return true;

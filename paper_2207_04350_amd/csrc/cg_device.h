@@ -736,6 +736,18 @@ constexpr int kWalkCap = 1024;               // reads per component handled in L
 constexpr int kWalkSmallBlock = 64;
 constexpr int kWalkSmallCap = 128;
 
+// Where a piece starts in the store, as the copy needs it (Section 4.4: the
+// piece is bases [skip, skip + plen) of its read in walking orientation).
+// Bits 0-62: forward, the stored base of the piece's first base; reverse,
+// one past the stored base of its first base (the piece is read backwards
+// from there).  Bit 63: the read is walked reverse-complemented.  A read
+// ends inside the store (read_off + read_len <= 16 seq_words), so the base
+// offset stays below 2^63.
+__device__ __forceinline__ uint64_t piece_anchor(uint64_t roff, uint32_t rlen, uint32_t skip,
+                                                 bool rev) {
+  return rev ? ((roff + rlen - skip) | (1ull << 63)) : roff + skip;
+}
+
 struct WalkArrays {
   int32_t *nb;     // [2q] local neighbour of slot k of read i (-1: none / cut)
   int32_t *eid;    // [2q] entry index in S of that slot
@@ -745,6 +757,7 @@ struct WalkArrays {
   // the LDS form also keeps what the pieces need, loaded before the doubling:
   int32_t *vid;    // [q] read id of local read i
   uint32_t *rlen;  // [q] its length
+  uint64_t *roff;  // [q] its first base in the store
   uint8_t *es;     // [2q] strand bits of the entry of slot k
   uint32_t *eo;    // [2q] its pre (explicit coordinates) or overlap length
   uint32_t *ep;    // [2q] its post (explicit coordinates)
@@ -783,6 +796,7 @@ __device__ __forceinline__ void walk_component(
     const CG_GLOBAL int32_t *leid = (const CG_GLOBAL int32_t *)loc_eid;
     const CG_GLOBAL int32_t *gperm = (const CG_GLOBAL int32_t *)perm;
     const CG_GLOBAL uint32_t *glen = (const CG_GLOBAL uint32_t *)g.read_len;
+    const CG_GLOBAL uint64_t *goff = (const CG_GLOBAL uint64_t *)g.read_off;
     const CG_GLOBAL uint8_t *gstr = (const CG_GLOBAL uint8_t *)g.strand;
     const CG_GLOBAL uint32_t *gov =
         (const CG_GLOBAL uint32_t *)(g.pre ? g.pre : g.ovl);
@@ -800,13 +814,18 @@ __device__ __forceinline__ void walk_component(
     }
     int c0[R], c1[R], e0[R], e1[R];
     uint32_t rl[R];
+    uint64_t ro[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int i = tid + u * BLOCK;
       const int deg = i < q ? rd[u] - ra[u] : 0;
       c0[u] = c1[u] = e0[u] = e1[u] = -1;
       rl[u] = 0;
-      if (i < q) rl[u] = glen[rv[u]];
+      ro[u] = 0;
+      if (i < q) {
+        rl[u] = glen[rv[u]];
+        ro[u] = goff[rv[u]];
+      }
       if (deg >= 1) {
         c0[u] = lcol[ra[u]];
         e0[u] = leid[ra[u]];
@@ -841,6 +860,7 @@ __device__ __forceinline__ void walk_component(
       w.eid[2 * i + 1] = e1[u];
       w.vid[i] = rv[u];
       w.rlen[i] = rl[u];
+      w.roff[i] = ro[u];
       w.es[2 * i] = (uint8_t)s0[u];
       w.es[2 * i + 1] = (uint8_t)s1[u];
       w.eo[2 * i] = o0[u];
@@ -983,7 +1003,7 @@ __device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, c
   int32_t *R_vid = out.layout_vid + st;
   uint8_t *R_rev = out.layout_rev + st;
   uint32_t *R_len = s.piece_len + st;
-  uint32_t *R_skip = s.piece_skip + st;
+  uint64_t *R_src = s.piece_src + st;
   const int rank_c = parts.comp_rank[c];
   for (int i = tid; i < q; i += BLOCK) {
     int rank = 0, pred = -1, succ = -1, succ_e = -1;
@@ -1010,6 +1030,7 @@ __device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, c
     // strand bits, overlap or coordinates of the two entries, and the read
     const int32_t v = kLds ? w.vid[i] : perm[st + i];
     const uint32_t L = kLds ? w.rlen[i] : g.read_len[v];
+    const uint64_t roff = kLds ? w.roff[i] : g.read_off[v];
     const uint32_t ses = ss < 0 ? 0u : (kLds ? w.es[ss] : (uint32_t)g.strand[succ_e]);
     const uint32_t pes = ps < 0 ? 0u : (kLds ? w.es[ps] : (uint32_t)g.strand[w.eid[ps]]);
     int orient;
@@ -1037,7 +1058,7 @@ __device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, c
     R_rev[rank] = (uint8_t)orient;
     R_len[rank] = plen;
     if constexpr (kLds) w.nxt[rank] = (int32_t)plen;  // nxt is free after the rays
-    R_skip[rank] = skip;
+    R_src[rank] = piece_anchor(roff, L, skip, orient != 0);
     s.lay_contig[st + rank] = rank_c;
     (void)succ;
   }
@@ -1078,55 +1099,43 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // One piece as the copy needs it.
 struct PieceD {
-  uint64_t src;   // base offset of the piece's read in the store
+  uint64_t a;     // piece_anchor without its strand bit
   uint64_t poff;  // first base of the piece in its contig
   uint64_t L;     // contig length
   uint64_t cb;    // first output word of the contig
-  uint32_t rlen;  // read length
   uint32_t plen;  // piece length
-  uint32_t skip;  // first base of the piece in the read's walking orientation
   int32_t rev;    // read walked reverse-complemented
 };
 
+// The per-piece arrays are read in piece order (coalesced across a wave's
+// lanes); only the two per-contig arrays are gathered.
 struct PieceArrays {
   const CG_GLOBAL int32_t *lay_contig;
-  const CG_GLOBAL int32_t *layout_vid;
-  const CG_GLOBAL uint8_t *layout_rev;
   const CG_GLOBAL uint64_t *piece_off;
   const CG_GLOBAL uint32_t *piece_len;
-  const CG_GLOBAL uint32_t *piece_skip;
-  const CG_GLOBAL uint64_t *read_off;
-  const CG_GLOBAL uint32_t *read_len;
+  const CG_GLOBAL uint64_t *piece_src;
   const CG_GLOBAL uint64_t *clen;
   const CG_GLOBAL uint64_t *cbase;
 };
 
 __device__ __forceinline__ PieceArrays piece_arrays(const int32_t *lay_contig,
-                                                    const int32_t *layout_vid,
-                                                    const uint8_t *layout_rev,
                                                     const uint64_t *piece_off,
                                                     const uint32_t *piece_len,
-                                                    const uint32_t *piece_skip,
-                                                    const uint64_t *read_off,
-                                                    const uint32_t *read_len, const uint64_t *clen,
-                                                    const uint64_t *cbase) {
-  return PieceArrays{(const CG_GLOBAL int32_t *)lay_contig,  (const CG_GLOBAL int32_t *)layout_vid,
-                     (const CG_GLOBAL uint8_t *)layout_rev,  (const CG_GLOBAL uint64_t *)piece_off,
-                     (const CG_GLOBAL uint32_t *)piece_len,  (const CG_GLOBAL uint32_t *)piece_skip,
-                     (const CG_GLOBAL uint64_t *)read_off,   (const CG_GLOBAL uint32_t *)read_len,
-                     (const CG_GLOBAL uint64_t *)clen,       (const CG_GLOBAL uint64_t *)cbase};
+                                                    const uint64_t *piece_src,
+                                                    const uint64_t *clen, const uint64_t *cbase) {
+  return PieceArrays{(const CG_GLOBAL int32_t *)lay_contig, (const CG_GLOBAL uint64_t *)piece_off,
+                     (const CG_GLOBAL uint32_t *)piece_len, (const CG_GLOBAL uint64_t *)piece_src,
+                     (const CG_GLOBAL uint64_t *)clen,      (const CG_GLOBAL uint64_t *)cbase};
 }
 
 __device__ __forceinline__ PieceD load_piece(const PieceArrays &A, int32_t p) {
   PieceD d;
   const int32_t k = A.lay_contig[p];
-  const int32_t v = A.layout_vid[p];
-  d.src = A.read_off[v];
-  d.rlen = A.read_len[v];
+  const uint64_t a = A.piece_src[p];
+  d.a = a & ~(1ull << 63);
+  d.rev = (int32_t)(a >> 63);
   d.plen = A.piece_len[p];
-  d.skip = A.piece_skip[p];
   d.poff = A.piece_off[p];
-  d.rev = A.layout_rev[p];
   d.L = A.clen[k];
   d.cb = A.cbase[k] >> 4;
   return d;
@@ -1164,16 +1173,15 @@ __device__ __forceinline__ uint32_t low_fields(int k) {
 
 // Stored base where the 16-base window holding a piece's first 16 bases (in
 // walking orientation) starts: forward at the piece's first base, reverse 15
-// bases below it (the window is then read backwards).
-__device__ __forceinline__ uint64_t head_src(uint64_t src, uint32_t rlen, uint32_t skip, bool rev) {
-  return rev ? src + rlen - 16 - skip : src + skip;
-}
+// bases below it (the window is then read backwards).  a is the piece's
+// anchor without its strand bit.
+__device__ __forceinline__ uint64_t head_src(uint64_t a, bool rev) { return rev ? a - 16 : a; }
 
 // The first k (<= 16) bases of a piece in walking orientation, in fields 0..k-1
 // (fields above k are not cleared).
 __device__ __forceinline__ uint32_t piece_head16(const CG_GLOBAL uint32_t *__restrict__ seq,
                                                  uint64_t nwords, const PieceD &f) {
-  const uint32_t x = window16(seq, nwords, head_src(f.src, f.rlen, f.skip, f.rev != 0));
+  const uint32_t x = window16(seq, nwords, head_src(f.a, f.rev != 0));
   return f.rev ? revcomp16(x) : x;
 }
 
@@ -1213,8 +1221,7 @@ __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
   c.nw = (uint32_t)(j1 - j0);
   const uint32_t fs = (uint32_t)(pend - 16 * (j1 - 1));
   // stored base where the window of the first group begins (modulo 2^64)
-  const uint64_t sb0 = d.rev ? d.src + d.rlen - 16 * kGroupWords - d.skip + d.poff - 16 * j0
-                             : d.src + d.skip - d.poff + 16 * j0;
+  const uint64_t sb0 = d.rev ? d.a - 16 * kGroupWords + d.poff - 16 * j0 : d.a - d.poff + 16 * j0;
   c.sw0 = (int64_t)sb0 >> 4;
   c.info = fs | (d.rev ? 32u : 0u) | (pend == d.L ? 64u : 0u) | ((uint32_t)(sb0 & 15) << 8);
   return c;
@@ -1222,7 +1229,7 @@ __device__ __forceinline__ CopyD copy_desc(const PieceD &d) {
 
 __device__ __forceinline__ CopyE copy_next(const PieceD &e) {
   CopyE c;
-  c.hsrc = head_src(e.src, e.rlen, e.skip, e.rev != 0);
+  c.hsrc = head_src(e.a, e.rev != 0);
   c.info = e.plen | (e.rev ? (1u << 30) : 0u) | (e.poff + e.plen == e.L ? (1u << 31) : 0u);
   return c;
 }

@@ -43,7 +43,7 @@ struct Scratch {
   uint32_t *fill;      // [n] induce: bucket cursors
   uint64_t *piece_off; // [n] assemble: base offset of each piece in its contig
   uint32_t *piece_len; // [n] assemble: bases of each piece
-  uint32_t *piece_skip;// [n] assemble: first base of each piece in its read's walking orientation
+  uint64_t *piece_src; // [n] assemble: where each piece starts in the store (see piece_anchor)
   int32_t *lay_contig; // [n] assemble: record index of each layout entry
   uint64_t *keys;      // [2n] partition fallback: sort keys
   uint64_t *bins;      // [2P] partition fallback: sorted bin keys
@@ -81,7 +81,7 @@ namespace cg {
 // Scratch carving shared by cg_footprint, the calls and the batch slices.
 struct Layout {
   size_t scan_status, tmp, lidx, fill, piece_off, piece_len, lay_contig, keys, bins, aux, walk,
-      estart, memb, piece_skip, comp_w, bin_reads, total;
+      estart, memb, piece_src, comp_w, bin_reads, total;
 };
 Layout layout(int64_t n, int64_t m, int64_t P);
 bool carve(cg_ctx *ctx, int64_t n, int64_t m, int64_t P, Scratch *s);

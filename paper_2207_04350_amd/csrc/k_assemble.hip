@@ -22,6 +22,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
   __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
+  __shared__ uint64_t s_roff[kWalkCap];
   __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int nc = *parts.d_n_comp;
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
     const int q = parts.comp_size[c];
     const int st = parts.comp_start[c];
     if (q <= kWalkCap) {
-      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+      WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
       walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
                            local.loc_eid, out, s, nullptr, sh_scan);
     } else {
@@ -74,15 +75,11 @@ constexpr int kCopyBlock = 256;
 
 __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restrict__ seq,
                                                          uint64_t seq_words,
-                                                         const uint32_t *__restrict__ read_len,
-                                                         const uint64_t *__restrict__ read_off,
                                                          const int32_t *__restrict__ bin_vptr,
                                                          int32_t P,
-                                                         const int32_t *__restrict__ layout_vid,
-                                                         const uint8_t *__restrict__ layout_rev,
                                                          const uint64_t *__restrict__ piece_off,
                                                          const uint32_t *__restrict__ piece_len,
-                                                         const uint32_t *__restrict__ piece_skip,
+                                                         const uint64_t *__restrict__ piece_src,
                                                          const int32_t *__restrict__ lay_contig,
                                                          const uint64_t *__restrict__ clen,
                                                          const uint64_t *__restrict__ cbase,
@@ -91,8 +88,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
                                                          uint32_t *__restrict__ bases) {
   if (*d_total_words > cap_words) return;
   const int32_t n_e = bin_vptr[P];
-  const PieceArrays A = piece_arrays(lay_contig, layout_vid, layout_rev, piece_off, piece_len,
-                                     piece_skip, read_off, read_len, clen, cbase);
+  const PieceArrays A = piece_arrays(lay_contig, piece_off, piece_len, piece_src, clen, cbase);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
@@ -125,11 +121,8 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
   // about eight pieces per wave, so a small graph still spreads over the chip
   const int cgrid = (n + 31) / 32 < 8192 ? (n + 31) / 32 : 8192;
   CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
-                     g.read_len,
-                     g.read_off, local.bin_vptr, P, out.layout_vid, out.layout_rev, s.piece_off,
-                     s.piece_len, s.piece_skip, s.lay_contig, out.len, out.base_off,
-                     out.d_total_words,
-                     out.cap_words, out.bases);
+                     local.bin_vptr, P, s.piece_off, s.piece_len, s.piece_src, s.lay_contig,
+                     out.len, out.base_off, out.d_total_words, out.cap_words, out.bases);
   return hip_check(hipGetLastError(), "k_asm");
 }
 

@@ -1385,6 +1385,7 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
   const CG_GLOBAL i32x2 *mem = (const CG_GLOBAL i32x2 *)(J.s.tmp + 2 * (int64_t)J.s.memb[c]);
   const CG_GLOBAL i32x4 *la = (const CG_GLOBAL i32x4 *)J.s.walk;
   const CG_GLOBAL uint32_t *glen = (const CG_GLOBAL uint32_t *)J.g.read_len;
+  const CG_GLOBAL uint64_t *goff = (const CG_GLOBAL uint64_t *)J.g.read_off;
   const CG_GLOBAL uint8_t *gstr = (const CG_GLOBAL uint8_t *)J.g.strand;
   const CG_GLOBAL uint32_t *gov = (const CG_GLOBAL uint32_t *)(J.g.pre ? J.g.pre : J.g.ovl);
   const CG_GLOBAL uint32_t *gpost = (const CG_GLOBAL uint32_t *)J.g.post;
@@ -1424,18 +1425,21 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
       if (kb[u] & 2u) A[u].z = J.g.col[b + 1];
     }
   }
-  // then the read lengths and the kept entries' strand bits, overlaps (or
-  // pre) and post: Bq = (length, ov of entry 0, ov of entry 1, strands), Cq =
-  // post of both
+  // then the read lengths and store offsets and the kept entries' strand
+  // bits, overlaps (or pre) and post: Bq = (length, ov of entry 0, ov of
+  // entry 1, strands), Cq = post of both, ro = store offset
   i32x4 Bq[R];
   i32x2 Cq[R];
+  uint64_t ro[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     Bq[u] = i32x4{0, 0, 0, 0};
     Cq[u] = i32x2{0, 0};
+    ro[u] = 0;
     if (tid + u * BLOCK >= q) continue;
     const int32_t b = A[u].w;
     Bq[u].x = (int32_t)glen[v[u]];
+    ro[u] = goff[v[u]];
     if (kb[u] & 1u) {
       Bq[u].y = (int32_t)gov[b];
       Bq[u].w = gstr[b];
@@ -1522,6 +1526,7 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
     w.ep[2 * r + 1] = s1 ? (uint32_t)Cq[u].y : 0u;
     w.vid[r] = v[u];
     w.rlen[r] = (uint32_t)Bq[u].x;
+    w.roff[r] = ro[u];
   }
   lds_barrier();
   // 4. perm and the local CSR rows, in local order
@@ -1566,6 +1571,7 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_tiny(BatchDev 
   __shared__ int32_t s_nb[2 * kWalkTinyCap], s_eid[2 * kWalkTinyCap], s_nxt[2 * kWalkTinyCap],
       s_dist[2 * kWalkTinyCap], s_endv[2 * kWalkTinyCap], s_vid[kWalkTinyCap];
   __shared__ uint32_t s_rlen[kWalkTinyCap], s_eo[2 * kWalkTinyCap], s_ep[2 * kWalkTinyCap];
+  __shared__ uint64_t s_roff[kWalkTinyCap];
   __shared__ uint8_t s_es[2 * kWalkTinyCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 3), hi = ld_const(B.wq_meta, 0);
@@ -1574,7 +1580,7 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_tiny(BatchDev 
     const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
     const int st = __builtin_amdgcn_readfirstlane(d.w);
     const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
-    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
     iw_component<kWalkSmallBlock, kWalkTinyCap>(J, c, q, st, w, sh_scan);
   }
 }
@@ -1584,6 +1590,7 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
   __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
       s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
   __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
+  __shared__ uint64_t s_roff[kWalkSmallCap];
   __shared__ uint8_t s_es[2 * kWalkSmallCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 1), hi = ld_const(B.wq_meta, 3);
@@ -1592,7 +1599,7 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
     const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
     const int st = __builtin_amdgcn_readfirstlane(d.w);
     const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
-    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
     iw_component<kWalkSmallBlock, kWalkSmallCap>(J, c, q, st, w, sh_scan);
   }
 }
@@ -1603,6 +1610,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
   __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
+  __shared__ uint64_t s_roff[kWalkCap];
   __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 1);
@@ -1611,7 +1619,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
     const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
     const int st = __builtin_amdgcn_readfirstlane(d.w);
     const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
-    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_es, s_eo, s_ep};
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
     iw_component<kWalkBlock, kWalkCap>(J, c, q, st, w, sh_scan);
   }
 }
@@ -1669,8 +1677,7 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
 // 9. packed copy: one wave per chunk of kChunkPieces consecutive pieces of a
 // job (the grid covers an upper bound on the chunks; waves past the last exit)
 __device__ __forceinline__ PieceArrays piece_arrays(const BJob &J) {
-  return piece_arrays(J.s.lay_contig, J.out.layout_vid, J.out.layout_rev, J.s.piece_off,
-                      J.s.piece_len, J.s.piece_skip, J.g.read_off, J.g.read_len, J.out.len,
+  return piece_arrays(J.s.lay_contig, J.s.piece_off, J.s.piece_len, J.s.piece_src, J.out.len,
                       J.out.base_off);
 }
 
