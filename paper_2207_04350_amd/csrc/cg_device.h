@@ -770,12 +770,25 @@ __device__ __forceinline__ void walk_component(
     const int32_t *__restrict__ loc_col, const int32_t *__restrict__ loc_eid,
     const cg_contigs &out, const Scratch &s, int32_t *sh_small, uint32_t *sh_scan);
 
+// What a component's contig record takes from the component table: its
+// record index (the component's (bin, label) rank), label and bin.  Loaded
+// when the component's work starts, so that no load waits at its end.
+struct CompRec {
+  int32_t rank, label, bin;
+};
+__device__ __forceinline__ CompRec comp_rec(const cg_parts &parts, int c, int32_t rank) {
+  return CompRec{rank, ((const CG_GLOBAL int32_t *)parts.comp_label)[c],
+                 ((const CG_GLOBAL int32_t *)parts.comp_bin)[c]};
+}
+__device__ __forceinline__ CompRec comp_rec(const cg_parts &parts, int c) {
+  return comp_rec(parts, c, ((const CG_GLOBAL int32_t *)parts.comp_rank)[c]);
+}
+
 // Steps 2-5 of the walk, from the component's rows in w (nb, eid; and in the
-// LDS form vid, rlen, es, eo, ep).
+// LDS form vid, rlen, roff, es, eo, ep).
 template <int BLOCK, int CAP, bool kLds>
-__device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, const cg_graph &g,
-                                           const cg_parts &parts,
-                                           const int32_t *__restrict__ perm,
+__device__ __forceinline__ void walk_chain(const CompRec &cr, int q, int st, WalkArrays w,
+                                           const cg_graph &g, const int32_t *__restrict__ perm,
                                            const cg_contigs &out, const Scratch &s,
                                            uint32_t *sh_scan);
 
@@ -786,6 +799,7 @@ __device__ __forceinline__ void walk_component(
     const int32_t *__restrict__ loc_col, const int32_t *__restrict__ loc_eid,
     const cg_contigs &out, const Scratch &s, int32_t *sh_small, uint32_t *sh_scan) {
   const int tid = threadIdx.x;
+  const CompRec cr = comp_rec(parts, c);
   // 1. local rows of the component's block
   if constexpr (kLds) {
     // and, in three rounds of loads issued together, the read ids and
@@ -879,14 +893,13 @@ __device__ __forceinline__ void walk_component(
     }
   }
   __syncthreads();
-  walk_chain<BLOCK, CAP, kLds>(c, q, st, w, g, parts, perm, out, s, sh_scan);
+  walk_chain<BLOCK, CAP, kLds>(cr, q, st, w, g, perm, out, s, sh_scan);
   (void)sh_small;
 }
 
 template <int BLOCK, int CAP, bool kLds>
-__device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, const cg_graph &g,
-                                           const cg_parts &parts,
-                                           const int32_t *__restrict__ perm,
+__device__ __forceinline__ void walk_chain(const CompRec &cr, int q, int st, WalkArrays w,
+                                           const cg_graph &g, const int32_t *__restrict__ perm,
                                            const cg_contigs &out, const Scratch &s,
                                            uint32_t *sh_scan) {
   const int tid = threadIdx.x;
@@ -1004,7 +1017,7 @@ __device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, c
   uint8_t *R_rev = out.layout_rev + st;
   uint32_t *R_len = s.piece_len + st;
   uint64_t *R_src = s.piece_src + st;
-  const int rank_c = parts.comp_rank[c];
+  const int rank_c = cr.rank;
   for (int i = tid; i < q; i += BLOCK) {
     int rank = 0, pred = -1, succ = -1, succ_e = -1;
     int ss = -1;  // slot of i leading to its successor
@@ -1075,8 +1088,8 @@ __device__ __forceinline__ void walk_chain(int c, int q, int st, WalkArrays w, c
     wbar();
   }
   if (tid == 0) {
-    out.label[rank_c] = parts.comp_label[c];
-    out.bin[rank_c] = parts.comp_bin[c];
+    out.label[rank_c] = cr.label;
+    out.bin[rank_c] = cr.bin;
     out.start[rank_c] = kLds ? w.vid[s0] : perm[st + s0];
     out.n_reads[rank_c] = q;
     out.len[rank_c] = s_carry;

@@ -60,6 +60,17 @@ __device__ __forceinline__ int32_t ld_const(const int32_t *a, int64_t i) {
   return ((const CG_CONST int32_t *)a)[i];
 }
 
+// A work-queue entry: a component, its job, and what its per-component
+// passes need of the component table, so that none of it is a load of its
+// own on the component's critical path.
+struct WqE {
+  int32_t job, c, q, st;  // job, component, reads, first local number
+  int32_t estart;         // its first local CSR entry
+  int32_t rank;           // its contig record (the component's (bin, label) rank)
+  const int32_t *mem;     // its member records (id, list slot | kept bits << 30)
+};
+static_assert(sizeof(WqE) == 32, "queue entries are read as 32 bytes");
+
 struct BatchDev {
   BJob *jobs;                       // [n_jobs]
   int32_t *tile_job;                // [n_vtiles]
@@ -68,9 +79,9 @@ struct BatchDev {
   int32_t *chunk_base;              // [n_jobs + 1] first copy chunk of each job
   int32_t *chunk_cp;                // [n_jobs] pieces per copy chunk of each job
   int2 *job_cnt;                    // [n_jobs] (components, component reads) of each job
-  // work queue of the per-component passes: every component of the batch as
-  // (job, component, reads, first local number), in decreasing read count
-  int4 *wq;                         // [upper bound on the batch's components]
+  // work queue of the per-component passes: every component of the batch,
+  // in decreasing read count
+  WqE *wq;                          // [upper bound on the batch's components]
   int32_t *wq_hist;                 // [kWqBuckets] components per read count (capped)
   int32_t *wq_cur;                  // [kWqBuckets] placement cursors
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
@@ -1257,6 +1268,11 @@ constexpr int kWqBlock = 256;
 constexpr int kWalkTinyCap = 32;  // reads of the components the tiny pass takes
 constexpr int kWqPer = kWqBuckets / kWqBlock;
 
+__device__ __forceinline__ WqE wq_make(const BJob &J, int j, int32_t c, int32_t q) {
+  return WqE{j, c, q, J.parts.comp_start[c], J.s.estart[c], J.parts.comp_rank[c],
+             J.s.tmp + 2 * (int64_t)J.s.memb[c]};
+}
+
 __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   __shared__ int32_t s_start[kWqBuckets], s_cnt[kWqBuckets], s_base[kWqBuckets];
   __shared__ int32_t sh[kWqBlock / kWave + 1];
@@ -1294,13 +1310,13 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   // the thread's first component is kept in registers for the placement
   // (with 128 workgroups of 256 threads, every component of a batch of up to
   // 32768 is a first one); later ones are loaded again there
-  int4 first = make_int4(-1, 0, 0, 0);
+  WqE first{-1, 0, 0, 0, 0, 0, nullptr};
   for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
     const int j = B.comp_job[i];
     const int32_t c = i - B.comp_base[j];
-    const cg_parts &P = B.jobs[j].parts;
-    const int32_t q = P.comp_size[c];
-    if (i == i0 + (int32_t)threadIdx.x) first = make_int4(j, c, q, P.comp_start[c]);
+    const BJob &J = B.jobs[j];
+    const int32_t q = J.parts.comp_size[c];
+    if (i == i0 + (int32_t)threadIdx.x) first = wq_make(J, j, c, q);
     atomicAdd(s_cnt + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
   }
   __syncthreads();
@@ -1311,14 +1327,14 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   }
   __syncthreads();
   for (int32_t i = i0 + threadIdx.x; i < i1; i += kWqBlock) {
-    int4 e = first;
+    WqE e = first;
     if (i != i0 + (int32_t)threadIdx.x) {
       const int j = B.comp_job[i];
       const int32_t c = i - B.comp_base[j];
-      const cg_parts &P = B.jobs[j].parts;
-      e = make_int4(j, c, P.comp_size[c], P.comp_start[c]);
+      const BJob &J = B.jobs[j];
+      e = wq_make(J, j, c, J.parts.comp_size[c]);
     }
-    const int b = e.z < kWqBuckets - 1 ? e.z : kWqBuckets - 1;
+    const int b = e.q < kWqBuckets - 1 ? e.q : kWqBuckets - 1;
     B.wq[s_base[b] + atomicAdd(s_cnt + b, 1)] = e;
   }
 }
@@ -1340,6 +1356,15 @@ __device__ __forceinline__ int4 wq_at(const BatchDev &B, int32_t x) {
   const uint64_t a = p[0], b = p[1];
   return make_int4((int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)(uint32_t)b,
                    (int)(uint32_t)(b >> 32));
+}
+// the whole entry x (uniform), by scalar loads
+__device__ __forceinline__ WqE wq_get(const BatchDev &B, int32_t x) {
+  WqE e;
+  const CG_CONST uint64_t *p = (const CG_CONST uint64_t *)(B.wq + x);
+  uint64_t *q = reinterpret_cast<uint64_t *>(&e);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = p[k];
+  return e;
 }
 
 // 6. induced subgraph of each component: sorted local numbers and local CSR
@@ -1378,11 +1403,12 @@ __device__ __forceinline__ int32_t lds_lower_bound(const int32_t *a, int q, int3
 }
 
 template <int BLOCK, int CAP>
-__device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st, WalkArrays w,
+__device__ __forceinline__ void iw_component(const BJob &J, const WqE &e, WalkArrays w,
                                              uint32_t *sh_scan) {
   constexpr int R = CAP >= BLOCK ? CAP / BLOCK : 1;  // members per thread
   const int tid = threadIdx.x;
-  const CG_GLOBAL i32x2 *mem = (const CG_GLOBAL i32x2 *)(J.s.tmp + 2 * (int64_t)J.s.memb[c]);
+  const int q = e.q, st = e.st;
+  const CG_GLOBAL i32x2 *mem = (const CG_GLOBAL i32x2 *)e.mem;
   const CG_GLOBAL i32x4 *la = (const CG_GLOBAL i32x4 *)J.s.walk;
   const CG_GLOBAL uint32_t *glen = (const CG_GLOBAL uint32_t *)J.g.read_len;
   const CG_GLOBAL uint64_t *goff = (const CG_GLOBAL uint64_t *)J.g.read_off;
@@ -1393,26 +1419,37 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
   // 1. member records, then their list entries A = (id, first column,
   // second column, first entry) and kept bits kb; a record without a list
   // slot takes them from the graph (flags give the kept entries)
-  int32_t v[R], rec[R];
+  // Every lane loads (a lane past the component member 0's record, a record
+  // without a slot list entry 0), so that each round's loads are issued
+  // together, without branches
+  int32_t v[R], rec[R], vl[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int i = tid + u * BLOCK;
-    v[u] = 0x7FFFFFFF;
-    rec[u] = kNoSlot;
-    if (i < q) {
-      const i32x2 m = mem[i];
-      v[u] = m.x;
-      rec[u] = m.y;
-    }
+    const i32x2 m = mem[i < q ? i : 0];
+    vl[u] = m.x;
+    v[u] = i < q ? m.x : 0x7FFFFFFF;
+    rec[u] = i < q ? m.y : kNoSlot;
   }
+  // list entries, and the read lengths and store offsets in the same round
   i32x4 A[R];
   uint32_t kb[R];
+  i32x4 Bq[R];
+  i32x2 Cq[R];
+  uint64_t ro[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    A[u] = i32x4{v[u], -1, -1, 0};
+    // (a record without a slot gets its entry from the graph below)
+    A[u] = la[rec[u] != kNoSlot ? rec[u] & kNoSlot : 0];
+    const uint32_t len = glen[vl[u]];
+    const uint64_t off = goff[vl[u]];
     kb[u] = (uint32_t)rec[u] >> 30;
-    if (rec[u] != kNoSlot) A[u] = la[rec[u] & kNoSlot];
+    Bq[u] = i32x4{(int32_t)len, 0, 0, 0};
+    Cq[u] = i32x2{0, 0};
+    ro[u] = off;
   }
+  // the contig record's label and bin, loaded now and stored at the end
+  const CompRec cr = comp_rec(J.parts, e.c, e.rank);
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int i = tid + u * BLOCK;
@@ -1420,26 +1457,17 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
       const int32_t x = v[u];
       kb[u] = ((uint32_t)J.flags[x] >> 1) & 3u;
       const int32_t b = J.g.row_ptr[x];
-      A[u].w = b;
+      A[u] = i32x4{x, -1, -1, b};
       if (kb[u] & 1u) A[u].y = J.g.col[b];
       if (kb[u] & 2u) A[u].z = J.g.col[b + 1];
     }
   }
-  // then the read lengths and store offsets and the kept entries' strand
-  // bits, overlaps (or pre) and post: Bq = (length, ov of entry 0, ov of
-  // entry 1, strands), Cq = post of both, ro = store offset
-  i32x4 Bq[R];
-  i32x2 Cq[R];
-  uint64_t ro[R];
+  // then the kept entries' strand bits, overlaps (or pre) and post: Bq =
+  // (length, ov of entry 0, ov of entry 1, strands), Cq = post of both
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    Bq[u] = i32x4{0, 0, 0, 0};
-    Cq[u] = i32x2{0, 0};
-    ro[u] = 0;
     if (tid + u * BLOCK >= q) continue;
     const int32_t b = A[u].w;
-    Bq[u].x = (int32_t)glen[v[u]];
-    ro[u] = goff[v[u]];
     if (kb[u] & 1u) {
       Bq[u].y = (int32_t)gov[b];
       Bq[u].w = gstr[b];
@@ -1534,7 +1562,7 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
   CG_GLOBAL int32_t *lrp = (CG_GLOBAL int32_t *)J.local.loc_row_ptr;
   CG_GLOBAL int32_t *lcol = (CG_GLOBAL int32_t *)J.local.loc_col;
   CG_GLOBAL int32_t *leid = (CG_GLOBAL int32_t *)J.local.loc_eid;
-  const int32_t estart = J.s.estart[c];
+  const int32_t estart = e.estart;
   int32_t carry = 0;
   for (int base = 0; base < q; base += BLOCK) {
     const int i = base + tid;
@@ -1561,7 +1589,7 @@ __device__ __forceinline__ void iw_component(const BJob &J, int c, int q, int st
     }
     carry += tot;
   }
-  walk_chain<BLOCK, CAP, true>(c, q, st, w, J.g, J.parts, J.local.perm, J.out, J.s, sh_scan);
+  walk_chain<BLOCK, CAP, true>(cr, q, st, w, J.g, J.local.perm, J.out, J.s, sh_scan);
 }
 
 // 6a. components of at most kWalkTinyCap reads (the queue's tail): one wave
@@ -1575,13 +1603,17 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_tiny(BatchDev 
   __shared__ uint8_t s_es[2 * kWalkTinyCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 3), hi = ld_const(B.wq_meta, 0);
-  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
-    const int4 d = wq_at(B, x);
-    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
-    const int st = __builtin_amdgcn_readfirstlane(d.w);
-    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+  // each round's entry is fetched while the previous round's component runs
+  int32_t x = wq_entry(lo, hi, 0);
+  WqE nx{};
+  if (x >= 0) nx = wq_get(B, x);
+  for (int32_t r = 1; x >= 0; ++r) {
+    const WqE e = nx;
+    x = wq_entry(lo, hi, r);
+    if (x >= 0) nx = wq_get(B, x);
+    const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-    iw_component<kWalkSmallBlock, kWalkTinyCap>(J, c, q, st, w, sh_scan);
+    iw_component<kWalkSmallBlock, kWalkTinyCap>(J, e, w, sh_scan);
   }
 }
 
@@ -1594,13 +1626,17 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
   __shared__ uint8_t s_es[2 * kWalkSmallCap];
   __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 1), hi = ld_const(B.wq_meta, 3);
-  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
-    const int4 d = wq_at(B, x);
-    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
-    const int st = __builtin_amdgcn_readfirstlane(d.w);
-    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+  // each round's entry is fetched while the previous round's component runs
+  int32_t x = wq_entry(lo, hi, 0);
+  WqE nx{};
+  if (x >= 0) nx = wq_get(B, x);
+  for (int32_t r = 1; x >= 0; ++r) {
+    const WqE e = nx;
+    x = wq_entry(lo, hi, r);
+    if (x >= 0) nx = wq_get(B, x);
+    const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-    iw_component<kWalkSmallBlock, kWalkSmallCap>(J, c, q, st, w, sh_scan);
+    iw_component<kWalkSmallBlock, kWalkSmallCap>(J, e, w, sh_scan);
   }
 }
 
@@ -1614,13 +1650,17 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
   __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 1);
-  for (int32_t r = 0, x; (x = wq_entry(lo, hi, r)) >= 0; ++r) {
-    const int4 d = wq_at(B, x);
-    const int c = __builtin_amdgcn_readfirstlane(d.y), q = __builtin_amdgcn_readfirstlane(d.z);
-    const int st = __builtin_amdgcn_readfirstlane(d.w);
-    const BJob J = job_at(B.jobs, __builtin_amdgcn_readfirstlane(d.x));
+  // each round's entry is fetched while the previous round's component runs
+  int32_t x = wq_entry(lo, hi, 0);
+  WqE nx{};
+  if (x >= 0) nx = wq_get(B, x);
+  for (int32_t r = 1; x >= 0; ++r) {
+    const WqE e = nx;
+    x = wq_entry(lo, hi, r);
+    if (x >= 0) nx = wq_get(B, x);
+    const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-    iw_component<kWalkBlock, kWalkCap>(J, c, q, st, w, sh_scan);
+    iw_component<kWalkBlock, kWalkCap>(J, e, w, sh_scan);
   }
 }
 
@@ -1954,7 +1994,7 @@ static int plan_sizes(int32_t n_jobs, const cg_job *jobs, int vertex_tile, Plan 
   // kTailChunkPieces (one partial chunk per job)
   P->sum_chunks += (sum_n / 16 + max_n) / kTailChunkPieces + n_jobs + 1;
   P->o_cjob = take(sizeof(int32_t) * (size_t)(sum_n > 0 ? sum_n : 1));
-  P->o_wq = take(sizeof(int4) * (size_t)(sum_n > 0 ? sum_n : 1));
+  P->o_wq = take(sizeof(WqE) * (size_t)(sum_n > 0 ? sum_n : 1));
   P->o_wqh = take(sizeof(int32_t) * kWqBuckets);
   P->o_wqc = take(sizeof(int32_t) * kWqBuckets);
   P->o_wqm = take(sizeof(int32_t) * 8);
@@ -2046,7 +2086,7 @@ static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
   d.chunk_base = (int32_t *)(mem + P.o_hbase);
   d.chunk_cp = (int32_t *)(mem + P.o_ccp);
   d.job_cnt = (int2 *)(mem + P.o_jcnt);
-  d.wq = (int4 *)(mem + P.o_wq);
+  d.wq = (WqE *)(mem + P.o_wq);
   d.wq_hist = (int32_t *)(mem + P.o_wqh);
   d.wq_cur = (int32_t *)(mem + P.o_wqc);
   d.wq_meta = (int32_t *)(mem + P.o_wqm);
