@@ -417,9 +417,9 @@ def main():
             "components": pick(lambda k: k.startswith("k_cc") or k == "kb_mask_cc"),
             "partition": pick(lambda k: k.startswith("k_part") or k.startswith("kb_weight")
                               or k in ("kb_lpt", "kb_tables", "kb_wq_place")),
-            "induce": pick(lambda k: k.startswith("k_ind") or k == "kb_induce"),
+            "induce": pick(lambda k: k.startswith("k_ind")),
             # the batched form induces and walks components of up to 1024
-            # reads in one pass
+            # reads in one pass (and induces the larger ones in it)
             "induce_walk": pick(lambda k: k.startswith("kb_induce_walk")),
             "assemble": pick(lambda k: k.startswith("k_asm") or k.startswith("kb_walk")
                              or k in ("kb_offsets", "kb_copy")),
@@ -464,7 +464,6 @@ def main():
     dom_launches, dom_ms = rkern[dom]
     dom_avg_us = 1e3 * dom_ms / dom_launches
     dom_map = {"kb_copy": ["k_asm_copy"], "kb_walk": ["k_asm_walk"], "kb_lpt": ["k_part_lpt"],
-               "kb_induce": ["k_ind_local", "k_ind_rows"],
                "kb_induce_walk": ["k_ind_local", "k_ind_rows", "k_asm_walk"],
                "kb_induce_walk_small": ["k_ind_local", "k_ind_rows", "k_asm_walk"],
                "kb_offsets": ["k_asm_offsets"]}

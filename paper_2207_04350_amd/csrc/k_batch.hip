@@ -1641,7 +1641,12 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
 }
 
 // 6c. components of kWalkSmallCap + 1 .. kWalkCap reads: one workgroup each,
-// both steps in one pass
+// both steps in one pass; and, first (the queue's head, largest first), the
+// induced subgraph of each component above kWalkCap reads, with the block
+// sort in scratch (its walk, whose arrays reuse the tile lists' memory,
+// waits for the next launch)
+static_assert(kIndBlock == kWalkBlock, "one workgroup shape for both components' steps");
+static_assert(kIndLocalCap <= 2 * kWalkCap, "the induce step's sort buffer is the walk's nxt array");
 __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
@@ -1649,29 +1654,26 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
   __shared__ uint64_t s_roff[kWalkCap];
   __shared__ uint8_t s_es[2 * kWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
-  const int32_t lo = ld_const(B.wq_meta, 2), hi = ld_const(B.wq_meta, 1);
+  const int32_t hi = ld_const(B.wq_meta, 1);
   // each round's entry is fetched while the previous round's component runs
-  int32_t x = wq_entry(lo, hi, 0);
+  int32_t x = wq_entry(0, hi, 0);
   WqE nx{};
   if (x >= 0) nx = wq_get(B, x);
   for (int32_t r = 1; x >= 0; ++r) {
     const WqE e = nx;
-    x = wq_entry(lo, hi, r);
+    x = wq_entry(0, hi, r);
     if (x >= 0) nx = wq_get(B, x);
+    if (e.q > kWalkCap) {
+      __syncthreads();  // the previous round's LDS is free
+      induce_listed<kIndBlock, kIndLocalCap>(B, make_int4(e.job, e.c, e.q, e.st), s_nxt,
+                                             (int32_t *)sh_scan);
+      __syncthreads();
+      continue;
+    }
     const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
     iw_component<kWalkBlock, kWalkCap>(J, e, w, sh_scan);
   }
-}
-
-// 6d. components above kWalkCap reads (the queue's head, largest first):
-// induced subgraph with the block sort in scratch
-__global__ __launch_bounds__(kIndBlock) void kb_induce(BatchDev B) {
-  __shared__ int32_t a[kIndLocalCap];
-  __shared__ int32_t sh_scan[kIndBlock / kWave + 1];
-  const int32_t hi = ld_const(B.wq_meta, 2);
-  for (int32_t r = 0, x; (x = wq_entry(0, hi, r)) >= 0; ++r)
-    induce_listed<kIndBlock, kIndLocalCap>(B, wq_at(B, x), a, sh_scan);
 }
 
 // 7. their walks, with the walk's arrays in scratch
@@ -1864,7 +1866,7 @@ struct cg_batch {
   // their grids stay within it, so every workgroup of the snake order runs
   // from the start (a workgroup that waits for a free slot starts its whole
   // share late)
-  int res_iw_tiny, res_iw_small, res_iw, res_induce, res_walk;
+  int res_iw_tiny, res_iw_small, res_iw, res_walk;
   // jobs too large for one workgroup's components pass: they run through the
   // single-graph kernels (grid-wide) ahead of the batched launches
   std::vector<cg_job> ext_jobs;
@@ -2156,14 +2158,13 @@ static int batch_alloc(cg_ctx *ctx, const cg_batch_params &prm, size_t bytes, cg
   b->mem = nullptr;
   b->mem_bytes = bytes > 0 ? bytes : 256;
   {
-    int dev = 0, cus = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0;
+    int dev = 0, cus = 0, k0 = 0, k1 = 0, k3 = 0, k4 = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k0, kb_induce_walk_tiny, kWalkSmallBlock,
                                                      0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k1, kb_induce_walk_small, kWalkSmallBlock,
                                                      0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&k2, kb_induce, kIndBlock, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k3, kb_induce_walk, kWalkBlock, 0) !=
             hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&k4, kb_walk, kWalkBlock, 0) != hipSuccess) {
@@ -2172,7 +2173,6 @@ static int batch_alloc(cg_ctx *ctx, const cg_batch_params &prm, size_t bytes, cg
     }
     b->res_iw_tiny = k0 * cus;
     b->res_iw_small = k1 * cus;
-    b->res_induce = k2 * cus;
     b->res_iw = k3 * cus;
     b->res_walk = k4 * cus;
   }
@@ -2300,9 +2300,9 @@ int cg_batch_run(cg_batch *b, void *stream) {
   CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
   CG_LAUNCH(ctx, kb_wq_place, dim3(128), dim3(kWqBlock), st, B);
   auto capped = [](int want, int fit) { return dim3((unsigned)(fit > 0 && fit < want ? fit : want)); };
-  // components above kWalkCap reads in two passes (sort and walk arrays in
-  // scratch), the others in one
-  CG_LAUNCH(ctx, kb_induce, capped(PB, b->res_induce), dim3(kIndBlock), st, B);
+  // components above kWalkCap reads in two passes (the induce step with the
+  // next ones, the walk after the last pass that reads the tile lists, since
+  // its arrays take their memory), the others in one
   CG_LAUNCH(ctx, kb_induce_walk, capped(PB, b->res_iw), dim3(kWalkBlock), st, B);
   CG_LAUNCH(ctx, kb_induce_walk_small, capped(4 * PB, b->res_iw_small), dim3(kWalkSmallBlock), st,
             B);
