@@ -1636,7 +1636,9 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
     if (x >= 0) nx = wq_get(B, x);
     const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-    iw_component<kWalkSmallBlock, kWalkSmallCap>(J, e, w, sh_scan);
+    // one member per lane up to kWave reads (a uniform branch), two above
+    if (e.q <= kWave) iw_component<kWalkSmallBlock, kWave>(J, e, w, sh_scan);
+    else iw_component<kWalkSmallBlock, kWalkSmallCap>(J, e, w, sh_scan);
   }
 }
 
