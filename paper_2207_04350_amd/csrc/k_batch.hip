@@ -113,7 +113,10 @@ __device__ __forceinline__ int job_of(const int32_t *__restrict__ base, int n_jo
 // bandwidth while all jobs stream at once): degree from row_ptr, the
 // "listed" (degree 1 or 2, the only reads that can keep an entry) and
 // "branch" (degree >= 3) bitmaps of the job, and every listed read with its
-// columns, packed per tile in id order by a block scan.
+// columns, packed per tile in id order by a block scan.  It also stores every
+// read's flags, label and label_comp as they are for a read the components
+// step leaves alone (the branch bit, its own id, -1), so that step, one
+// workgroup per job, stores only what its listed reads change.
 // ---------------------------------------------------------------------------
 struct MaskTile {
   const int32_t *row_ptr;
@@ -122,6 +125,9 @@ struct MaskTile {
                      // (id, first column, second column or -1, first entry)
   uint32_t *bits;    // the job's bitmaps: W listed words, then W branch words
   int2 *tile_cnt;    // (listed reads, branch reads) of this tile
+  uint8_t *flags;    // the job's outputs, given their defaults here (below)
+  int32_t *label;
+  int32_t *label_comp;
   int32_t n, v0, W, pad_;
 };
 static_assert(sizeof(MaskTile) % 8 == 0, "tile descriptors are copied in 8-byte words");
@@ -209,6 +215,32 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_tiles(const MaskTile *__
       bits[D.W + w] = bb;
     }
   }
+  // the defaults of every read (16-byte stores of whole groups)
+  {
+    CG_GLOBAL uint8_t *fl = (CG_GLOBAL uint8_t *)D.flags;
+    CG_GLOBAL int32_t *lab = (CG_GLOBAL int32_t *)D.label;
+    CG_GLOBAL int32_t *lc = (CG_GLOBAL int32_t *)D.label_comp;
+#pragma unroll
+    for (int g = 0; g < kMaskGroups; ++g) {
+      const int32_t v = v0[g];
+      uint32_t f = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f |= (dg[4 * g + i] >= 3 ? 1u : 0u) << (8 * i);
+      if (v + 3 < n) {
+        *(CG_GLOBAL uint32_t *)(fl + v) = f;
+        *(CG_GLOBAL i32x4 *)(lab + v) = i32x4{v, v + 1, v + 2, v + 3};
+        *(CG_GLOBAL i32x4 *)(lc + v) = i32x4{-1, -1, -1, -1};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (v + i < n) {
+            fl[v + i] = (uint8_t)(f >> (8 * i));
+            lab[v + i] = v + i;
+            lc[v + i] = -1;
+          }
+      }
+    }
+  }
   // listed reads packed in id order: group 0 of every thread precedes group
   // 1, so one scan of (listed, branch) counts of both groups, 16-bit fields
   // (a tile holds fewer than 2^16 reads), gives every position
@@ -263,8 +295,9 @@ __global__ __launch_bounds__(kMaskThreads) void kb_mask_tiles(const MaskTile *__
 //     its component's smallest id): a read first points at its smallest kept
 //     neighbour below it, and only an edge that leaves open is hooked
 //  E  roots and per-root counts (4 per read + 1 per path end)
-//  H  flags, labels and label_comp of every read as 16-byte stores of whole
-//     words (what a read of degree 1-2 changes is stored after)
+//  H  flags, labels and label_comp: what a read of degree 1-2 changes of the
+//     defaults the tile pass stored (when one-read components are eligible,
+//     every read's, with their numbering)
 //  F  eligible components in label order (one scan over the threads' runs)
 //     and each component's members grouped for the induce step
 // The listed reads' state (entry, forest/counter, hook/root) is in LDS, or
@@ -582,68 +615,23 @@ __device__ __forceinline__ int32_t mc_sweep_table(int32_t n, int32_t min_reads, 
   return cbase;
 }
 
-// H (for jobs whose listed reads are in LDS, after F and G): flags, labels
-// and label_comp of every read, four consecutive reads per lane (16-byte
-// stores, consecutive across a wave); reads of degree 1-2 look up their
-// state: kept bits, a member's label (its root's id), a numbered root's
-// component.  All loads of the kernel are done by now: gfx9 counts stores
-// and loads in one counter, so a load behind these stores would wait for
-// them.
-__device__ __forceinline__ void mc_write_lds(int32_t n, const McOut &O, const uint32_t *lw,
-                                             const uint32_t *bw, const int32_t *wp,
-                                             const uint32_t *s_lid, const int32_t *s_b) {
-  constexpr int R = 2;  // groups of four reads per thread per round, their lookups together
-  for (int32_t base = 0; base < n; base += 4 * kMcBlock * R) {
-    int32_t v4[R];
-    uint32_t fw[R];
-    int32_t lab[R][4], lcx[R][4];
-#pragma unroll
-    for (int g = 0; g < R; ++g) {
-      v4[g] = base + 4 * ((int32_t)threadIdx.x + g * kMcBlock);
-      const int w = v4[g] < n ? v4[g] >> 5 : 0, sh = v4[g] & 31;
-      const uint32_t lword = lw[w];
-      const uint32_t ln = v4[g] < n ? (lword >> sh) & 15u : 0u;
-      fw[g] = (((bw[w] >> sh) & 15u) * 0x00204081u) & 0x01010101u;  // branch bit i to byte i
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lab[g][i] = v4[g] + i;
-        lcx[g][i] = -1;
-      }
-      if (ln) {
-        int32_t l = wp[w] + __popc(lword & ((1u << sh) - 1u));
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (!((ln >> i) & 1u)) continue;
-          const uint32_t kept = s_lid[l] >> 30;
-          const int32_t rt = s_b[l];
-          if (kept) {
-            fw[g] |= kept << (8 * i + 1);
-            if (rt < 0) lcx[g][i] = ~rt;
-            else if (rt != l) lab[g][i] = (int32_t)(s_lid[rt] & kIdMask);
-          }
-          ++l;
-        }
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < R; ++g) {
-      const int32_t v = v4[g];
-      if (v >= n) continue;
-      if (v + 3 < n) {
-        *(CG_GLOBAL uint32_t *)(O.flags + v) = fw[g];
-        *(CG_GLOBAL i32x4 *)(O.label + v) = i32x4{lab[g][0], lab[g][1], lab[g][2], lab[g][3]};
-        *(CG_GLOBAL i32x4 *)(O.label_comp + v) =
-            i32x4{lcx[g][0], lcx[g][1], lcx[g][2], lcx[g][3]};
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (v + i < n) {
-            O.flags[v + i] = (uint8_t)(fw[g] >> (8 * i));
-            O.label[v + i] = lab[g][i];
-            O.label_comp[v + i] = lcx[g][i];
-          }
-      }
-    }
+// H (for jobs whose listed reads are in LDS, after F and G): what the
+// listed reads change of the defaults the tile pass stored (the branch bit,
+// own id, -1): kept bits, a member's label (its root's id), a numbered
+// root's component.  Scattered stores of the listed reads only; all loads of
+// the kernel are done by now (gfx9 counts stores and loads in one counter,
+// so a load behind these stores would wait for them).
+__device__ __forceinline__ void mc_write_listed(int32_t L, const McOut &O, const uint32_t *s_lid,
+                                                const int32_t *s_b) {
+  for (int32_t l = threadIdx.x; l < L; l += kMcBlock) {
+    const uint32_t x = s_lid[l];
+    const uint32_t kept = x >> 30;
+    if (!kept) continue;
+    const int32_t v = (int32_t)(x & kIdMask);
+    const int32_t rt = s_b[l];
+    O.flags[v] = (uint8_t)(kept << 1);
+    if (rt < 0) O.label_comp[v] = ~rt;
+    else if (rt != l) O.label[v] = (int32_t)(s_lid[rt] & kIdMask);
   }
 }
 
@@ -712,36 +700,8 @@ __device__ __forceinline__ int32_t mc_components(
     if (kept) mc_add(A.a + A.b[l], 4 + (__popc(kept) == 1 ? 1 : 0));
   }
   barrier();
-  // H. every read of the thread's words: branch bits, label = own id,
-  // label_comp = -1 (16-byte stores; the job's last word read by read)
-  for (int32_t w = w0; w < w1; ++w) {
-    const int32_t v0 = w << 5;
-    const uint32_t br = bw[w];
-    if (v0 + 32 <= n) {
-#pragma unroll
-      for (int k = 0; k < 8; k += 4) {
-        // four reads per flag word: branch bit i of the nibble to byte i
-        const uint32_t f0 = (((br >> (4 * k)) & 15u) * 0x00204081u) & 0x01010101u;
-        const uint32_t f1 = (((br >> (4 * k + 4)) & 15u) * 0x00204081u) & 0x01010101u;
-        const uint32_t f2 = (((br >> (4 * k + 8)) & 15u) * 0x00204081u) & 0x01010101u;
-        const uint32_t f3 = (((br >> (4 * k + 12)) & 15u) * 0x00204081u) & 0x01010101u;
-        *(CG_GLOBAL i32x4 *)(O.flags + v0 + 4 * k) =
-            i32x4{(int32_t)f0, (int32_t)f1, (int32_t)f2, (int32_t)f3};
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int32_t v = v0 + 4 * k;
-        *(CG_GLOBAL i32x4 *)(O.label + v) = i32x4{v, v + 1, v + 2, v + 3};
-        *(CG_GLOBAL i32x4 *)(O.label_comp + v) = i32x4{-1, -1, -1, -1};
-      }
-    } else {
-      for (int32_t v = v0; v < n; ++v) {
-        O.flags[v] = (uint8_t)((br >> (v - v0)) & 1u);
-        O.label[v] = v;
-        O.label_comp[v] = -1;
-      }
-    }
-  }
+  // H. every read's flags, label and label_comp hold their defaults (the
+  // branch bit, own id, -1) from the tile pass; F and G store the changes
   // F. eligible components in label order, numbered from the threads' runs
   // (one scan), member cursors in `a`, ~component in `b` of a numbered root
   int32_t n_comp;
@@ -1061,7 +1021,7 @@ __global__ __launch_bounds__(kMcBlock) void kb_mask_cc(BatchDev B) {
       n_comp = mc_sweep_table<true>(n, J.min_reads, O, s_lw, s_bw, s_wp,
                                     McState<true>{s_lid, s_b, s_a}, sh64);
     else
-      mc_write_lds(n, O, s_lw, s_bw, s_wp, s_lid, s_b);
+      mc_write_listed(L, O, s_lid, s_b);
   } else {
     n_comp = mc_components<false>(J, O,
                                   McArr<false>{(CG_GLOBAL uint32_t *)J.s.lidx,
@@ -2066,8 +2026,8 @@ static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
     // in its fill scratch (both reused by later steps)
     for (int32_t v0 = 0; !h.external && v0 < J.g.n; v0 += kMaskTile)
       b->h_mtiles.push_back(MaskTile{J.g.row_ptr, J.g.col, (int4 *)h.s.walk,
-                                     (uint32_t *)h.s.fill, d_mtcnt + n_mt++, J.g.n, v0,
-                                     (J.g.n + 31) / 32, 0});
+                                     (uint32_t *)h.s.fill, d_mtcnt + n_mt++, J.flags, J.label,
+                                     J.parts.label_comp, J.g.n, v0, (J.g.n + 31) / 32, 0});
     if (h.external) {
       b->ext_jobs.push_back(J);
       b->ext_s.push_back(h.s);
