@@ -282,6 +282,89 @@ __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
   }
 }
 
+// Stable sort of a[0, n) by bits 16 and up of its 32-bit keys, whose low 16
+// bits are each key's index (the input is in index order), so the result is
+// the order of the whole keys.  LSD radix sort over `passes` 8-bit digits
+// from bit 16.  Each wave takes a contiguous run of keys, 64 per round in
+// order: the lanes holding the same digit are found by eight ballots, and a
+// key's rank is the wave's running count of its digit (in LDS) plus the
+// lanes below it with the same digit.  One block scan over the counts in
+// (digit, wave) order gives every digit's start for every wave.  tmp holds
+// n keys, cnt 256 counters per wave (LDS), sh the block scan's words.
+// n <= kRadixRounds * BLOCK.  Returns the array holding the result (a after
+// an even number of passes, else tmp).
+constexpr int kRadixRounds = 8;
+template <int BLOCK>
+__device__ __forceinline__ uint32_t *radix_sort_hi16(uint32_t *a, uint32_t *tmp, int n, int passes,
+                                                     uint32_t *cnt, uint32_t *sh) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int E = 256 * NW / BLOCK;  // (digit, wave) counters per thread in the scan
+  static_assert(E * BLOCK == 256 * NW, "whole counters per thread");
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int per_w = ((n + NW - 1) / NW + kWave - 1) & ~(kWave - 1);
+  const int rounds = per_w / kWave;  // uniform, at most kRadixRounds
+  const uint64_t below = (1ull << l) - 1ull;
+  uint32_t *my = cnt + w * 256;
+  uint32_t *src = a, *dst = tmp;
+  for (int p = 0; p < passes; ++p) {
+    const int s = 16 + 8 * p;
+    for (int d = l; d < 256; d += kWave) my[d] = 0;
+    uint32_t x[kRadixRounds];
+    int pos[kRadixRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+      x[r] = 0;
+      pos[r] = 0;
+      if (r >= rounds) continue;
+      const int i = w * per_w + r * kWave + l;
+      const bool v = i < n;
+      x[r] = v ? src[i] : 0u;
+      const uint32_t d = (x[r] >> s) & 255u;
+      uint64_t peers = __ballot(v);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(v && bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t c = my[d];  // the digit's count before this round
+      pos[r] = (int)c + __popcll(peers & below);
+      // the lowest lane holding the digit adds the round's keys of it
+      if (v && (peers & below) == 0) my[d] = c + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // every (digit, wave) count to its start: exclusive scan in digit-major
+    // order
+    uint32_t c[E], sum = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = (int)threadIdx.x * E + k;
+      c[k] = cnt[(e % NW) * 256 + e / NW];
+      sum += c[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<uint32_t, BLOCK>(sum, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = (int)threadIdx.x * E + k;
+      cnt[(e % NW) * 256 + e / NW] = ex;
+      ex += c[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+      if (r >= rounds) continue;
+      const int i = w * per_w + r * kWave + l;
+      if (i < n) dst[my[(x[r] >> s) & 255u] + pos[r]] = x[r];
+    }
+    __syncthreads();
+    uint32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
 // number of elements of the sorted array a[0..len) that are < x
 __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int len, uint64_t x) {
   int lo = 0, hi = len;
@@ -312,6 +395,13 @@ __device__ __forceinline__ uint32_t wave_next_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x130, 0xF, 0xF, false);
 }
 
+// weight of the t-th item in LPT order, from the sorted keys (32-bit keys
+// (2^16-1 - w) << 16 | index, or 64-bit (2^32-1 - w) << 32 | index)
+__device__ __forceinline__ uint32_t lpt_item_weight(const uint32_t *srt, const uint64_t *keys,
+                                                    bool k32, int t) {
+  return 0xFFFFFFFFu - (k32 ? 0xFFFF0000u | (srt[t] >> 16) : (uint32_t)(keys[t] >> 32));
+}
+
 // Bin keys are (load << 16) | bin: ascending key order is ascending
 // (load, bin), i.e. the least loaded bin with the lowest index first.
 constexpr int kBinBits = 16;
@@ -335,6 +425,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         const uint8_t *__restrict__ comp_kind = nullptr,
                                         int32_t *__restrict__ comp_estart = nullptr) {
   __shared__ uint64_t win[kWave];
+  __shared__ uint32_t s_cnt[BLOCK >= 1024 ? BLOCK / kWave * 256 : 1];  // the radix sorts' counters
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
   __shared__ int64_t sh_scan64[BLOCK / kWave + 1];
   __shared__ unsigned long long s_wsum;
@@ -388,7 +479,16 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
       keys[i] = i < nc ? ((uint64_t)(0xFFFFFFFFu - (uint32_t)w) << 32) | (uint32_t)i : ~0ull;
   }
   __syncthreads();
-  if (k32)
+  // the keys in LPT order: with a 1024-thread workgroup, radix passes over
+  // the weight's bytes (one when every weight is below 256); else (fewer
+  // waves, whose rounds of the radix sort run one after another, wide keys,
+  // or more keys than the radix sort holds) a bitonic sort
+  constexpr bool kRadix = BLOCK >= 1024;
+  const uint32_t *srt = keys32;
+  if (kRadix && k32 && nc <= kRadixRounds * BLOCK)
+    srt = radix_sort_hi16<BLOCK>(keys32, keys32 + N2, nc, s_wmax < 256u ? 1 : 2, s_cnt,
+                                 reinterpret_cast<uint32_t *>(sh_scan));
+  else if (k32)
     bitonic_sort(keys32, N2);
   else
     bitonic_sort(keys, N2);
@@ -410,6 +510,37 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   while ((1 << kb) < P) ++kb;
   const bool narrow = kb <= 16 && s_wsum + 1 < (1ull << (32 - kb));
   int i0 = 0;
+  if (!single_window && nc > P) {
+    // The first round in one pass.  Every weight is at least 1, so item t
+    // (t < P) finds bins 0..t-1 loaded and bin t empty, the least loaded one
+    // with the lowest index: items 0..P-1 go to bins 0..P-1.  The weights do
+    // not increase along the items, so in the bin list sorted by (load, bin)
+    // bin t comes after the bins of smaller load (those past its run of
+    // equal weights) and in bin order within its run.
+    for (int t = tid; t < P; t += blockDim.x) {
+      const uint32_t wt = lpt_item_weight(srt, keys, k32, t);
+      int lo = 0, hi = t;  // the run's first item: the first of weight <= wt
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lpt_item_weight(srt, keys, k32, mid) > wt) lo = mid + 1;
+        else hi = mid;
+      }
+      const int g0 = lo;
+      lo = t;
+      hi = P;  // one past the run's last item (within the first round)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lpt_item_weight(srt, keys, k32, mid) < wt) hi = mid;
+        else lo = mid + 1;
+      }
+      const int pos = (P - lo) + (t - g0);
+      binA[pos] = narrow ? (uint64_t)(((uint32_t)wt << kb) | (uint32_t)t)
+                         : ((uint64_t)wt << kBinBits) | (uint64_t)t;
+      bin_of[k32 ? (srt[t] & 0xFFFFu) : (uint32_t)keys[t]] = t;
+    }
+    i0 = P;
+  }
+  __syncthreads();  // (outside the branch: inside it, the compiler kept a stack frame)
   while (i0 < nc) {
     const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
     if (tid < kWave && narrow) {
@@ -421,7 +552,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         uint64_t item = 0;
         if (l < cnt) {
           const int at = i0 + base + l;
-          item = k32 ? ((uint64_t)(0xFFFF0000u | (keys32[at] >> 16)) << 32) | (keys32[at] & 0xFFFFu)
+          item = k32 ? ((uint64_t)(0xFFFF0000u | (srt[at] >> 16)) << 32) | (srt[at] & 0xFFFFu)
                      : keys[at];
         }
         int32_t mine = 0;  // bin of item l
@@ -500,7 +631,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         uint64_t item = 0;
         if (l < cnt) {
           const int at = i0 + base + l;
-          item = k32 ? ((uint64_t)(0xFFFF0000u | (keys32[at] >> 16)) << 32) | (keys32[at] & 0xFFFFu)
+          item = k32 ? ((uint64_t)(0xFFFF0000u | (srt[at] >> 16)) << 32) | (srt[at] & 0xFFFFu)
                      : keys[at];
         }
         int32_t mine = 0;  // bin of item l, kept in lane l until the batch ends
@@ -563,14 +694,20 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
   for (int i = tid; i < nc; i += blockDim.x)
     atomicAdd((unsigned long long *)binB + bin_of[i], (unsigned long long)comp_size[i]);
   __syncthreads();
-  if (b32)
+  // (bin, label) order: radix passes over the bin's bytes (one up to 256
+  // bins) as above, else a bitonic sort
+  const uint32_t *srt2 = keys32;
+  if (kRadix && b32 && nc <= kRadixRounds * BLOCK)
+    srt2 = radix_sort_hi16<BLOCK>(keys32, keys32 + N2, nc, P <= 256 ? 1 : 2, s_cnt,
+                                  reinterpret_cast<uint32_t *>(sh_scan));
+  else if (b32)
     bitonic_sort(keys32, N2);
   else
     bitonic_sort(keys, N2);
   int carry = 0, ecarry = 0;
   for (int base = 0; base < nc; base += BLOCK) {
     const int i = base + tid;
-    const uint32_t c = i < nc ? (b32 ? keys32[i] & 0xFFFFu : (uint32_t)keys[i]) : 0u;
+    const uint32_t c = i < nc ? (b32 ? srt2[i] & 0xFFFFu : (uint32_t)keys[i]) : 0u;
     const int32_t sz = i < nc ? comp_size[c] : 0;
     if (comp_estart) {
       // reads and local entries in one scan: (reads << 32) | entries, each
