@@ -3,7 +3,9 @@ form for at most 64 bins): one key per lane, single steps, rounds of equal
 weights and prefix rounds, re-sorted by the same 64-lane bitonic network.
 It must place every component exactly as sequential LPT does (Section 4.3:
 components by decreasing weight, each to the least loaded bin, ties to the
-lower bin index).  The GPU parity tests check the kernels themselves."""
+lower bin index).  Two more models: the first round of LPT over more than
+64 bins built in one pass, and the radix sort of the 1024-thread partition
+kernel.  The GPU parity tests check the kernels themselves."""
 import numpy as np
 
 W = 64     # lanes of a wave: the bins of one window
@@ -134,3 +136,97 @@ def test_lane_model_matches_sequential_lpt():
         assert lpt_emu(ws, P) == lpt_seq(ws, P), (trial, P, n)
     # every kind of step was taken
     assert stats["step"] and stats["eq"] and stats["gen"]
+
+
+def first_round_list(ws_sorted, P):
+    """The sorted (load, bin) list after the first P items, as the partition
+    kernel builds it in one pass for more than 64 bins: item t goes to bin t,
+    and bin t sits after the bins past its run of equal weights, in bin order
+    within the run."""
+    out = [None] * P
+    for t in range(P):
+        wt = ws_sorted[t]
+        g0 = next(g for g in range(t + 1) if ws_sorted[g] == wt)
+        end = next((g for g in range(t, P) if ws_sorted[g] < wt), P)
+        out[(P - end) + (t - g0)] = (wt, t)
+    return out
+
+
+def test_first_round_in_one_pass_matches_lpt():
+    rng = np.random.default_rng(3)
+    for P in (65, 100, 1024):
+        for kind in ("uniform", "ties", "ones", "heavy"):
+            m = P + int(rng.integers(1, 2 * P))
+            if kind == "uniform":
+                w = rng.integers(1, 10**6, m)
+            elif kind == "ties":
+                w = rng.integers(1, 6, m)
+            elif kind == "ones":
+                w = np.ones(m, dtype=int)
+            else:
+                w = (rng.pareto(1.1, m) * 10 + 1).astype(int)
+            ws = sorted(w.tolist(), reverse=True)
+            # sequential LPT over the first P items
+            load = [0] * P
+            for t in range(P):
+                b = min(range(P), key=lambda b: (load[b], b))
+                assert b == t, (P, kind, t)
+                load[b] += ws[t]
+            assert first_round_list(ws, P) == sorted((load[b], b) for b in range(P)), (P, kind)
+
+
+def radix_hi16_model(keys, passes, nw):
+    """The radix sort of the 1024-thread partition kernel, lane by lane: each
+    of nw waves ranks 64 keys per round by digit (the lanes holding the same
+    digit found by eight ballots) against its running count per digit, one
+    scan over (digit, wave) counts in digit-major order gives the starts."""
+    n = len(keys)
+    per_w = (-(-n // nw) + 63) // 64 * 64
+    src = list(keys)
+    for p in range(passes):
+        s = 16 + 8 * p
+        cnt = [[0] * 256 for _ in range(nw)]
+        rank = {}
+        for w in range(nw):
+            for r in range(per_w // 64):
+                idx = [w * per_w + r * 64 + l for l in range(64)]
+                valid = [i < n for i in idx]
+                d = [(src[i] >> s) & 255 if v else 0 for i, v in zip(idx, valid)]
+                ball = lambda pred: sum(1 << l for l in range(64) if pred(l))
+                peers0 = ball(lambda l: valid[l])
+                peers = []
+                for l in range(64):
+                    pm = peers0
+                    for b in range(8):
+                        m = ball(lambda k: valid[k] and (d[k] >> b) & 1)
+                        pm &= m if (d[l] >> b) & 1 else ~m
+                    peers.append(pm)
+                before = [cnt[w][d[l]] for l in range(64)]
+                for l in range(64):
+                    if valid[l]:
+                        rank[idx[l]] = before[l] + bin(peers[l] & ((1 << l) - 1)).count("1")
+                        if peers[l] & ((1 << l) - 1) == 0:
+                            cnt[w][d[l]] = before[l] + bin(peers[l]).count("1")
+        flat = [cnt[e % nw][e // nw] for e in range(256 * nw)]
+        start, acc = [0] * len(flat), 0
+        for e, c in enumerate(flat):
+            start[e], acc = acc, acc + c
+        dst = [None] * n
+        for i in range(n):
+            w = i // per_w
+            t = start[((src[i] >> s) & 255) * nw + w] + rank[i]
+            assert 0 <= t < n and dst[t] is None
+            dst[t] = src[i]
+        src = dst
+    return src
+
+
+def test_radix_sort_model_is_a_stable_sort():
+    rng = np.random.default_rng(5)
+    for n, nw in ((1, 4), (63, 4), (200, 4), (513, 16), (1500, 16)):
+        for kind in ("small", "uniform", "equal"):
+            hi = {"small": rng.integers(0, 40, n), "uniform": rng.integers(0, 65536, n),
+                  "equal": np.full(n, 9)}[kind]
+            keys = [int(h) << 16 | i for i, h in enumerate(hi)]
+            passes = 1 if hi.max() < 256 else 2
+            assert radix_hi16_model(keys, passes, nw) == sorted(keys), (n, nw, kind)
