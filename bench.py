@@ -519,10 +519,11 @@ def main():
                     "hbm_frac": maskcc_bytes / (maskcc_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
                     if maskcc_ms else None,
                     "cold_median": maskcc(cold_ph), "warm_median": maskcc(warm_ph),
-                    "kernels": "kb_mask_tiles (degrees, bitmaps and the reads of degree 1-2 "
-                               "with their columns, over the whole chip) + kb_mask_cc (one "
-                               "workgroup per graph: kept entries, union-find in LDS, labels, the "
-                               "component table and its members, label_comp of every read)",
+                    "kernels": "kb_mask_tiles (degrees, bitmaps, every read's default flags, "
+                               "label and label_comp, and the reads of degree 1-2 with their "
+                               "columns, over the whole chip) + kb_mask_cc (one workgroup per "
+                               "graph: kept entries, union-find in LDS, the component table and "
+                               "its members, what the reads of degree 1-2 change)",
                     # what the phase's kernels move in all (the calibrated
                     # counters of the committed profile): random lines and the
                     # arrays the later steps need, far above the fused minimum
