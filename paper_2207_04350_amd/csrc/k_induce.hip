@@ -84,6 +84,13 @@ __global__ __launch_bounds__(kScanBlock) void k_ind_rows(
   const int blk = lookback_ticket(sc);
   const int64_t i = (int64_t)blk * kScanBlock + threadIdx.x;
   const int32_t n_e = bin_vptr[P];
+  // the grid covers every read and only the n_e reads of the contigs have
+  // local numbers: blocks past them take no part in the scan (a block looks
+  // back at lower tickets only, and the last block out clears every status)
+  if ((int64_t)blk * kScanBlock > n_e) {
+    lookback_finish(sc, nblocks);
+    return;
+  }
   int32_t v = -1;
   uint32_t f = 0;
   if (i < n_e) {
