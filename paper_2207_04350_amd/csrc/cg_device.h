@@ -424,7 +424,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         unsigned int *status,
                                         const uint8_t *__restrict__ comp_kind = nullptr,
                                         int32_t *__restrict__ comp_estart = nullptr) {
-  __shared__ uint64_t win[kWave];
+  __shared__ uint64_t win[2][kWave];  // a window's raised keys, alternating buffers
   __shared__ uint32_t s_cnt[BLOCK >= 1024 ? BLOCK / kWave * 256 : 1];  // the radix sorts' counters
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
   __shared__ int64_t sh_scan64[BLOCK / kWave + 1];
@@ -541,12 +541,26 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     i0 = P;
   }
   __syncthreads();  // (outside the branch: inside it, the compiler kept a stack frame)
+  // Above 64 bins the windows are pipelined: after a window's steps, wave 0
+  // forms the next window in its lanes as the W least of the raised keys and
+  // the next W keys of the list (a bitonic merge in registers) and goes on,
+  // while the other waves merge the raised keys back into the list.  One
+  // barrier per window; the raised keys alternate between two buffers, so a
+  // window's keys are written while the other waves still merge the last
+  // ones, and the list alternates between binA and binB.
+  uint32_t key32 = 0xFFFFFFFFu;  // wave 0: the window's keys (narrow or wide)
+  uint64_t key64 = ~0ull;
+  if (tid < kWave) {
+    if (narrow) key32 = tid < W ? (uint32_t)binA[tid] : 0xFFFFFFFFu;
+    else key64 = tid < W ? binA[tid] : ~0ull;
+  }
+  int cur = 0;
   while (i0 < nc) {
     const int T = single_window ? nc - i0 : (nc - i0 < W ? nc - i0 : W);
     if (tid < kWave && narrow) {
       const int l = tid;
       const uint32_t bmask = (1u << kb) - 1u;
-      uint32_t key = l < W ? (uint32_t)binA[l] : 0xFFFFFFFFu;
+      uint32_t key = key32;
       for (int base = 0; base < T; base += kWave) {
         const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
         uint64_t item = 0;
@@ -622,10 +636,11 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         }
         if (l < cnt) bin_of[(uint32_t)item] = mine;
       }
-      if (l < W) win[l] = key;
+      if (l < W) win[cur][l] = key;
+      key32 = key;
     } else if (tid < kWave) {
       const int l = tid;
-      uint64_t key = l < W ? binA[l] : ~0ull;
+      uint64_t key = key64;
       for (int base = 0; base < T; base += kWave) {
         const int cnt = __builtin_amdgcn_readfirstlane(T - base < kWave ? T - base : kWave);
         uint64_t item = 0;
@@ -651,33 +666,66 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         }
         if (l < cnt) bin_of[(uint32_t)item] = mine;
       }
-      if (l < W) win[l] = key;
+      if (l < W) win[cur][l] = key;
+      key64 = key;
     }
+    // the window's raised keys are out, and the previous window's merge (by
+    // the other waves, during these steps) is done
     __syncthreads();
     if (single_window) {
-      if (tid < W) binA[tid] = win[tid];
+      if (tid < W) binA[tid] = win[cur][tid];
     } else {
-      // merge the window (sorted) with binA[W..P) (sorted) into binB
-      for (int idx = tid; idx < P; idx += blockDim.x) {
-        uint64_t x;
-        int pos;
-        if (idx < W) {
-          x = win[idx];
-          pos = idx + lower_bound_u64(binA + W, P - W, x);
-        } else {
-          x = binA[idx];
-          pos = (idx - W) + lower_bound_u64(win, W, x);
+      if (tid < kWave) {
+        if (i0 + T < nc) {
+          // the next window: the W (= 64) least of the raised keys and
+          // binA[W..2W), as min(raised key l, binA[2W-1-l]) (a bitonic run
+          // holding exactly those) sorted by the bitonic merge's stages
+          const int l = tid, j = W + (kWave - 1) - l;
+          if (narrow) {
+            const uint32_t b = j < P ? (uint32_t)binA[j] : 0xFFFFFFFFu;
+            uint32_t c = key32 < b ? key32 : b;
+            c = bitonic_lane_step<32>(c, l, kWave);
+            c = bitonic_lane_step<16>(c, l, kWave);
+            c = bitonic_lane_step<8>(c, l, kWave);
+            c = bitonic_lane_step<4>(c, l, kWave);
+            c = bitonic_lane_step<2>(c, l, kWave);
+            key32 = bitonic_lane_step<1>(c, l, kWave);
+          } else {
+            const uint64_t b = j < P ? binA[j] : ~0ull;
+            uint64_t c = key64 < b ? key64 : b;
+            c = bitonic_lane_step<32>(c, l, kWave);
+            c = bitonic_lane_step<16>(c, l, kWave);
+            c = bitonic_lane_step<8>(c, l, kWave);
+            c = bitonic_lane_step<4>(c, l, kWave);
+            c = bitonic_lane_step<2>(c, l, kWave);
+            key64 = bitonic_lane_step<1>(c, l, kWave);
+          }
         }
-        binB[pos] = x;
+      } else {
+        // the other waves: the raised keys (sorted) merged with binA[W..P)
+        // (sorted) into binB
+        const uint64_t *wk = win[cur];
+        for (int idx = tid - kWave; idx < P; idx += (int)blockDim.x - kWave) {
+          uint64_t x;
+          int pos;
+          if (idx < W) {
+            x = wk[idx];
+            pos = idx + lower_bound_u64(binA + W, P - W, x);
+          } else {
+            x = binA[idx];
+            pos = (idx - W) + lower_bound_u64(wk, W, x);
+          }
+          binB[pos] = x;
+        }
       }
-      __syncthreads();
       uint64_t *t = binA;
       binA = binB;
       binB = t;
+      cur ^= 1;
     }
-    __syncthreads();
     i0 += T;
   }
+  __syncthreads();  // the last merge is done: binA holds the final bin list
   // 3. (bin, label) order, read offsets and the reads of each bin; keys
   // (bin << 16) | i in 32 bits when bin and index fit 16 bits
   const bool b32 = nc <= 0xFFFF && P <= 0x10000;
