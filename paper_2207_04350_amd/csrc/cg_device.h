@@ -424,6 +424,7 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
                                         unsigned int *status,
                                         const uint8_t *__restrict__ comp_kind = nullptr,
                                         int32_t *__restrict__ comp_estart = nullptr) {
+  static_assert(BLOCK > 2 * kWave, "the pipelined windows' merge needs threads beyond two waves");
   __shared__ uint64_t win[2][kWave];  // a window's raised keys, alternating buffers
   __shared__ uint32_t s_cnt[BLOCK >= 1024 ? BLOCK / kWave * 256 : 1];  // the radix sorts' counters
   __shared__ int32_t sh_scan[BLOCK / kWave + 1];
@@ -541,7 +542,8 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
     i0 = P;
   }
   __syncthreads();  // (outside the branch: inside it, the compiler kept a stack frame)
-  // Above 64 bins the windows are pipelined: after a window's steps, wave 0
+  // Above 64 bins the windows are pipelined (the workgroup has more than
+  // 2 * 64 threads): after a window's steps, wave 0
   // forms the next window in its lanes as the W least of the raised keys and
   // the next W keys of the list (a bitonic merge in registers) and goes on,
   // while the other waves merge the raised keys back into the list.  One
@@ -703,19 +705,31 @@ __device__ __forceinline__ int lpt_body(int nc, int P, const int32_t *__restrict
         }
       } else {
         // the other waves: the raised keys (sorted) merged with binA[W..P)
-        // (sorted) into binB
+        // (sorted) into binB.  Merge thread t < W places raised key t (its
+        // rank in binA[W..P) by binary search); the others place the list's
+        // keys, two at once (each one's rank among the W = 64 raised keys by
+        // six fixed steps, the two searches interleaved)
         const uint64_t *wk = win[cur];
-        for (int idx = tid - kWave; idx < P; idx += (int)blockDim.x - kWave) {
-          uint64_t x;
-          int pos;
-          if (idx < W) {
-            x = wk[idx];
-            pos = idx + lower_bound_u64(binA + W, P - W, x);
-          } else {
-            x = binA[idx];
-            pos = (idx - W) + lower_bound_u64(wk, W, x);
+        const int t = tid - kWave, mt = (int)blockDim.x - kWave - W;  // list threads
+        if (t < W) {
+          const uint64_t x = wk[t];
+          binB[t + lower_bound_u64(binA + W, P - W, x)] = x;
+        } else {
+          for (int j0 = t - W; j0 < P - W; j0 += 2 * mt) {
+            const int j1 = j0 + mt;
+            const bool two = j1 < P - W;
+            const uint64_t x0 = binA[W + j0], x1 = two ? binA[W + j1] : 0ull;
+            int r0 = 0, r1 = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1) {
+              r0 += wk[r0 + step - 1] < x0 ? step : 0;
+              r1 += wk[r1 + step - 1] < x1 ? step : 0;
+            }
+            r0 += wk[r0] < x0 ? 1 : 0;
+            r1 += wk[r1] < x1 ? 1 : 0;
+            binB[j0 + r0] = x0;
+            if (two) binB[j1 + r1] = x1;
           }
-          binB[pos] = x;
         }
       }
       uint64_t *t = binA;
