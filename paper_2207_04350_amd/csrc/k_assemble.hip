@@ -4,8 +4,10 @@
 // contributes the part of its walking orientation that precedes its overlap
 // with the next read (len - ovl bases), the last read all its bases.
 //
-//  k_asm_walk     one workgroup per component: start read, walk order by
-//                 pointer jumping over the chain's arcs (Wyllie list
+//  k_asm_walk_small  one wave per component of at most kWalkSmallCap reads
+//                 (small LDS arrays, so many are walked at once per CU)
+//  k_asm_walk     one workgroup per larger component: start read, walk order
+//                 by pointer jumping over the chain's arcs (Wyllie list
 //                 ranking), orientation from the strand bits, piece lengths
 //                 and offsets, layout and contig record
 //  k_asm_offsets  contig base offsets (16-base aligned) in (bin, label) order
@@ -16,9 +18,34 @@
 
 namespace cg {
 
+constexpr int32_t kWalkSplitReads = 1 << 19;  // reads from which the walk takes two passes
+
+__global__ __launch_bounds__(kWalkSmallBlock) void k_asm_walk_small(cg_graph g, cg_parts parts,
+                                                                   cg_local local, cg_contigs out,
+                                                                   Scratch s) {
+  __shared__ int32_t s_nb[2 * kWalkSmallCap], s_eid[2 * kWalkSmallCap], s_nxt[2 * kWalkSmallCap],
+      s_dist[2 * kWalkSmallCap], s_endv[2 * kWalkSmallCap], s_vid[kWalkSmallCap];
+  __shared__ uint32_t s_rlen[kWalkSmallCap], s_eo[2 * kWalkSmallCap], s_ep[2 * kWalkSmallCap];
+  __shared__ uint64_t s_roff[kWalkSmallCap];
+  __shared__ uint8_t s_es[2 * kWalkSmallCap];
+  __shared__ uint32_t sh_scan[kWalkSmallBlock / kWave + 1];
+  const int nc = *parts.d_n_comp;
+  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int q = parts.comp_size[c];
+    if (q > kWalkSmallCap) continue;  // k_asm_walk's
+    const int st = parts.comp_start[c];
+    WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
+    walk_component<kWalkSmallBlock, kWalkSmallCap, true>(c, q, st, w, g, parts, local.perm,
+                                                         local.loc_row_ptr, local.loc_col,
+                                                         local.loc_eid, out, s, nullptr, sh_scan);
+  }
+}
+
+// skip_to: components of at most this many reads are k_asm_walk_small's (0:
+// every component is this kernel's)
 __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts parts, cg_local local,
                                                          cg_contigs out, Scratch s,
-                                                         int32_t *gbuf) {
+                                                         int32_t *gbuf, int32_t skip_to) {
   __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
       s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
   __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
@@ -29,6 +56,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
   const int n = g.n;
   for (int c = blockIdx.x; c < nc; c += gridDim.x) {
     const int q = parts.comp_size[c];
+    if (q <= skip_to) continue;  // k_asm_walk_small's
     const int st = parts.comp_start[c];
     if (q <= kWalkCap) {
       WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
@@ -114,8 +142,16 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
     return hip_check(hipGetLastError(), "k_asm");
   }
   const int wgrid = n < 4096 ? n : 4096;
+  // A large graph has thousands of components, most of them small: those of
+  // at most kWalkSmallCap reads go one wave each to a pass of their own with
+  // small LDS arrays (many per CU).  On a smaller graph the second launch
+  // costs more than it saves (on 125,000 reads: 26 us against 17).
+  const bool split = n >= kWalkSplitReads;
+  if (split)
+    CG_LAUNCH(ctx, k_asm_walk_small, dim3(n < 8192 ? n : 8192), dim3(kWalkSmallBlock), st, g,
+              parts, local, out, s);
   CG_LAUNCH(ctx, k_asm_walk, dim3(wgrid), dim3(kWalkBlock), st, g, parts, local, out, s,
-                     s.walk);
+                     s.walk, split ? kWalkSmallCap : 0);
   CG_LAUNCH(ctx, k_asm_offsets, dim3(1), dim3(kScanBlock), st, parts.d_n_comp, out.len,
                      out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
   // about eight pieces per wave, so a small graph still spreads over the chip
