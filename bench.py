@@ -63,6 +63,7 @@ def algo_bytes(kernel, s):
         "k_ind_fill": 4 * N + 4 * N + 8 * n_e,
         "k_ind_local": 8 * n_e + 4 * n_e,
         "k_ind_rows": 4 * n_e + n_e + 4 * (n_e + 1) + 8 * m_e + 4 * n_e,
+        "k_ind_rows_wide": 4 * n_e + n_e + 4 * (n_e + 1) + 8 * m_e + 4 * n_e,
         # perm, local rows, entries (columns + ids, strands + overlaps), read
         # lengths and store offsets; layout (id, strand) and pieces (length,
         # store anchor, offset) written

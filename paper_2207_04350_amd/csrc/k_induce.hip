@@ -8,7 +8,8 @@
 //  k_ind_local  one workgroup per component: sort the block by read id
 //               (LDS bitonic up to 1024 reads, rank counting above)
 //  k_ind_rows   local CSR rows (look-back scan of kept degrees), columns
-//               renumbered through the local numbers, entry index kept
+//               renumbered through the local numbers, entry index kept;
+//               k_ind_rows_wide does the same four rows per thread
 #include "cg_device.h"
 
 namespace cg {
@@ -118,6 +119,78 @@ __global__ __launch_bounds__(kScanBlock) void k_ind_rows(
   lookback_finish(sc, nblocks);
 }
 
+// k_ind_rows with kRowsWide consecutive local numbers per thread.  On a
+// large graph it keeps four rows' loads in flight per thread and puts a
+// quarter of the blocks in the look-back; on a small one, whose few thousand
+// contig reads fill only a few dozen blocks, one row per thread spreads them
+// over four times as many compute units and is the faster form.
+constexpr int32_t kRowsWideReads = 1 << 19;  // reads from which the wide form runs
+constexpr int kRowsWide = 4;
+__global__ __launch_bounds__(kScanBlock) void k_ind_rows_wide(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+    const uint8_t *__restrict__ flags, const int32_t *__restrict__ bin_vptr, int32_t P,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ lidx,
+    int32_t *__restrict__ loc_row_ptr, int32_t *__restrict__ loc_col,
+    int32_t *__restrict__ loc_eid, int32_t *__restrict__ d_sizes, ScanCtx sc, int nblocks) {
+  const int blk = lookback_ticket(sc);
+  const int32_t n_e = bin_vptr[P];
+  // the grid covers every read and only the n_e reads of the contigs have
+  // local numbers: blocks past them take no part in the scan (a block looks
+  // back at lower tickets only, and the last block out clears every status)
+  if ((int64_t)blk * kScanBlock * kRowsWide > n_e) {
+    lookback_finish(sc, nblocks);
+    return;
+  }
+  const int64_t i0 = ((int64_t)blk * kScanBlock + threadIdx.x) * kRowsWide;
+  // every load of the thread's rows is issued before the scan, level by
+  // level (read, flags, row start, columns, their local numbers), and the
+  // stores come after it: gfx9 counts loads and stores in one counter, so a
+  // load behind a store would wait for it
+  int32_t v[kRowsWide], b[kRowsWide], c0[kRowsWide], c1[kRowsWide];
+  uint32_t f[kRowsWide];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) v[k] = i0 + k < n_e ? perm[i0 + k] : -1;
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) {
+    f[k] = v[k] >= 0 ? flags[v[k]] : 0u;
+    sum += ((f[k] >> 1) & 1) + ((f[k] >> 2) & 1);
+  }
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) b[k] = (f[k] & 6u) ? row_ptr[v[k]] : 0;
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) {
+    c0[k] = (f[k] & 2u) ? col[b[k]] : -1;
+    c1[k] = (f[k] & 4u) ? col[b[k] + 1] : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) {
+    c0[k] = c0[k] >= 0 ? lidx[c0[k]] : -1;
+    c1[k] = c1[k] >= 0 ? lidx[c1[k]] : -1;
+  }
+  unsigned long long incl_end;
+  unsigned long long ex = lookback_block_scan(sc, blk, (unsigned long long)sum, &incl_end);
+#pragma unroll
+  for (int k = 0; k < kRowsWide; ++k) {
+    const int64_t i = i0 + k;
+    if (i <= n_e) loc_row_ptr[i] = (int32_t)ex;
+    if (i == n_e) d_sizes[1] = (int32_t)ex;
+    int32_t t = (int32_t)ex;
+    if (f[k] & 2u) {
+      loc_col[t] = c0[k];
+      loc_eid[t] = b[k];
+      ++t;
+    }
+    if (f[k] & 4u) {
+      loc_col[t] = c1[k];
+      loc_eid[t] = b[k] + 1;
+      ++t;
+    }
+    ex = (unsigned long long)t;
+  }
+  lookback_finish(sc, nblocks);
+}
+
 int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_t *flags,
                   const int32_t *label, const cg_parts &parts, int32_t P, const cg_local &out,
                   hipStream_t st) {
@@ -135,10 +208,17 @@ int launch_induce(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uint8_
     CG_LAUNCH(ctx, k_ind_local, dim3(lgrid), dim3(kIndBlock), st, parts.d_n_comp,
                        parts.comp_size, parts.comp_start, s.tmp, out.perm, s.lidx);
   }
-  const int nb = scan_blocks((int64_t)n + 1);
-  CG_LAUNCH(ctx, k_ind_rows, dim3(nb), dim3(kScanBlock), st, g.row_ptr, g.col, flags,
-                     out.bin_vptr, P, out.perm, s.lidx, out.loc_row_ptr, out.loc_col, out.loc_eid,
-                     out.d_sizes, scan_ctx(ctx, s), nb);
+  if (n >= kRowsWideReads) {
+    const int nb = scan_blocks(((int64_t)n + kRowsWide) / kRowsWide);
+    CG_LAUNCH(ctx, k_ind_rows_wide, dim3(nb), dim3(kScanBlock), st, g.row_ptr, g.col, flags,
+              out.bin_vptr, P, out.perm, s.lidx, out.loc_row_ptr, out.loc_col, out.loc_eid,
+              out.d_sizes, scan_ctx(ctx, s), nb);
+  } else {
+    const int nb = scan_blocks((int64_t)n + 1);
+    CG_LAUNCH(ctx, k_ind_rows, dim3(nb), dim3(kScanBlock), st, g.row_ptr, g.col, flags,
+              out.bin_vptr, P, out.perm, s.lidx, out.loc_row_ptr, out.loc_col, out.loc_eid,
+              out.d_sizes, scan_ctx(ctx, s), nb);
+  }
   return hip_check(hipGetLastError(), "k_ind");
 }
 

@@ -29,23 +29,38 @@ __global__ __launch_bounds__(kPartBlock) void k_part_count(int32_t n, const uint
   atomicAdd((uint32_t *)cnt + label[v], 4u + (degL == 1 ? 1u : 0u));
 }
 
+// kCompactPer consecutive reads per thread, so that every block of a large
+// graph is resident at once and the look-back chain is short
+constexpr int kCompactPer = 4;
 __global__ __launch_bounds__(kScanBlock) void k_part_compact(
     int32_t n, const uint8_t *__restrict__ flags, int32_t *label_comp, int32_t min_reads,
     int32_t *__restrict__ comp_label, int32_t *__restrict__ comp_size,
     uint8_t *__restrict__ comp_kind, int32_t *__restrict__ d_n_comp, ScanCtx sc, int nblocks) {
   const int blk = lookback_ticket(sc);
-  const int64_t v = (int64_t)blk * kScanBlock + threadIdx.x;
-  const uint32_t c = v < n ? (uint32_t)label_comp[v] : 0u;
-  const uint32_t q = c >> 2;
-  const bool elig = v < n && q >= (uint32_t)min_reads && !(flags[v] & 1);
+  const int64_t v0 = ((int64_t)blk * kScanBlock + threadIdx.x) * kCompactPer;
+  uint32_t c[kCompactPer];
+  bool elig[kCompactPer];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kCompactPer; ++k) {
+    const int64_t v = v0 + k;
+    c[k] = v < n ? (uint32_t)label_comp[v] : 0u;
+    elig[k] = v < n && (c[k] >> 2) >= (uint32_t)min_reads && !(flags[v] & 1);
+    cnt += elig[k] ? 1u : 0u;
+  }
   unsigned long long incl_end;
-  const unsigned long long ex = lookback_block_scan(sc, blk, elig ? 1ull : 0ull, &incl_end);
-  if (v < n) {
-    if (elig) {
+  unsigned long long ex = lookback_block_scan(sc, blk, (unsigned long long)cnt, &incl_end);
+#pragma unroll
+  for (int k = 0; k < kCompactPer; ++k) {
+    const int64_t v = v0 + k;
+    if (v >= n) continue;
+    if (elig[k]) {
+      const uint32_t q = c[k] >> 2;
       comp_label[ex] = (int32_t)v;
       comp_size[ex] = (int32_t)q;
-      comp_kind[ex] = q == 1 ? CG_KIND_SINGLE : ((c & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
+      comp_kind[ex] = q == 1 ? CG_KIND_SINGLE : ((c[k] & 3u) ? CG_KIND_PATH : CG_KIND_CYCLE);
       label_comp[v] = (int32_t)ex;
+      ++ex;
     } else {
       label_comp[v] = -1;
     }
@@ -107,7 +122,7 @@ int launch_partition(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const uin
     CG_LAUNCH(ctx, k_part_count, dim3(grid), dim3(kPartBlock), st, n, flags, label,
                        out.label_comp);
   }
-  const int nb = scan_blocks(n > 0 ? n : 1);
+  const int nb = scan_blocks(n > 0 ? (n + kCompactPer - 1) / kCompactPer : 1);
   CG_LAUNCH(ctx, k_part_compact, dim3(nb), dim3(kScanBlock), st, n, flags, out.label_comp,
                      min_reads, out.comp_label, out.comp_size, out.comp_kind, out.d_n_comp,
                      scan_ctx(ctx, s), nb);
