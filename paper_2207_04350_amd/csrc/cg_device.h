@@ -240,10 +240,16 @@ __device__ __forceinline__ void bitonic_segments(K *a, int N2, int k0, int k1) {
 // workgroup.  Only the stages whose pairs lie 64 or more apart go through
 // memory, two per pass and barrier; the stages inside 64-element segments
 // run in registers (for N2 = 512: 4 passes through memory, 45 stages).
-template <typename K>
+// kLdsOnly: the barriers order LDS only, so the caller's global loads stay
+// in flight through the sort.
+template <typename K, bool kLdsOnly = false>
 __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
+  auto bar = [] {
+    if constexpr (kLdsOnly) lds_barrier();
+    else __syncthreads();
+  };
   bitonic_segments(a, N2, 2, N2 < kWave ? N2 : kWave);
-  __syncthreads();
+  bar();
   for (int k = 2 * kWave; k <= N2; k <<= 1) {
     int j = k >> 1;
     // two stages (j, j/2) per barrier: each thread takes the four elements
@@ -264,7 +270,7 @@ __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
         a[i + j] = x2;
         a[i + j + h] = x3;
       }
-      __syncthreads();
+      bar();
     }
     if (j >= kWave) {  // one stage left above the register stages
       for (int t = threadIdx.x; t < N2 / 2; t += blockDim.x) {
@@ -275,10 +281,10 @@ __device__ __forceinline__ void bitonic_sort(K *a, int N2) {
           a[i + j] = x;
         }
       }
-      __syncthreads();
+      bar();
     }
     bitonic_segments(a, N2, k, k);
-    __syncthreads();
+    bar();
   }
 }
 
@@ -835,21 +841,8 @@ __device__ __forceinline__ void sort_component_block(int q, int st,
     while (N2 < q) N2 <<= 1;
     for (int i = threadIdx.x; i < N2; i += BLOCK) a[i] = i < q ? members[MS * i] : 0x7FFFFFFF;
     __syncthreads();
-    for (int k = 2; k <= N2; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < N2; i += BLOCK) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const int32_t x = a[i], y = a[ixj];
-            if ((x > y) == ((i & k) == 0)) {
-              a[i] = y;
-              a[ixj] = x;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
+    // non-negative ids padded with the largest int32: the same order as uint32
+    bitonic_sort(reinterpret_cast<uint32_t *>(a), N2);
     for (int i = threadIdx.x; i < q; i += BLOCK) {
       const int32_t v = a[i];
       perm[st + i] = v;

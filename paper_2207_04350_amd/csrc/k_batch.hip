@@ -1469,21 +1469,11 @@ __device__ __forceinline__ void iw_component(const BJob &J, const WqE &e, WalkAr
       if (i < N2) a[i] = i < q ? v[u] : 0x7FFFFFFF;
     }
     lds_barrier();
-    for (int k = 2; k <= N2; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < N2; i += BLOCK) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const int32_t x = a[i], y = a[ixj];
-            if ((x > y) == ((i & k) == 0)) {
-              a[i] = y;
-              a[ixj] = x;
-            }
-          }
-        }
-        lds_barrier();
-      }
-    }
+    // ids are non-negative and the padding is the largest int32, so their
+    // order as uint32 is the same; the stages within 64 elements run in
+    // registers (8 barriers for 512 ids instead of 45), and the barriers
+    // order LDS only, so the gathers above stay in flight
+    bitonic_sort<uint32_t, true>(reinterpret_cast<uint32_t *>(a), N2);
 #pragma unroll
     for (int u = 0; u < R; ++u) rk[u] = tid + u * BLOCK < q ? lds_lower_bound(a, q, v[u]) : 0;
   }
