@@ -85,7 +85,7 @@ struct BatchDev {
   int32_t *wq_hist;                 // [kWqBuckets] components per read count (capped)
   int32_t *wq_cur;                  // [kWqBuckets] placement cursors
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
-                                    // reads, 2: above kWalkCap, 3: above kWalkTinyCap
+                                    // reads, 2: above kIwCap, 3: above kWalkTinyCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
   int32_t *chunk_job;               // [bound on the chunks] job of each copy chunk
   unsigned int *counters;           // [8] 2: LPT ticket
@@ -1222,10 +1222,18 @@ __global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
 // number), and the queue heads of the per-component passes.  Handing the
 // largest components out first to whichever workgroup is free is LPT list
 // scheduling of the whole batch's components onto the workgroups.
-// Components above kWalkCap reads form the queue's head (two passes, arrays
+// Components above kIwCap reads form the queue's head (two passes, arrays
 // in scratch), those of at most kWalkSmallCap its tail (one wave each).
 constexpr int kWqBlock = 256;
 constexpr int kWalkTinyCap = 32;  // reads of the components the tiny pass takes
+// Reads of the components that the one-pass workgroup form takes (its walk
+// arrays in LDS).  Each such component's time is mostly latency (dependent
+// gathers, barriers), about the same from 129 to 512 reads, so the pass
+// wants every component on a workgroup of its own: LDS sized for 512 reads
+// (and 2 members per thread) lets four workgroups share a compute unit,
+// where LDS for 1024 held two, and a batch's 634 components above 128 reads
+// then took two rounds.  Larger components take the two-pass form.
+constexpr int kIwCap = 512;
 constexpr int kWqPer = kWqBuckets / kWqBlock;
 
 __device__ __forceinline__ WqE wq_make(const BJob &J, int j, int32_t c, int32_t q) {
@@ -1256,7 +1264,7 @@ __global__ __launch_bounds__(kWqBlock) void kb_wq_place(BatchDev B) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.wq_meta[0] = tot;
     B.wq_meta[1] = s_start[kWalkSmallCap];  // components above kWalkSmallCap reads
-    B.wq_meta[2] = s_start[kWalkCap];       // above kWalkCap
+    B.wq_meta[2] = s_start[kIwCap];         // above kIwCap
     B.wq_meta[3] = s_start[kWalkTinyCap];   // above kWalkTinyCap
   }
   // this workgroup's components: a contiguous range; counted per bucket in
@@ -1592,19 +1600,20 @@ __global__ __launch_bounds__(kWalkSmallBlock) void kb_induce_walk_small(BatchDev
   }
 }
 
-// 6c. components of kWalkSmallCap + 1 .. kWalkCap reads: one workgroup each,
+// 6c. components of kWalkSmallCap + 1 .. kIwCap reads: one workgroup each,
 // both steps in one pass; and, first (the queue's head, largest first), the
-// induced subgraph of each component above kWalkCap reads, with the block
-// sort in scratch (its walk, whose arrays reuse the tile lists' memory,
-// waits for the next launch)
+// induced subgraph of each component above kIwCap reads, with the block
+// sort in LDS up to kIndLocalCap reads, else in scratch (its walk, whose
+// arrays reuse the tile lists' memory, waits for the next launch)
 static_assert(kIndBlock == kWalkBlock, "one workgroup shape for both components' steps");
-static_assert(kIndLocalCap <= 2 * kWalkCap, "the induce step's sort buffer is the walk's nxt array");
+static_assert(kIndLocalCap <= 2 * kIwCap, "the induce step's sort buffer is the walk's nxt array");
+static_assert(kIwCap <= kWalkCap && kIwCap % kWalkBlock == 0, "whole members per thread");
 __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
-  __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
-      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
-  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
-  __shared__ uint64_t s_roff[kWalkCap];
-  __shared__ uint8_t s_es[2 * kWalkCap];
+  __shared__ int32_t s_nb[2 * kIwCap], s_eid[2 * kIwCap], s_nxt[2 * kIwCap],
+      s_dist[2 * kIwCap], s_endv[2 * kIwCap], s_vid[kIwCap];
+  __shared__ uint32_t s_rlen[kIwCap], s_eo[2 * kIwCap], s_ep[2 * kIwCap];
+  __shared__ uint64_t s_roff[kIwCap];
+  __shared__ uint8_t s_es[2 * kIwCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int32_t hi = ld_const(B.wq_meta, 1);
   // each round's entry is fetched while the previous round's component runs
@@ -1615,7 +1624,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
     const WqE e = nx;
     x = wq_entry(0, hi, r);
     if (x >= 0) nx = wq_get(B, x);
-    if (e.q > kWalkCap) {
+    if (e.q > kIwCap) {
       __syncthreads();  // the previous round's LDS is free
       induce_listed<kIndBlock, kIndLocalCap>(B, make_int4(e.job, e.c, e.q, e.st), s_nxt,
                                              (int32_t *)sh_scan);
@@ -1624,7 +1633,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_induce_walk(BatchDev B) {
     }
     const BJob J = job_at(B.jobs, e.job);
     WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-    iw_component<kWalkBlock, kWalkCap>(J, e, w, sh_scan);
+    iw_component<kWalkBlock, kIwCap>(J, e, w, sh_scan);
   }
 }
 
@@ -2252,7 +2261,7 @@ int cg_batch_run(cg_batch *b, void *stream) {
   CG_LAUNCH(ctx, kb_tables, dim3(256), dim3(kTablesBlock), st, B);
   CG_LAUNCH(ctx, kb_wq_place, dim3(128), dim3(kWqBlock), st, B);
   auto capped = [](int want, int fit) { return dim3((unsigned)(fit > 0 && fit < want ? fit : want)); };
-  // components above kWalkCap reads in two passes (the induce step with the
+  // components above kIwCap reads in two passes (the induce step with the
   // next ones, the walk after the last pass that reads the tile lists, since
   // its arrays take their memory), the others in one
   CG_LAUNCH(ctx, kb_induce_walk, capped(PB, b->res_iw), dim3(kWalkBlock), st, B);

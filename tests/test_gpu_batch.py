@@ -50,10 +50,16 @@ def _mixed_graphs():
     gs.append(_chain_graph(r, [7000, 5000, 1], cycles=[4000, 600]))
     gs[-1].meta["min_reads"] = 1
     # explicit coordinates through every batched walk form: one-wave walks
-    # (up to 128 reads), the LDS walk (129-1024) and the global-array walk
-    # (above 1024), chains and cycles, clipped and arbitrary; and a job with
-    # coordinates above the batched entry bound (single-graph route)
+    # (up to 128 reads), the one-pass LDS walk (129-512) and the two-pass
+    # global-array walk (above 512: the induce step's sort in LDS up to 1024
+    # reads, in scratch above), chains and cycles, clipped and arbitrary;
+    # and a job with coordinates above the batched entry bound (single-graph
+    # route)
     rc = np.random.default_rng(33)
+    gs.append(synth.with_alignment_ends(
+        _chain_graph(rc, [128, 129, 512, 513, 1024, 1025], cycles=[512, 513, 1024],
+                     len_lo=30, len_hi=80), rc, 3))
+    gs[-1].meta = dict(gs[-1].meta, min_reads=2)
     gs.append(synth.with_alignment_ends(
         _chain_graph(rc, [200, 900, 3000, 60], cycles=[1500], len_lo=30, len_hi=80), rc, 3))
     gs[-1].meta = dict(gs[-1].meta, min_reads=2)
