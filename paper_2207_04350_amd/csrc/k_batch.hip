@@ -87,7 +87,8 @@ struct BatchDev {
   int32_t *wq_meta;                 // [8] 0: components, 1: those above kWalkSmallCap
                                     // reads, 2: above kIwCap, 3: above kWalkTinyCap
   int32_t *comp_job;                // [sum n] job of each batch-wide component
-  int32_t *chunk_job;               // [bound on the chunks] job of each copy chunk
+  int4 *chunk_desc;                 // [bound on the chunks] copy chunk: job, first piece,
+                                    // pieces (0: the job's bases overflowed), job's pieces
   unsigned int *counters;           // [8] 2: LPT ticket
   const int32_t *job_order;         // [n_jobs] jobs by decreasing read count
   int2 *mt_cnt;                     // [n_mtiles] (listed reads, branch reads) of each mask tile
@@ -1178,37 +1179,31 @@ __global__ __launch_bounds__(kBatchLptBlock) void kb_lpt(BatchDev B) {
   __threadfence();
 }
 
-// 4b. the job of every batch-wide component and copy chunk, so that the
-// persistent passes find it with one load: one entry per thread, by binary
-// search in the bases (staged in LDS up to kTablesJobCap jobs)
+// 4b. the job of every batch-wide component, so that the work queue's
+// placement finds it with one load, and the queue's histogram: one entry per
+// thread, by binary search in the bases (staged in LDS up to kTablesJobCap
+// jobs)
 constexpr int kTablesBlock = 256;
 constexpr int kTablesJobCap = 4096;
 
 __global__ __launch_bounds__(kTablesBlock) void kb_tables(BatchDev B) {
-  __shared__ int32_t s_cb[kTablesJobCap + 1], s_hb[kTablesJobCap + 1];
+  __shared__ int32_t s_cb[kTablesJobCap + 1];
   __shared__ int32_t s_hist[kWqBuckets];
   for (int b = threadIdx.x; b < kWqBuckets; b += kTablesBlock) s_hist[b] = 0;
   const int nj = B.n_jobs;
   const bool in_lds = nj <= kTablesJobCap;
   if (in_lds) {
-    for (int i = threadIdx.x; i <= nj; i += kTablesBlock) {
-      s_cb[i] = B.comp_base[i];
-      s_hb[i] = B.chunk_base[i];
-    }
+    for (int i = threadIdx.x; i <= nj; i += kTablesBlock) s_cb[i] = B.comp_base[i];
   }
   __syncthreads();
-  const int32_t tc = B.comp_base[nj], th = B.chunk_base[nj];
-  const int32_t nmax = tc > th ? tc : th;
-  for (int32_t i = blockIdx.x * kTablesBlock + threadIdx.x; i < nmax;
+  const int32_t tc = B.comp_base[nj];
+  for (int32_t i = blockIdx.x * kTablesBlock + threadIdx.x; i < tc;
        i += gridDim.x * kTablesBlock) {
-    if (i < tc) {
-      const int j = job_of(in_lds ? s_cb : B.comp_base, nj, i);
-      B.comp_job[i] = j;
-      // the work queue's histogram: components per read count
-      const int32_t q = B.jobs[j].parts.comp_size[i - (in_lds ? s_cb[j] : B.comp_base[j])];
-      atomicAdd(s_hist + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
-    }
-    if (i < th) B.chunk_job[i] = job_of(in_lds ? s_hb : B.chunk_base, nj, i);
+    const int j = job_of(in_lds ? s_cb : B.comp_base, nj, i);
+    B.comp_job[i] = j;
+    // the work queue's histogram: components per read count
+    const int32_t q = B.jobs[j].parts.comp_size[i - (in_lds ? s_cb[j] : B.comp_base[j])];
+    atomicAdd(s_hist + (q < kWqBuckets - 1 ? q : kWqBuckets - 1), 1);
   }
   // (counted in LDS: many components share a read count, and their global
   // atomics would queue on one address)
@@ -1656,7 +1651,7 @@ __global__ __launch_bounds__(kWalkBlock) void kb_walk(BatchDev B) {
   }
 }
 
-// 8. contig word offsets per job
+// 8. contig word offsets per job, and the descriptors of its copy chunks
 __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   const BJob J = job_at(B.jobs, blockIdx.x);
@@ -1675,6 +1670,19 @@ __global__ __launch_bounds__(kScanBlock) void kb_offsets(BatchDev B) {
     *J.out.d_total_words = carry;
     if (carry > J.out.cap_words) atomicOr(&B.fixed->status, CG_STATUS_BASES_OVERFLOW);
   }
+  // the job's copy chunks, each in one 16-byte descriptor, so that a copy
+  // wave starts from one load (none of the job's bases is written when
+  // they overflow its buffer)
+  const int32_t j = blockIdx.x;
+  const int32_t h0 = B.chunk_base[j], h1 = B.chunk_base[j + 1];
+  const int32_t n_e = B.piece_base[j + 1] - B.piece_base[j];
+  const int32_t cp = B.chunk_cp[j];
+  const bool over = carry > J.out.cap_words;
+  for (int32_t h = h0 + (int32_t)threadIdx.x; h < h1; h += kScanBlock) {
+    const int32_t c0 = (h - h0) * cp;
+    const int32_t cnt = n_e - c0 < cp ? n_e - c0 : cp;
+    B.chunk_desc[h] = make_int4(j, c0, over ? 0 : cnt, n_e);
+  }
 }
 
 // 9. packed copy: one wave per chunk of kChunkPieces consecutive pieces of a
@@ -1691,13 +1699,12 @@ __global__ __launch_bounds__(1024) void kb_copy(BatchDev B) {
   const int32_t total = ld_const(B.chunk_base, B.n_jobs);
   for (int32_t ch = gw; ch < total; ch += nwv) {
     // a chunk never spans two jobs, so the job is the same for the whole wave
-    const int j = ld_const(B.chunk_job, ch);
+    const CG_CONST uint64_t *pd = (const CG_CONST uint64_t *)(B.chunk_desc + ch);
+    const uint64_t d0 = pd[0], d1 = pd[1];
+    const int j = (int)(uint32_t)d0, c0 = (int)(uint32_t)(d0 >> 32);
+    const int cnt = (int)(uint32_t)d1, n_e = (int)(uint32_t)(d1 >> 32);
+    if (cnt <= 0) continue;  // the job's bases overflowed its buffer
     const BJob J = job_at(B.jobs, j);
-    if (*J.out.d_total_words > J.out.cap_words) continue;
-    const int32_t n_e = ld_const(B.piece_base, j + 1) - ld_const(B.piece_base, j);
-    const int cp = ld_const(B.chunk_cp, j);
-    const int32_t c0 = (ch - ld_const(B.chunk_base, j)) * cp;
-    const int cnt = n_e - c0 < cp ? n_e - c0 : cp;
     copy_chunk(J.g.seq, J.g.seq_words, J.out.bases, piece_arrays(J), c0, cnt, n_e, lane_id());
   }
 }
@@ -1961,7 +1968,7 @@ static int plan_sizes(int32_t n_jobs, const cg_job *jobs, int vertex_tile, Plan 
   P->o_wqh = take(sizeof(int32_t) * kWqBuckets);
   P->o_wqc = take(sizeof(int32_t) * kWqBuckets);
   P->o_wqm = take(sizeof(int32_t) * 8);
-  P->o_hjob = take(sizeof(int32_t) * (size_t)(P->sum_chunks > 0 ? P->sum_chunks : 1));
+  P->o_hjob = take(sizeof(int4) * (size_t)(P->sum_chunks > 0 ? P->sum_chunks : 1));
   P->o_counters = take(sizeof(unsigned int) * 8);
   P->o_order = take(sizeof(int32_t) * n_jobs);
   P->job_off.resize(n_jobs);
@@ -2054,7 +2061,7 @@ static void plan_fill(cg_batch *b, const Plan &P, const cg_job *jobs) {
   d.wq_cur = (int32_t *)(mem + P.o_wqc);
   d.wq_meta = (int32_t *)(mem + P.o_wqm);
   d.comp_job = (int32_t *)(mem + P.o_cjob);
-  d.chunk_job = (int32_t *)(mem + P.o_hjob);
+  d.chunk_desc = (int4 *)(mem + P.o_hjob);
   d.counters = (unsigned int *)(mem + P.o_counters);
   d.job_order = (const int32_t *)(mem + P.o_order);
   d.mt_cnt = d_mtcnt;
