@@ -1226,8 +1226,9 @@ constexpr int kWalkTinyCap = 32;  // reads of the components the tiny pass takes
 // gathers, barriers), about the same from 129 to 512 reads, so the pass
 // wants every component on a workgroup of its own: LDS sized for 512 reads
 // (and 2 members per thread) lets four workgroups share a compute unit,
-// where LDS for 1024 held two, and a batch's 634 components above 128 reads
-// then took two rounds.  Larger components take the two-pass form.
+// where LDS for 1024 held two, so that a batch with more components above
+// 128 reads than two per compute unit took two rounds of them.  Larger
+// components take the two-pass form.
 constexpr int kIwCap = 512;
 constexpr int kWqPer = kWqBuckets / kWqBlock;
 
