@@ -100,6 +100,9 @@ __global__ __launch_bounds__(kScanBlock) void k_asm_offsets(const int32_t *__res
 }
 
 constexpr int kCopyBlock = 256;
+constexpr int kCopyWavesPerCU = 16;  // resident copy waves per compute unit (4 per SIMD)
+constexpr int kCopyRounds = 4;       // copy chunks per resident wave slot
+constexpr int kCopyMinPieces = 2;    // pieces per copy chunk at least
 
 __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restrict__ seq,
                                                          uint64_t seq_words,
@@ -113,17 +116,20 @@ __global__ __launch_bounds__(kCopyBlock) void k_asm_copy(const uint32_t *__restr
                                                          const uint64_t *__restrict__ cbase,
                                                          const uint64_t *__restrict__ d_total_words,
                                                          uint64_t cap_words,
-                                                         uint32_t *__restrict__ bases) {
+                                                         uint32_t *__restrict__ bases,
+                                                         int32_t chunk_target) {
   if (*d_total_words > cap_words) return;
   const int32_t n_e = bin_vptr[P];
   const PieceArrays A = piece_arrays(lay_contig, piece_off, piece_len, piece_src, clen, cbase);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int32_t gw = blockIdx.x * (blockDim.x / kWave) + wave;
   const int32_t nwv = gridDim.x * (blockDim.x / kWave);
-  // pieces per wave: enough chunks to give every wave of the grid work,
-  // at most one piece per lane
-  int32_t C = (n_e + nwv - 1) / nwv;
-  C = C < 1 ? 1 : (C > kWave ? kWave : C);
+  // pieces per chunk: about chunk_target chunks (a few per wave slot of the
+  // device, so the slots drain evenly while each chunk's setup, a chain of
+  // dependent descriptor loads, is paid for enough pieces), at least
+  // kCopyMinPieces, at most one piece per lane
+  int32_t C = (n_e + chunk_target - 1) / chunk_target;
+  C = C < kCopyMinPieces ? kCopyMinPieces : (C > kWave ? kWave : C);
   const int32_t n_chunks = (n_e + C - 1) / C;
   for (int32_t ch = gw; ch < n_chunks; ch += nwv) {
     const int32_t c0 = ch * C;
@@ -156,9 +162,19 @@ int launch_assemble(cg_ctx *ctx, const cg_graph &g, const Scratch &s, const cg_p
                      out.base_off, out.cap_words, out.d_total_words, ctx->fixed);
   // about eight pieces per wave, so a small graph still spreads over the chip
   const int cgrid = (n + 31) / 32 < 8192 ? (n + 31) / 32 : 8192;
+  // chunks: kCopyRounds per resident wave slot (kCopyWavesPerCU per compute
+  // unit at the copy's register use), and never fewer than the grid's waves
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  const int64_t tgt = (int64_t)kCopyRounds * kCopyWavesPerCU * cus;
+  const int64_t gw = (int64_t)cgrid * (kCopyBlock / kWave);
+  const int32_t chunk_target = (int32_t)(tgt > gw ? gw : tgt);
   CG_LAUNCH(ctx, k_asm_copy, dim3(cgrid), dim3(kCopyBlock), st, g.seq, g.seq_words,
                      local.bin_vptr, P, s.piece_off, s.piece_len, s.piece_src, s.lay_contig,
-                     out.len, out.base_off, out.d_total_words, out.cap_words, out.bases);
+                     out.len, out.base_off, out.d_total_words, out.cap_words, out.bases,
+                     chunk_target);
   return hip_check(hipGetLastError(), "k_asm");
 }
 
