@@ -11,9 +11,10 @@
 //                 ranking), orientation from the strand bits, piece lengths
 //                 and offsets, layout and contig record
 //  k_asm_offsets  contig base offsets (16-base aligned) in (bin, label) order
-//  k_asm_copy     one workgroup per piece: every output word is written by
-//                 the piece holding its first base, 2-bit funnel shifts for
-//                 unaligned starts, reverse + complement in registers
+//  k_asm_copy     chunks of consecutive pieces, one wave each: every output
+//                 word is written by the piece holding its first base, 2-bit
+//                 funnel shifts for unaligned starts, reverse + complement in
+//                 registers
 #include "cg_device.h"
 
 namespace cg {
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
 }
 
 // contig word offsets: one workgroup, scan of ceil(len/16) in record order
+constexpr int kOffRun = 8;  // contigs per thread k_asm_offsets holds in registers
 __global__ __launch_bounds__(kScanBlock) void k_asm_offsets(const int32_t *__restrict__ d_n_comp,
                                                             const uint64_t *__restrict__ len,
                                                             uint64_t *__restrict__ base_off,
@@ -85,13 +87,33 @@ __global__ __launch_bounds__(kScanBlock) void k_asm_offsets(const int32_t *__res
   __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   const int nc = *d_n_comp;
   unsigned long long carry = 0;
-  for (int base = 0; base < nc; base += kScanBlock) {
-    const int k = base + threadIdx.x;
-    const unsigned long long wds = k < nc ? (len[k] + 15) / 16 : 0;
-    unsigned long long tot;
-    const unsigned long long ex = block_excl_scan<unsigned long long, kScanBlock>(wds, sh, &tot);
-    if (k < nc) base_off[k] = 16 * (carry + ex);
-    carry += tot;
+  if (nc <= kOffRun * kScanBlock) {
+    // thread t takes contigs t*E .. t*E + E-1: their lengths loaded at once,
+    // one block scan of the thread sums (a loop over blocks of contigs
+    // waited for a load and a scan per block)
+    const int E = (nc + kScanBlock - 1) / kScanBlock;
+    const int k0 = (int)threadIdx.x * E;
+    unsigned long long w[kOffRun], x = 0;
+#pragma unroll
+    for (int r = 0; r < kOffRun; ++r) {
+      w[r] = r < E && k0 + r < nc ? (len[k0 + r] + 15) / 16 : 0;
+      x += w[r];
+    }
+    unsigned long long ex = block_excl_scan<unsigned long long, kScanBlock>(x, sh, &carry);
+#pragma unroll
+    for (int r = 0; r < kOffRun; ++r) {
+      if (r < E && k0 + r < nc) base_off[k0 + r] = 16 * ex;
+      ex += w[r];
+    }
+  } else {
+    for (int base = 0; base < nc; base += kScanBlock) {
+      const int k = base + threadIdx.x;
+      const unsigned long long wds = k < nc ? (len[k] + 15) / 16 : 0;
+      unsigned long long tot;
+      const unsigned long long ex = block_excl_scan<unsigned long long, kScanBlock>(wds, sh, &tot);
+      if (k < nc) base_off[k] = 16 * (carry + ex);
+      carry += tot;
+    }
   }
   if (threadIdx.x == 0) {
     *d_total_words = carry;
