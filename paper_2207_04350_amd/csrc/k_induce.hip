@@ -15,6 +15,7 @@
 namespace cg {
 
 
+constexpr int kIndBinLds = 2048;  // bins whose reads k_ind_zero sums in LDS
 __global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_t *__restrict__ d_n_comp,
                                                          const int32_t *__restrict__ comp_bin,
                                                          const int32_t *__restrict__ comp_size,
@@ -27,19 +28,40 @@ __global__ __launch_bounds__(kScanBlock) void k_ind_zero(int32_t P, const int32_
        c += (int64_t)gridDim.x * blockDim.x)
     fill[c] = 0;
   if (blockIdx.x == 0) {
-    // the reads of each bin, then their prefix: bin_vptr
+    // the reads of each bin (in LDS up to kIndBinLds bins, four components'
+    // loads per thread issued together), then their prefix: bin_vptr
     __shared__ int64_t sh[kScanBlock / kWave + 1];
-    for (int b = threadIdx.x; b < P; b += kScanBlock) bin_reads[b] = 0;
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += kScanBlock)
-      atomicAdd((unsigned long long *)bin_reads + comp_bin[c], (unsigned long long)comp_size[c]);
+    __shared__ unsigned long long s_br[kIndBinLds];
+    const bool lds = P <= kIndBinLds;
+    if (lds) {
+      for (int b = threadIdx.x; b < P; b += kScanBlock) s_br[b] = 0;
+      __syncthreads();
+      for (int c0 = threadIdx.x; c0 < nc; c0 += 4 * kScanBlock) {
+        int32_t bb[4], sz[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = c0 + r * kScanBlock;
+          bb[r] = c < nc ? comp_bin[c] : -1;
+          sz[r] = c < nc ? comp_size[c] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (bb[r] >= 0) atomicAdd(s_br + bb[r], (unsigned long long)sz[r]);
+      }
+    } else {
+      for (int b = threadIdx.x; b < P; b += kScanBlock) bin_reads[b] = 0;
+      __syncthreads();
+      for (int c = threadIdx.x; c < nc; c += kScanBlock)
+        atomicAdd((unsigned long long *)bin_reads + comp_bin[c], (unsigned long long)comp_size[c]);
+    }
     __syncthreads();
     int64_t carry = 0;
     for (int base = 0; base < P; base += kScanBlock) {
       const int b = base + threadIdx.x;
-      const int64_t x = b < P ? (int64_t)__hip_atomic_load(bin_reads + b, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT)
-                              : 0;
+      int64_t x = 0;
+      if (b < P)
+        x = lds ? (int64_t)s_br[b]
+                : (int64_t)__hip_atomic_load(bin_reads + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       int64_t tot;
       const int64_t ex = block_excl_scan<int64_t, kScanBlock>(x, sh, &tot);
       if (b < P) bin_vptr[b] = (int32_t)(carry + ex);
