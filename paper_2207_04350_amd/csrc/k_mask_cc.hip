@@ -76,12 +76,17 @@ __global__ __launch_bounds__(kMaskBlock) void k_mask(int32_t n, const int32_t *_
   fx->mask_ticket = 0;
 }
 
-__global__ __launch_bounds__(kWave) void k_mask_sum(int nparts, const Fixed *fx,
-                                                    int32_t *__restrict__ d_counts) {
+// one workgroup: a few parts per thread (their loads issued together), then
+// one block-wide sum (one wave looping over thousands of parts waited for a
+// load per turn)
+__global__ __launch_bounds__(kScanBlock) void k_mask_sum(int nparts, const Fixed *fx,
+                                                         int32_t *__restrict__ d_counts) {
+  __shared__ unsigned long long sh[kScanBlock / kWave + 1];
   unsigned long long a = 0;
-  for (int i = lane_id(); i < nparts; i += kWave) a += fx->mask_part[i];
-  for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off);
-  if (lane_id() == 0) store_counts(a, d_counts);
+  for (int i = threadIdx.x; i < nparts; i += kScanBlock) a += fx->mask_part[i];
+  unsigned long long tot;
+  (void)block_excl_scan<unsigned long long, kScanBlock>(a, sh, &tot);
+  if (threadIdx.x == 0) store_counts(tot, d_counts);
 }
 
 int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_counts,
@@ -93,7 +98,7 @@ int launch_mask(cg_ctx *ctx, const cg_graph &g, uint8_t *flags, int32_t *d_count
   CG_LAUNCH(ctx, k_mask, dim3((unsigned)grid), dim3(kMaskBlock), st, g.n, g.row_ptr, g.col, flags,
             ctx->fixed, d_counts);
   if (grid > kMaskSumInKernel)
-    CG_LAUNCH(ctx, k_mask_sum, dim3(1), dim3(kWave), st, (int)grid, ctx->fixed, d_counts);
+    CG_LAUNCH(ctx, k_mask_sum, dim3(1), dim3(kScanBlock), st, (int)grid, ctx->fixed, d_counts);
   return hip_check(hipGetLastError(), "k_mask");
 }
 
