@@ -93,6 +93,10 @@ def csrc_digest():
     return h.hexdigest()
 
 
+# counter profiles of the single-graph workloads' plain form
+PLAIN_PROFILES = {"large1g": "plain_1gbp_hbm_bytes.md"}
+
+
 def profiled_traffic(kernel, profile="batched_512graphs_hbm_bytes.md"):
     """HBM bytes per launch of a kernel from a committed counter profile
     (scaled FETCH_SIZE + WRITE_SIZE), or None when the kernel sources changed
@@ -533,10 +537,14 @@ def main():
                     if maskcc_traffic and maskcc_ms else None},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(kname(dom).replace("k_", "kb_", 1))
-                     if args.workload == "batch" and not use_plain else None,
+                     "traffic": (profiled_traffic(kname(dom).replace("k_", "kb_", 1))
+                                 if args.workload == "batch" and not use_plain else
+                                 profiled_traffic(kname(dom), PLAIN_PROFILES[args.workload])
+                                 if use_plain and args.workload in PLAIN_PROFILES else None),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
-                                     "profiles/batched_512graphs_hbm_bytes.md)",
+                                     "profiles/%s)" % (PLAIN_PROFILES.get(args.workload)
+                                                       if use_plain else
+                                                       "batched_512graphs_hbm_bytes.md"),
                      "avg_launch_us": dom_avg_us, "bytes_per_launch": dom_bytes_per_launch,
                      "timing": "HIP events around each launch on its stream, %d eager steps"
                                % args.steps},
