@@ -43,15 +43,20 @@ __global__ __launch_bounds__(kWalkSmallBlock) void k_asm_walk_small(cg_graph g, 
 }
 
 // skip_to: components of at most this many reads are k_asm_walk_small's (0:
-// every component is this kernel's)
+// every component is this kernel's).  Components of up to kAsmWalkCap reads
+// are walked in LDS, larger ones in global scratch: LDS arrays for 512 reads
+// let four workgroups share a compute unit (two with arrays for 1024), and
+// a component's walk is mostly latency, so more of them at once pays.
+constexpr int kAsmWalkCap = 512;
+static_assert(kAsmWalkCap % kWalkBlock == 0, "whole members per thread");
 __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts parts, cg_local local,
                                                          cg_contigs out, Scratch s,
                                                          int32_t *gbuf, int32_t skip_to) {
-  __shared__ int32_t s_nb[2 * kWalkCap], s_eid[2 * kWalkCap], s_nxt[2 * kWalkCap],
-      s_dist[2 * kWalkCap], s_endv[2 * kWalkCap], s_vid[kWalkCap];
-  __shared__ uint32_t s_rlen[kWalkCap], s_eo[2 * kWalkCap], s_ep[2 * kWalkCap];
-  __shared__ uint64_t s_roff[kWalkCap];
-  __shared__ uint8_t s_es[2 * kWalkCap];
+  __shared__ int32_t s_nb[2 * kAsmWalkCap], s_eid[2 * kAsmWalkCap], s_nxt[2 * kAsmWalkCap],
+      s_dist[2 * kAsmWalkCap], s_endv[2 * kAsmWalkCap], s_vid[kAsmWalkCap];
+  __shared__ uint32_t s_rlen[kAsmWalkCap], s_eo[2 * kAsmWalkCap], s_ep[2 * kAsmWalkCap];
+  __shared__ uint64_t s_roff[kAsmWalkCap];
+  __shared__ uint8_t s_es[2 * kAsmWalkCap];
   __shared__ uint32_t sh_scan[kWalkBlock / kWave + 1];
   const int nc = *parts.d_n_comp;
   const int n = g.n;
@@ -59,9 +64,9 @@ __global__ __launch_bounds__(kWalkBlock) void k_asm_walk(cg_graph g, cg_parts pa
     const int q = parts.comp_size[c];
     if (q <= skip_to) continue;  // k_asm_walk_small's
     const int st = parts.comp_start[c];
-    if (q <= kWalkCap) {
+    if (q <= kAsmWalkCap) {
       WalkArrays w{s_nb, s_eid, s_nxt, s_dist, s_endv, s_vid, s_rlen, s_roff, s_es, s_eo, s_ep};
-      walk_component<kWalkBlock, kWalkCap, true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
+      walk_component<kWalkBlock, kAsmWalkCap, true>(c, q, st, w, g, parts, local.perm, local.loc_row_ptr, local.loc_col,
                            local.loc_eid, out, s, nullptr, sh_scan);
     } else {
       // per-component slices of global scratch: the blocks of different
