@@ -1151,7 +1151,38 @@ __device__ __forceinline__ void walk_chain(const CompRec &cr, int q, int st, Wal
   }
   wbar();
   for (int span = 1; span < q; span <<= 1) {
-    if (kLds) {
+    if (kLds && BLOCK == kWave) {
+      // one wave: the rays' successors, then the successors' fields, each
+      // round of a lane's LDS loads issued together (indices in bounds,
+      // results selected after), so a doubling step waits for two rounds of
+      // loads (in a 256-thread workgroup this measured no better)
+      constexpr int U = 2 * CAP / BLOCK;
+      int xr[U], rn[U], rd[U], re[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = tid + u * BLOCK;
+        xr[u] = r < 2 * q ? w.nxt[r] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = tid + u * BLOCK;
+        const int x = xr[u] >= 0 ? xr[u] : 0;
+        rn[u] = w.nxt[x];
+        rd[u] = w.dist[r] + w.dist[x];
+        re[u] = w.endv[x];
+      }
+      wbar();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = tid + u * BLOCK;
+        if (xr[u] >= 0) {
+          w.nxt[r] = rn[u];
+          w.dist[r] = rd[u];
+          w.endv[r] = re[u];
+        }
+      }
+      wbar();
+    } else if (kLds) {
       int rn[(2 * CAP / BLOCK)], rd[(2 * CAP / BLOCK)], re[(2 * CAP / BLOCK)];
 #pragma unroll
       for (int u = 0; u < (2 * CAP / BLOCK); ++u) {
